@@ -1,0 +1,823 @@
+/*
+ * bqo.c -- CPU oracle (TEST INFRASTRUCTURE ONLY) for one time step of the
+ * extended Boussinesq solver advanced by the variable-step third-order
+ * Adams-Bashforth scheme of arXiv 1909.04153 (Tavakkol, Son & Lynett).
+ *
+ * Plain FP64, single-threaded, natural loop order, no blocking or fusion.
+ * Built with -O2 -ffp-contract=off.  Nothing here is shared with, or called
+ * by, the GPU library; only tests, the smoke check and the benchmark's CPU
+ * baseline may use it.
+ *
+ * What each part follows and what pins it (tests/test_oracle_*.py):
+ *   ab3 alpha (Sec. 3.2.2.1, Eq. 30 / Eq. 42) .... pinned: constant-step
+ *       collapse to 23/12, -16/12, 5/12; exact rational integral of the
+ *       Lagrange interpolant; exactness on quadratics; order 3 on an ODE.
+ *   FD weights (Sec. 3.2.2.2, Eq. 35, 38, 41 = Eq. 44-46) ... pinned: BDF2,
+ *       central and forward special cases; exactness on 1, t, t^2.
+ *   composed F* weights (Eq. 43 with 44-46) ..... pinned: equal to the
+ *       quadratic-extrapolation increment; (2, -3, 1) at constant step.
+ *   lazy EMA (Sec. 3.2.2.4, Eq. 47) .............. pinned: hand sequences.
+ *   Thomas solve of Eq. 19-21 ..................... pinned: dense LAPACK solve.
+ *   KP07 face flux (Sec. 3.1, reading) ............ pinned: physical flux of a
+ *       uniform state, hydrostatic lake-at-rest flux, dry|dry = 0, mirror
+ *       symmetry.
+ *   full step (Eq. 5-15, 19-22, 42-47) ............ pinned: lake at rest on an
+ *       uneven bed, closed-basin mass, Madsen-Sorensen linear dispersion,
+ *       solitary-wave propagation, third-order temporal convergence on a
+ *       y-uniform case, Ritter dam break in the NLSW limit (d = 0).
+ *   wavemaker ghost values, sponge, Manning friction (Sec. 3.3, readings) ...
+ *       parity unpinned beyond the MS wave number (bisection vs. relation).
+ */
+#include "bqo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+struct bqo_domain {
+  bqo_params p;
+  double* wave_amp;
+  double* wave_omega;
+  double* wave_phase;
+  double* wave_k;
+  int nx, ny;
+  int sx;          /* row stride of cell arrays with ghosts: nx + 4 */
+  int cs;          /* row stride of the corner array: nx + 5 */
+  double eps;
+  /* static */
+  double* bc;      /* corner bed b, corners -2..nx+2 x -2..ny+2 */
+  double* bbar;    /* cell-average bed, with ghosts */
+  double* bfx;     /* bed at x-face between cells (i-1, j) and (i, j) */
+  double* bfy;     /* bed at y-face between cells (i, j-1) and (i, j) */
+  double* dep;     /* still-water depth d (Sec. 2: d = 0 on land) */
+  double* ddx;     /* d_x, interior */
+  double* ddy;
+  double* Ax; double* Bx; double* Cx;  /* Eq. 21, alpha = x */
+  double* Ay; double* By; double* Cy;  /* Eq. 21, alpha = y */
+  /* state and histories */
+  double* w;       /* with ghosts */
+  double* P[3];    /* ring: slot n % 3 holds level n, with ghosts */
+  double* Q[3];
+  double* E[3];    /* ring of E, F, G (Eq. 11-13), interior */
+  double* F[3];
+  double* G[3];
+  /* scratch */
+  double* Us;      /* U*^{n+1} */
+  double* Vs;
+  double* la; double* lb; double* lc; double* lr; double* lx;
+  double t;
+  int64_t n;
+  double dt_hist[3]; /* dt_hist[0] = dt of the last step, [1], [2] older */
+  double smax;
+  int status;
+};
+
+#define CI(d, i, j) ((size_t)((j) + 2) * (size_t)(d)->sx + (size_t)((i) + 2))
+#define II(d, i, j) ((size_t)(j) * (size_t)(d)->nx + (size_t)(i))
+#define KI(d, i, j) ((size_t)((j) + 2) * (size_t)(d)->cs + (size_t)((i) + 2))
+
+static double sq(double a) { return a * a; }
+
+/* ------------------------------------------------------------------------ */
+/* Time-stepping weights                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Eq. (30) / Eq. (42): weights of X_t^i, X_t^{i-1}, X_t^{i-2} with
+ * h0 = dt_i, h1 = dt_{i-1}, h2 = dt_{i-2}. */
+void bqo_ab3_alpha(double h0, double h1, double h2, double alpha[3]) {
+  alpha[0] = h0 / 6.0 * ((h0 / h1) * (2.0 * h0 + 6.0 * h1 + 3.0 * h2) / (h1 + h2) + 6.0);
+  alpha[1] = -h0 / 6.0 * ((h0 / h1) * (2.0 * h0 + 3.0 * h1 + 3.0 * h2) / h2);
+  alpha[2] = h0 / 6.0 * ((h0 / h2) * (2.0 * h0 + 3.0 * h1) / (h1 + h2));
+}
+
+/* Eq. (35), (38), (41) (written for F* as Eq. 44-46): D[3k + m] is the
+ * weight of Y^{n-m} in the estimate of Y_t at t_{n-k}. */
+void bqo_fd_weights(double h1, double h2, double D[9]) {
+  const double s = h1 + h2;
+  /* Y_t at t_n (Eq. 35 / 44) */
+  D[0] = (2.0 * h1 + h2) / (h1 * s);
+  D[1] = -s / (h1 * h2);
+  D[2] = h1 / (h2 * s);
+  /* Y_t at t_{n-1} (Eq. 38 / 45) */
+  D[3] = h2 / (h1 * s);
+  D[4] = (h1 - h2) / (h1 * h2);
+  D[5] = -h1 / (h2 * s);
+  /* Y_t at t_{n-2} (Eq. 41 / 46) */
+  D[6] = -h2 / (h1 * s);
+  D[7] = s / (h1 * h2);
+  D[8] = -(h1 + 2.0 * h2) / (h2 * s);
+}
+
+/* Weights used at step n.  The first two steps are forward Euler (Sec.
+ * 3.2.1); the time derivative of F*, G* there is 0 at the very first step
+ * (no history) and the first-order backward difference at the second.
+ * From the third step on, alpha is Eq. (42) and the derivative estimates are
+ * Eq. (44)-(46) (fstar_order 2) or, in the linear reading, the two-point
+ * backward difference at every node (fstar_order 1). */
+void bqo_step_weights(int64_t n, int32_t fstar_order, double h0, double h1, double h2, double alpha[3], double D[9]) {
+  for (int k = 0; k < 9; ++k) D[k] = 0.0;
+  if (n == 0) {
+    alpha[0] = h0; alpha[1] = 0.0; alpha[2] = 0.0;
+  } else if (n == 1) {
+    alpha[0] = h0; alpha[1] = 0.0; alpha[2] = 0.0;
+    D[0] = 1.0 / h1;
+    D[1] = -1.0 / h1;
+  } else {
+    bqo_ab3_alpha(h0, h1, h2, alpha);
+    if (fstar_order == 1) {
+      for (int k = 0; k < 3; ++k) {
+        D[3 * k + 0] = 1.0 / h1;
+        D[3 * k + 1] = -1.0 / h1;
+      }
+    } else {
+      bqo_fd_weights(h1, h2, D);
+    }
+  }
+}
+
+/* Eq. (47): drop at once, rise gradually. */
+double bqo_lazy_ema(double cand, double prev, double a) {
+  if (cand <= prev) return cand;
+  return a * cand + (1.0 - a) * prev;
+}
+
+/* Textbook Thomas algorithm for a_i x_{i-1} + b_i x_i + c_i x_{i+1} = r_i. */
+void bqo_thomas(int32_t n, const double* a, const double* b, const double* c, const double* r, double* x) {
+  double* cp = (double*)malloc(sizeof(double) * (size_t)n);
+  double* rp = (double*)malloc(sizeof(double) * (size_t)n);
+  cp[0] = c[0] / b[0];
+  rp[0] = r[0] / b[0];
+  for (int i = 1; i < n; ++i) {
+    const double m = b[i] - a[i] * cp[i - 1];
+    cp[i] = c[i] / m;
+    rp[i] = (r[i] - a[i] * rp[i - 1]) / m;
+  }
+  x[n - 1] = rp[n - 1];
+  for (int i = n - 2; i >= 0; --i) x[i] = rp[i] - cp[i] * x[i + 1];
+  free(cp);
+  free(rp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* KP07 building blocks (Kurganov & Petrova 2007, as used by TL17, Sec. 3.1)  */
+/* ------------------------------------------------------------------------ */
+
+double bqo_minmod(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return fmax(a, fmax(b, c));
+  return 0.0;
+}
+
+/* desingularised velocity from a flux and a non-negative depth */
+static double desing(double flux, double h, double eps) {
+  const double h4 = h * h * h * h;
+  return sqrt(2.0) * h * flux / sqrt(h4 + fmax(h4, eps));
+}
+
+/* One side of a face: depth and (velocity-consistent) fluxes. */
+typedef struct { double w, h, u, v, hu, hv; } side_t;
+
+static side_t make_side(double w, double P, double Q, double bf, double eps) {
+  side_t s;
+  s.w = w;
+  s.h = fmax(w - bf, 0.0);
+  s.u = desing(P, s.h, eps);
+  s.v = desing(Q, s.h, eps);
+  s.hu = s.h * s.u;
+  s.hv = s.h * s.v;
+  return s;
+}
+
+/* Central-upwind flux through a face normal to direction "dir" (0 = x, 1 = y)
+ * from the left/lower side L and right/upper side R.  Components are in
+ * (w, P, Q) order. */
+static void cu_flux(double g, const side_t* L, const side_t* R, int dir, double H[3]) {
+  const double cL = sqrt(g * L->h), cR = sqrt(g * R->h);
+  const double unL = dir == 0 ? L->u : L->v;
+  const double unR = dir == 0 ? R->u : R->v;
+  const double ap = fmax(fmax(unL + cL, unR + cR), 0.0);
+  const double am = fmin(fmin(unL - cL, unR - cR), 0.0);
+  double FL[3], FR[3];
+  if (dir == 0) {
+    FL[0] = L->hu; FL[1] = L->hu * L->u + 0.5 * g * L->h * L->h; FL[2] = L->hu * L->v;
+    FR[0] = R->hu; FR[1] = R->hu * R->u + 0.5 * g * R->h * R->h; FR[2] = R->hu * R->v;
+  } else {
+    FL[0] = L->hv; FL[1] = L->hv * L->u; FL[2] = L->hv * L->v + 0.5 * g * L->h * L->h;
+    FR[0] = R->hv; FR[1] = R->hv * R->u; FR[2] = R->hv * R->v + 0.5 * g * R->h * R->h;
+  }
+  const double UL[3] = {L->w, L->hu, L->hv};
+  const double UR[3] = {R->w, R->hu, R->hv};
+  const double den = ap - am;
+  for (int k = 0; k < 3; ++k) {
+    if (den == 0.0) {
+      H[k] = 0.0;
+    } else {
+      H[k] = (ap * FL[k] - am * FR[k]) / den + ap * am / den * (UR[k] - UL[k]);
+    }
+  }
+}
+
+void bqo_face_flux_const(double g, double eps, double bf,
+                         double wL, double PL, double QL,
+                         double wR, double PR, double QR, double H[3]) {
+  side_t L = make_side(wL, PL, QL, bf, eps);
+  side_t R = make_side(wR, PR, QR, bf, eps);
+  cu_flux(g, &L, &R, 0, H);
+}
+
+/* Piecewise-linear reconstruction of cell (i, j) in direction dir: the values
+ * at its low face (lo) and high face (hi) for w, P, Q, with the KP07
+ * positivity correction of w against the face beds. */
+typedef struct { double w_lo, w_hi, P_lo, P_hi, Q_lo, Q_hi; } recon_t;
+
+/* theta in [1, 2]: generalised minmod slope; theta = 0: unlimited central
+ * slope (a knob that removes the limiter's switching, used to measure the
+ * temporal order of the scheme on a smooth semi-discrete system) */
+static void slope_faces(double qm, double q0, double qp, double theta, double* lo, double* hi) {
+  const double s = theta > 0.0 ? bqo_minmod(theta * (q0 - qm), 0.5 * (qp - qm), theta * (qp - q0)) : 0.5 * (qp - qm);
+  *lo = q0 - 0.5 * s;
+  *hi = q0 + 0.5 * s;
+}
+
+static recon_t reconstruct(const bqo_domain* d, const double* P, const double* Q, int i, int j, int dir) {
+  recon_t r;
+  const int di = dir == 0 ? 1 : 0, dj = dir == 0 ? 0 : 1;
+  const double th = d->p.theta;
+  const double* w = d->w;
+  slope_faces(w[CI(d, i - di, j - dj)], w[CI(d, i, j)], w[CI(d, i + di, j + dj)], th, &r.w_lo, &r.w_hi);
+  slope_faces(P[CI(d, i - di, j - dj)], P[CI(d, i, j)], P[CI(d, i + di, j + dj)], th, &r.P_lo, &r.P_hi);
+  slope_faces(Q[CI(d, i - di, j - dj)], Q[CI(d, i, j)], Q[CI(d, i + di, j + dj)], th, &r.Q_lo, &r.Q_hi);
+  const double b_lo = dir == 0 ? d->bfx[CI(d, i, j)] : d->bfy[CI(d, i, j)];
+  const double b_hi = dir == 0 ? d->bfx[CI(d, i + 1, j)] : d->bfy[CI(d, i, j + 1)];
+  const double wc = w[CI(d, i, j)];
+  if (r.w_hi < b_hi) {
+    r.w_hi = b_hi;
+    r.w_lo = 2.0 * wc - b_hi;
+  } else if (r.w_lo < b_lo) {
+    r.w_lo = b_lo;
+    r.w_hi = 2.0 * wc - b_lo;
+  }
+  return r;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Setup                                                                      */
+/* ------------------------------------------------------------------------ */
+
+static double* zalloc(size_t n) { return (double*)calloc(n, sizeof(double)); }
+
+double bqo_ms_wavenumber(double omega, double depth, double g, double B) {
+  /* Madsen-Sorensen linear dispersion from Eq. (1)-(3) linearised on a flat
+   * bed: omega^2 = g d k^2 (1 + B (kd)^2) / (1 + (B + 1/3)(kd)^2).
+   * omega(k) is increasing; solve by bisection. */
+  if (omega <= 0.0 || depth <= 0.0) return 0.0;
+  double lo = 0.0, hi = 1.0;
+  for (;;) {
+    const double kd = hi * depth;
+    const double w2 = g * depth * hi * hi * (1.0 + B * kd * kd) / (1.0 + (B + 1.0 / 3.0) * kd * kd);
+    if (w2 > omega * omega) break;
+    hi *= 2.0;
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    const double kd = mid * depth;
+    const double w2 = g * depth * mid * mid * (1.0 + B * kd * kd) / (1.0 + (B + 1.0 / 3.0) * kd * kd);
+    if (w2 < omega * omega) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+static int is_wave(int bc) { return bc == BQO_SINE || bc == BQO_IRREGULAR; }
+
+bqo_domain* bqo_create(const bqo_params* pin, const double* depth_c) {
+  if (!pin || !depth_c || pin->nx < 3 || pin->ny < 3 || !(pin->dx > 0) || !(pin->dy > 0)) return NULL;
+  for (int s = 1; s < 4; ++s)
+    if (is_wave(pin->bc[s])) return NULL; /* wavemaker on the west side only */
+  if (pin->fstar_order < 0 || pin->fstar_order > 2) return NULL;
+  bqo_domain* d = (bqo_domain*)calloc(1, sizeof(bqo_domain));
+  d->p = *pin;
+  if (d->p.fstar_order != 1) d->p.fstar_order = 2;
+  const int nx = d->nx = pin->nx, ny = d->ny = pin->ny;
+  d->sx = nx + 4;
+  d->cs = nx + 5;
+  d->eps = pin->eps_desing > 0 ? pin->eps_desing : fmax(pow(pin->dx, 4), pow(pin->dy, 4));
+  const int nw = pin->n_waves > 0 ? pin->n_waves : 0;
+  d->wave_amp = zalloc(nw + 1);
+  d->wave_omega = zalloc(nw + 1);
+  d->wave_phase = zalloc(nw + 1);
+  d->wave_k = zalloc(nw + 1);
+  for (int m = 0; m < nw; ++m) {
+    d->wave_amp[m] = pin->wave_amp[m];
+    d->wave_omega[m] = pin->wave_omega[m];
+    d->wave_phase[m] = pin->wave_phase ? pin->wave_phase[m] : 0.0;
+  }
+  d->p.wave_amp = d->wave_amp;
+  d->p.wave_omega = d->wave_omega;
+  d->p.wave_phase = d->wave_phase;
+
+  const size_t ncell = (size_t)(nx + 4) * (size_t)(ny + 4);
+  const size_t nint = (size_t)nx * (size_t)ny;
+  d->bc = zalloc((size_t)(nx + 5) * (size_t)(ny + 5));
+  d->bbar = zalloc(ncell); d->bfx = zalloc(ncell); d->bfy = zalloc(ncell);
+  d->dep = zalloc(ncell); d->ddx = zalloc(nint); d->ddy = zalloc(nint);
+  d->Ax = zalloc(nint); d->Bx = zalloc(nint); d->Cx = zalloc(nint);
+  d->Ay = zalloc(nint); d->By = zalloc(nint); d->Cy = zalloc(nint);
+  d->w = zalloc(ncell);
+  for (int k = 0; k < 3; ++k) {
+    d->P[k] = zalloc(ncell); d->Q[k] = zalloc(ncell);
+    d->E[k] = zalloc(nint); d->F[k] = zalloc(nint); d->G[k] = zalloc(nint);
+  }
+  d->Us = zalloc(nint); d->Vs = zalloc(nint);
+  const int nl = nx > ny ? nx : ny;
+  d->la = zalloc(nl); d->lb = zalloc(nl); d->lc = zalloc(nl); d->lr = zalloc(nl); d->lx = zalloc(nl);
+
+  /* corner bed, then mirror across each side (x first, then y) */
+  for (int j = 0; j <= ny; ++j)
+    for (int i = 0; i <= nx; ++i) d->bc[KI(d, i, j)] = -depth_c[(size_t)j * (nx + 1) + i];
+  for (int j = 0; j <= ny; ++j)
+    for (int k = 1; k <= 2; ++k) {
+      d->bc[KI(d, -k, j)] = d->bc[KI(d, k, j)];
+      d->bc[KI(d, nx + k, j)] = d->bc[KI(d, nx - k, j)];
+    }
+  for (int i = -2; i <= nx + 2; ++i)
+    for (int k = 1; k <= 2; ++k) {
+      d->bc[KI(d, i, -k)] = d->bc[KI(d, i, k)];
+      d->bc[KI(d, i, ny + k)] = d->bc[KI(d, i, ny - k)];
+    }
+  for (int j = -2; j < ny + 2; ++j)
+    for (int i = -2; i < nx + 2; ++i) {
+      const double b00 = d->bc[KI(d, i, j)], b10 = d->bc[KI(d, i + 1, j)];
+      const double b01 = d->bc[KI(d, i, j + 1)], b11 = d->bc[KI(d, i + 1, j + 1)];
+      d->bbar[CI(d, i, j)] = 0.25 * (b00 + b10 + b01 + b11);
+      d->bfx[CI(d, i, j)] = 0.5 * (b00 + b01);
+      d->bfy[CI(d, i, j)] = 0.5 * (b00 + b10);
+      d->dep[CI(d, i, j)] = fmax(0.0 - d->bbar[CI(d, i, j)], 0.0);
+    }
+  const double Bc = pin->B + 1.0 / 3.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double dd = d->dep[CI(d, i, j)];
+      const double dx_ = (d->dep[CI(d, i + 1, j)] - d->dep[CI(d, i - 1, j)]) / (2.0 * pin->dx);
+      const double dy_ = (d->dep[CI(d, i, j + 1)] - d->dep[CI(d, i, j - 1)]) / (2.0 * pin->dy);
+      d->ddx[II(d, i, j)] = dx_;
+      d->ddy[II(d, i, j)] = dy_;
+      /* Eq. (21) */
+      d->Ax[II(d, i, j)] = dd * dx_ / (6.0 * pin->dx) - Bc * dd * dd / (pin->dx * pin->dx);
+      d->Bx[II(d, i, j)] = 1.0 + 2.0 * Bc * dd * dd / (pin->dx * pin->dx);
+      d->Cx[II(d, i, j)] = -dd * dx_ / (6.0 * pin->dx) - Bc * dd * dd / (pin->dx * pin->dx);
+      d->Ay[II(d, i, j)] = dd * dy_ / (6.0 * pin->dy) - Bc * dd * dd / (pin->dy * pin->dy);
+      d->By[II(d, i, j)] = 1.0 + 2.0 * Bc * dd * dd / (pin->dy * pin->dy);
+      d->Cy[II(d, i, j)] = -dd * dy_ / (6.0 * pin->dy) - Bc * dd * dd / (pin->dy * pin->dy);
+    }
+  /* wavemaker wave numbers at the mean depth of the first interior column */
+  double dwm = 0.0;
+  for (int j = 0; j < ny; ++j) dwm += d->dep[CI(d, 0, j)];
+  dwm /= ny;
+  for (int m = 0; m < nw; ++m) d->wave_k[m] = bqo_ms_wavenumber(d->wave_omega[m], dwm, pin->g, pin->B);
+  d->status = BQO_OK;
+  return d;
+}
+
+void bqo_free(bqo_domain* d) {
+  if (!d) return;
+  double* ptrs[] = {d->wave_amp, d->wave_omega, d->wave_phase, d->wave_k, d->bc, d->bbar, d->bfx, d->bfy,
+                    d->dep, d->ddx, d->ddy, d->Ax, d->Bx, d->Cx, d->Ay, d->By, d->Cy, d->w,
+                    d->P[0], d->P[1], d->P[2], d->Q[0], d->Q[1], d->Q[2], d->E[0], d->E[1], d->E[2],
+                    d->F[0], d->F[1], d->F[2], d->G[0], d->G[1], d->G[2], d->Us, d->Vs,
+                    d->la, d->lb, d->lc, d->lr, d->lx};
+  for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
+  free(d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Boundary conditions (Sec. 3.3): two ghost layers                           */
+/* ------------------------------------------------------------------------ */
+
+static double ramp(const bqo_domain* d, double t) {
+  if (!(d->p.wave_ramp > 0.0)) return 1.0;
+  return 1.0 - exp(-sq(t / d->p.wave_ramp));
+}
+
+/* surface elevation and x-flux of the incident wave at x, t */
+static void wave_at(const bqo_domain* d, double x, double t, double* eta, double* P) {
+  double e = 0.0, q = 0.0;
+  const double r = ramp(d, t);
+  for (int m = 0; m < d->p.n_waves; ++m) {
+    const double term = r * d->wave_amp[m] * sin(d->wave_omega[m] * t - d->wave_k[m] * x + d->wave_phase[m]);
+    e += term;
+    q += d->wave_omega[m] / d->wave_k[m] * term;
+  }
+  *eta = e;
+  *P = q;
+}
+
+static void fill_ghosts(bqo_domain* d, double* P, double* Q, double t) {
+  const int nx = d->nx, ny = d->ny;
+  double* w = d->w;
+  /* x sides for interior rows */
+  for (int j = 0; j < ny; ++j) {
+    for (int k = 1; k <= 2; ++k) {
+      if (is_wave(d->p.bc[BQO_W])) {
+        double e, q;
+        wave_at(d, (0.5 - k) * d->p.dx, t, &e, &q);
+        w[CI(d, -k, j)] = e;
+        P[CI(d, -k, j)] = q;
+        Q[CI(d, -k, j)] = 0.0;
+      } else {
+        w[CI(d, -k, j)] = w[CI(d, k - 1, j)];
+        P[CI(d, -k, j)] = -P[CI(d, k - 1, j)];
+        Q[CI(d, -k, j)] = Q[CI(d, k - 1, j)];
+      }
+      w[CI(d, nx - 1 + k, j)] = w[CI(d, nx - k, j)];
+      P[CI(d, nx - 1 + k, j)] = -P[CI(d, nx - k, j)];
+      Q[CI(d, nx - 1 + k, j)] = Q[CI(d, nx - k, j)];
+    }
+  }
+  /* y sides for all columns including the x ghosts */
+  for (int i = -2; i < nx + 2; ++i) {
+    for (int k = 1; k <= 2; ++k) {
+      w[CI(d, i, -k)] = w[CI(d, i, k - 1)];
+      P[CI(d, i, -k)] = P[CI(d, i, k - 1)];
+      Q[CI(d, i, -k)] = -Q[CI(d, i, k - 1)];
+      w[CI(d, i, ny - 1 + k)] = w[CI(d, i, ny - k)];
+      P[CI(d, i, ny - 1 + k)] = P[CI(d, i, ny - k)];
+      Q[CI(d, i, ny - 1 + k)] = -Q[CI(d, i, ny - k)];
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* State, CFL (Eq. 22) and diagnostics                                        */
+/* ------------------------------------------------------------------------ */
+
+int bqo_set_state(bqo_domain* d, const double* eta, const double* P, const double* Q) {
+  const int nx = d->nx, ny = d->ny;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      if (!(eta[II(d, i, j)] >= -d->dep[CI(d, i, j)])) return BQO_EINVAL;
+  const size_t ncell = (size_t)(nx + 4) * (size_t)(ny + 4);
+  const size_t nint = (size_t)nx * (size_t)ny;
+  for (int k = 0; k < 3; ++k) {
+    memset(d->P[k], 0, ncell * sizeof(double));
+    memset(d->Q[k], 0, ncell * sizeof(double));
+    memset(d->E[k], 0, nint * sizeof(double));
+    memset(d->F[k], 0, nint * sizeof(double));
+    memset(d->G[k], 0, nint * sizeof(double));
+  }
+  memset(d->w, 0, ncell * sizeof(double));
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double h = eta[II(d, i, j)] + d->dep[CI(d, i, j)];
+      d->w[CI(d, i, j)] = h + d->bbar[CI(d, i, j)];
+      d->P[0][CI(d, i, j)] = P[II(d, i, j)];
+      d->Q[0][CI(d, i, j)] = Q[II(d, i, j)];
+    }
+  d->n = 0;
+  d->t = 0.0;
+  d->dt_hist[0] = d->dt_hist[1] = d->dt_hist[2] = 0.0;
+  d->status = BQO_OK;
+  fill_ghosts(d, d->P[0], d->Q[0], 0.0);
+  return BQO_OK;
+}
+
+/* max over interior cells of max((|u| + c)/dx, (|v| + c)/dy); NaN -> +inf */
+static double max_speed(const bqo_domain* d) {
+  const double* P = d->P[d->n % 3];
+  const double* Q = d->Q[d->n % 3];
+  double s = 0.0;
+  for (int j = 0; j < d->ny; ++j)
+    for (int i = 0; i < d->nx; ++i) {
+      const double h = fmax(d->w[CI(d, i, j)] - d->bbar[CI(d, i, j)], 0.0);
+      const double u = desing(P[CI(d, i, j)], h, d->eps);
+      const double v = desing(Q[CI(d, i, j)], h, d->eps);
+      const double c = sqrt(d->p.g * h);
+      const double sc = fmax((fabs(u) + c) / d->p.dx, (fabs(v) + c) / d->p.dy);
+      if (sc != sc) return INFINITY;
+      if (sc > s) s = sc;
+    }
+  return s;
+}
+
+static void diagnostics(const bqo_domain* d, double* mass, double* energy) {
+  const double* P = d->P[d->n % 3];
+  const double* Q = d->Q[d->n % 3];
+  double m = 0.0, e = 0.0;
+  for (int j = 0; j < d->ny; ++j)
+    for (int i = 0; i < d->nx; ++i) {
+      const double h = d->w[CI(d, i, j)] - d->bbar[CI(d, i, j)];
+      const double dd = d->dep[CI(d, i, j)];
+      m += h * d->p.dx * d->p.dy;
+      double ec = 0.0;
+      if (dd > 0.0) ec += 0.5 * d->p.g * sq(h - dd);
+      if (h > 1e-6) ec += 0.5 * (sq(P[CI(d, i, j)]) + sq(Q[CI(d, i, j)])) / h;
+      e += ec * d->p.dx * d->p.dy;
+    }
+  *mass = m;
+  *energy = e;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spatial operator: E, F, G of Eq. (11)-(13)                                 */
+/* ------------------------------------------------------------------------ */
+
+static void compute_rhs(const bqo_domain* d, const double* P, const double* Q, double* E, double* F, double* G) {
+  const int nx = d->nx, ny = d->ny;
+  const double dx = d->p.dx, dy = d->p.dy, g = d->p.g, eps = d->eps;
+  /* x-face fluxes: face i between cells (i-1, j) and (i, j), i = 0..nx */
+  const size_t nfx = (size_t)(nx + 1) * (size_t)ny;
+  const size_t nfy = (size_t)nx * (size_t)(ny + 1);
+  double* Hx = (double*)malloc(sizeof(double) * 3 * nfx);
+  double* Hy = (double*)malloc(sizeof(double) * 3 * nfy);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i <= nx; ++i) {
+      const recon_t rl = reconstruct(d, P, Q, i - 1, j, 0);
+      const recon_t rr = reconstruct(d, P, Q, i, j, 0);
+      const double bf = d->bfx[CI(d, i, j)];
+      side_t L = make_side(rl.w_hi, rl.P_hi, rl.Q_hi, bf, eps);
+      side_t R = make_side(rr.w_lo, rr.P_lo, rr.Q_lo, bf, eps);
+      cu_flux(g, &L, &R, 0, &Hx[3 * ((size_t)j * (nx + 1) + i)]);
+    }
+  for (int j = 0; j <= ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const recon_t rl = reconstruct(d, P, Q, i, j - 1, 1);
+      const recon_t rr = reconstruct(d, P, Q, i, j, 1);
+      const double bf = d->bfy[CI(d, i, j)];
+      side_t L = make_side(rl.w_hi, rl.P_hi, rl.Q_hi, bf, eps);
+      side_t R = make_side(rr.w_lo, rr.P_lo, rr.Q_lo, bf, eps);
+      cu_flux(g, &L, &R, 1, &Hy[3 * ((size_t)j * nx + i)]);
+    }
+  const double Bd = d->p.B;
+  const double gn2 = g * d->p.manning_n * d->p.manning_n;
+  const double* w = d->w;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double* hw = &Hx[3 * ((size_t)j * (nx + 1) + i)];
+      const double* he = &Hx[3 * ((size_t)j * (nx + 1) + i + 1)];
+      const double* hs = &Hy[3 * ((size_t)j * nx + i)];
+      const double* hn = &Hy[3 * ((size_t)(j + 1) * nx + i)];
+      /* well-balanced bed slope source: -g h b_x with h the mean of the
+       * cell's own face depths */
+      const recon_t rx = reconstruct(d, P, Q, i, j, 0);
+      const recon_t ry = reconstruct(d, P, Q, i, j, 1);
+      const double bw = d->bfx[CI(d, i, j)], be = d->bfx[CI(d, i + 1, j)];
+      const double bs = d->bfy[CI(d, i, j)], bn = d->bfy[CI(d, i, j + 1)];
+      const double hW = fmax(rx.w_lo - bw, 0.0), hE = fmax(rx.w_hi - be, 0.0);
+      const double hS = fmax(ry.w_lo - bs, 0.0), hN = fmax(ry.w_hi - bn, 0.0);
+      double e = -(he[0] - hw[0]) / dx - (hn[0] - hs[0]) / dy;
+      double f = -(he[1] - hw[1]) / dx - (hn[1] - hs[1]) / dy - g * (be - bw) / dx * 0.5 * (hE + hW);
+      double gg = -(he[2] - hw[2]) / dx - (hn[2] - hs[2]) / dy - g * (bn - bs) / dy * 0.5 * (hN + hS);
+      /* dispersive terms of Eq. (12)-(13), central differences; eta = h - d */
+      const double dd = d->dep[CI(d, i, j)];
+      if (dd > 0.0) {
+#define ETA(a, b) ((w[CI(d, i + (a), j + (b))] - d->bbar[CI(d, i + (a), j + (b))]) - d->dep[CI(d, i + (a), j + (b))])
+        const double exx = (ETA(1, 0) - 2.0 * ETA(0, 0) + ETA(-1, 0)) / (dx * dx);
+        const double eyy = (ETA(0, 1) - 2.0 * ETA(0, 0) + ETA(0, -1)) / (dy * dy);
+        const double exy = (ETA(1, 1) - ETA(1, -1) - ETA(-1, 1) + ETA(-1, -1)) / (4.0 * dx * dy);
+        const double exxx = (ETA(2, 0) - 2.0 * ETA(1, 0) + 2.0 * ETA(-1, 0) - ETA(-2, 0)) / (2.0 * dx * dx * dx);
+        const double eyyy = (ETA(0, 2) - 2.0 * ETA(0, 1) + 2.0 * ETA(0, -1) - ETA(0, -2)) / (2.0 * dy * dy * dy);
+        const double exyy = ((ETA(1, 1) - 2.0 * ETA(1, 0) + ETA(1, -1)) - (ETA(-1, 1) - 2.0 * ETA(-1, 0) + ETA(-1, -1))) /
+                            (2.0 * dx * dy * dy);
+        const double exxy = ((ETA(1, 1) - 2.0 * ETA(0, 1) + ETA(-1, 1)) - (ETA(1, -1) - 2.0 * ETA(0, -1) + ETA(-1, -1))) /
+                            (2.0 * dx * dx * dy);
+#undef ETA
+        const double dX = d->ddx[II(d, i, j)], dY = d->ddy[II(d, i, j)];
+        f += Bd * g * dd * dd * dd * (exxx + exyy) + Bd * g * dd * dd * (dX * (2.0 * exx + eyy) + dY * exy);
+        gg += Bd * g * dd * dd * dd * (eyyy + exxy) + Bd * g * dd * dd * (dY * (2.0 * eyy + exx) + dX * exy);
+      }
+      /* Manning friction f1, f2 at the cell centre */
+      const double h = fmax(w[CI(d, i, j)] - d->bbar[CI(d, i, j)], 0.0);
+      if (h > 0.0 && gn2 > 0.0) {
+        const double u = desing(P[CI(d, i, j)], h, eps);
+        const double v = desing(Q[CI(d, i, j)], h, eps);
+        const double sp = sqrt(u * u + v * v);
+        f -= gn2 * u * sp / cbrt(h);
+        gg -= gn2 * v * sp / cbrt(h);
+      }
+      E[II(d, i, j)] = e;
+      F[II(d, i, j)] = f;
+      G[II(d, i, j)] = gg;
+    }
+  free(Hx);
+  free(Hy);
+}
+
+int bqo_rhs(bqo_domain* d, double* E, double* F, double* G) {
+  compute_rhs(d, d->P[d->n % 3], d->Q[d->n % 3], E, F, G);
+  return BQO_OK;
+}
+
+int bqo_wave_numbers(bqo_domain* d, double* k_out) {
+  for (int m = 0; m < d->p.n_waves; ++m) k_out[m] = d->wave_k[m];
+  return BQO_OK;
+}
+
+/* Eq. (14): F*(Q) and Eq. (15): G*(P) at interior cell (i, j) */
+static double fstar(const bqo_domain* d, const double* Q, int i, int j) {
+  const double dd = d->dep[CI(d, i, j)], dX = d->ddx[II(d, i, j)], dY = d->ddy[II(d, i, j)];
+  const double dx = d->p.dx, dy = d->p.dy;
+  const double qy = (Q[CI(d, i, j + 1)] - Q[CI(d, i, j - 1)]) / (2.0 * dy);
+  const double qx = (Q[CI(d, i + 1, j)] - Q[CI(d, i - 1, j)]) / (2.0 * dx);
+  const double qxy = (Q[CI(d, i + 1, j + 1)] - Q[CI(d, i + 1, j - 1)] - Q[CI(d, i - 1, j + 1)] + Q[CI(d, i - 1, j - 1)]) /
+                     (4.0 * dx * dy);
+  return dd * dX * qy / 6.0 + dd * dY * qx / 6.0 + (d->p.B + 1.0 / 3.0) * dd * dd * qxy;
+}
+
+static double gstar(const bqo_domain* d, const double* P, int i, int j) {
+  const double dd = d->dep[CI(d, i, j)], dX = d->ddx[II(d, i, j)], dY = d->ddy[II(d, i, j)];
+  const double dx = d->p.dx, dy = d->p.dy;
+  const double py = (P[CI(d, i, j + 1)] - P[CI(d, i, j - 1)]) / (2.0 * dy);
+  const double px = (P[CI(d, i + 1, j)] - P[CI(d, i - 1, j)]) / (2.0 * dx);
+  const double pxy = (P[CI(d, i + 1, j + 1)] - P[CI(d, i + 1, j - 1)] - P[CI(d, i - 1, j + 1)] + P[CI(d, i - 1, j - 1)]) /
+                     (4.0 * dx * dy);
+  return dd * dX * py / 6.0 + dd * dY * px / 6.0 + (d->p.B + 1.0 / 3.0) * dd * dd * pxy;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One time step                                                              */
+/* ------------------------------------------------------------------------ */
+
+static int step_one(bqo_domain* d, double dt_prescribed) {
+  if (d->status != BQO_OK) return d->status;
+  const int nx = d->nx, ny = d->ny;
+  const int64_t n = d->n;
+  if (d->p.t_end > 0.0 && d->t >= d->p.t_end) {
+    d->status = BQO_EDONE;
+    return d->status;
+  }
+  /* Eq. (22) on the current state, then Eq. (47) */
+  const double s = max_speed(d);
+  d->smax = s;
+  if (!isfinite(s)) {
+    d->status = BQO_ENONFINITE;
+    return d->status;
+  }
+  double dt;
+  if (dt_prescribed > 0.0) {
+    dt = dt_prescribed;
+  } else if (d->p.fixed_dt) {
+    dt = d->p.dt_init;
+  } else {
+    const double cand = s > 0.0 ? d->p.cfl / s : d->p.dt_max;
+    if (n == 0) {
+      dt = d->p.dt_init > 0.0 ? d->p.dt_init : cand;
+    } else {
+      dt = bqo_lazy_ema(cand, d->dt_hist[0], d->p.ema_alpha);
+    }
+    if (dt > d->p.dt_max) dt = d->p.dt_max;
+    if (dt < d->p.dt_min) {
+      d->status = BQO_EDTMIN;
+      return d->status;
+    }
+  }
+  const double h0 = dt, h1 = d->dt_hist[0], h2 = d->dt_hist[1];
+  double alpha[3], D[9];
+  bqo_step_weights(n, d->p.fstar_order, h0, h1, h2, alpha, D);
+
+  const int s0 = (int)(n % 3), s1 = (int)((n + 2) % 3), s2 = (int)((n + 1) % 3);
+  double* Pn = d->P[s0];
+  double* Qn = d->Q[s0];
+  compute_rhs(d, Pn, Qn, d->E[s0], d->F[s0], d->G[s0]);
+
+  const double* Ph[3] = {d->P[s0], d->P[s1], d->P[s2]};
+  const double* Qh[3] = {d->Q[s0], d->Q[s1], d->Q[s2]};
+  const double* Eh[3] = {d->E[s0], d->E[s1], d->E[s2]};
+  const double* Fh[3] = {d->F[s0], d->F[s1], d->F[s2]};
+  const double* Gh[3] = {d->G[s0], d->G[s1], d->G[s2]};
+  double* wnew = (double*)malloc(sizeof(double) * (size_t)nx * ny);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const size_t q = II(d, i, j);
+      double Fs[3], Gs[3];
+      for (int m = 0; m < 3; ++m) {
+        Fs[m] = fstar(d, Qh[m], i, j);
+        Gs[m] = gstar(d, Ph[m], i, j);
+      }
+      /* U*^n, V*^n from Eq. (9)-(10) as the rows of Eq. (19)-(20) */
+      const double Un = d->Ax[q] * Pn[CI(d, i - 1, j)] + d->Bx[q] * Pn[CI(d, i, j)] + d->Cx[q] * Pn[CI(d, i + 1, j)];
+      const double Vn = d->Ay[q] * Qn[CI(d, i, j - 1)] + d->By[q] * Qn[CI(d, i, j)] + d->Cy[q] * Qn[CI(d, i, j + 1)];
+      /* Eq. (42), (43) with (44)-(46) */
+      double wn = d->w[CI(d, i, j)], Un1 = Un, Vn1 = Vn;
+      for (int k = 0; k < 3; ++k) {
+        const double Ft = D[3 * k + 0] * Fs[0] + D[3 * k + 1] * Fs[1] + D[3 * k + 2] * Fs[2];
+        const double Gt = D[3 * k + 0] * Gs[0] + D[3 * k + 1] * Gs[1] + D[3 * k + 2] * Gs[2];
+        wn += alpha[k] * Eh[k][q];
+        Un1 += alpha[k] * (Fh[k][q] + Ft);
+        Vn1 += alpha[k] * (Gh[k][q] + Gt);
+      }
+      wnew[q] = wn;
+      d->Us[q] = Un1;
+      d->Vs[q] = Vn1;
+    }
+  const double t1 = d->t + dt;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) d->w[CI(d, i, j)] = wnew[II(d, i, j)];
+  free(wnew);
+
+  /* Eq. (19): x-lines for P^{n+1} (into the slot of level n-2) */
+  double* Pnew = d->P[s2];
+  double* Qnew = d->Q[s2];
+  double Pg = 0.0;
+  if (is_wave(d->p.bc[BQO_W])) {
+    double e;
+    wave_at(d, -0.5 * d->p.dx, t1, &e, &Pg);
+  }
+  for (int j = 0; j < ny; ++j) {
+    for (int i = 0; i < nx; ++i) {
+      const size_t q = II(d, i, j);
+      d->la[i] = d->Ax[q]; d->lb[i] = d->Bx[q]; d->lc[i] = d->Cx[q]; d->lr[i] = d->Us[q];
+    }
+    if (is_wave(d->p.bc[BQO_W])) d->lr[0] -= d->la[0] * Pg;  /* Dirichlet ghost */
+    else d->lb[0] -= d->la[0];                                 /* P_{-1} = -P_0 */
+    d->lb[nx - 1] -= d->lc[nx - 1];                            /* P_{nx} = -P_{nx-1} */
+    d->la[0] = 0.0;
+    d->lc[nx - 1] = 0.0;
+    bqo_thomas(nx, d->la, d->lb, d->lc, d->lr, d->lx);
+    for (int i = 0; i < nx; ++i) Pnew[CI(d, i, j)] = d->lx[i];
+  }
+  /* Eq. (20): y-lines for Q^{n+1} */
+  for (int i = 0; i < nx; ++i) {
+    for (int j = 0; j < ny; ++j) {
+      const size_t q = II(d, i, j);
+      d->la[j] = d->Ay[q]; d->lb[j] = d->By[q]; d->lc[j] = d->Cy[q]; d->lr[j] = d->Vs[q];
+    }
+    d->lb[0] -= d->la[0];
+    d->lb[ny - 1] -= d->lc[ny - 1];
+    d->la[0] = 0.0;
+    d->lc[ny - 1] = 0.0;
+    bqo_thomas(ny, d->la, d->lb, d->lc, d->lr, d->lx);
+    for (int j = 0; j < ny; ++j) Qnew[CI(d, i, j)] = d->lx[j];
+  }
+  /* sponge layers (Sec. 3.3): relax eta, P, Q of wet cells towards rest */
+  int any_sponge = 0;
+  for (int sd = 0; sd < 4; ++sd)
+    if (d->p.bc[sd] == BQO_SPONGE && d->p.sponge_width[sd] > 0.0) any_sponge = 1;
+  if (any_sponge) {
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        if (!(d->dep[CI(d, i, j)] > 0.0)) continue;
+        const double dist[4] = {(i + 0.5) * d->p.dx, (nx - i - 0.5) * d->p.dx, (j + 0.5) * d->p.dy,
+                                (ny - j - 0.5) * d->p.dy};
+        double sig = 0.0;
+        for (int sd = 0; sd < 4; ++sd) {
+          const double L = d->p.sponge_width[sd];
+          if (d->p.bc[sd] == BQO_SPONGE && L > 0.0 && dist[sd] < L) sig += d->p.sponge_sigma * sq((L - dist[sd]) / L);
+        }
+        if (sig > 0.0) {
+          const double fac = exp(-sig * dt);
+          d->w[CI(d, i, j)] = 0.0 + (d->w[CI(d, i, j)] - 0.0) * fac;
+          Pnew[CI(d, i, j)] *= fac;
+          Qnew[CI(d, i, j)] *= fac;
+        }
+      }
+  }
+  d->dt_hist[2] = d->dt_hist[1];
+  d->dt_hist[1] = d->dt_hist[0];
+  d->dt_hist[0] = dt;
+  d->t = t1;
+  d->n = n + 1;
+  fill_ghosts(d, Pnew, Qnew, t1);
+  return BQO_OK;
+}
+
+int bqo_step(bqo_domain* d, int32_t n_steps) {
+  for (int k = 0; k < n_steps; ++k) {
+    const int rc = step_one(d, 0.0);
+    if (rc != BQO_OK) return rc;
+  }
+  return BQO_OK;
+}
+
+int bqo_step_dt(bqo_domain* d, double dt) {
+  if (!(dt > 0.0)) return BQO_EINVAL;
+  return step_one(d, dt);
+}
+
+int bqo_info_get(bqo_domain* d, bqo_info* out) {
+  out->t = d->t;
+  out->n = d->n;
+  out->dt_last = d->dt_hist[0];
+  out->dt_prev1 = d->dt_hist[1];
+  out->dt_prev2 = d->dt_hist[2];
+  out->smax = max_speed(d);
+  diagnostics(d, &out->mass, &out->energy);
+  out->status = d->status;
+  return BQO_OK;
+}
+
+int bqo_read(bqo_domain* d, int32_t which, double* out) {
+  const double* P = d->P[d->n % 3];
+  const double* Q = d->Q[d->n % 3];
+  for (int j = 0; j < d->ny; ++j)
+    for (int i = 0; i < d->nx; ++i) {
+      double v;
+      switch (which) {
+        case 0: v = (d->w[CI(d, i, j)] - d->bbar[CI(d, i, j)]) - d->dep[CI(d, i, j)]; break;
+        case 1: v = P[CI(d, i, j)]; break;
+        case 2: v = Q[CI(d, i, j)]; break;
+        case 3: v = d->w[CI(d, i, j)]; break;
+        default: return BQO_EINVAL;
+      }
+      out[II(d, i, j)] = v;
+    }
+  return BQO_OK;
+}

@@ -1,0 +1,286 @@
+"""Seeded synthetic scenarios: bathymetry, initial states and wave forcing.
+
+This module only generates inputs (shapes, sizes, value distributions); it
+contains none of the solver's arithmetic.  Both the GPU library and the CPU
+oracle consume what it produces, so it is the one piece they share.
+
+The paper's laboratory benchmarks (conical island, Lynett et al. 2019 shelf,
+Haller et al. 2002 and Hamm 1992 rip-channel basins, Sec. 5) are not available
+here; the generators below stand in for them with the same kinds of geometry
+and forcing: a solitary wave on a flat bed, a plane beach running up to dry
+land under a sine wavemaker, a barred beach cut by rip channels under a
+JONSWAP irregular wavemaker with sponge side walls, and seeded mixtures of
+these for batched and served runs.
+
+A scenario is a plain dict ``spec`` with keys
+  params   -- solver parameters (nx, ny, dx, dy, B, manning_n, cfl, bc, ...)
+  depth_c  -- (ny+1, nx+1) still-water depth at cell corners (+wet, -land)
+  eta, P, Q -- (ny, nx) initial state (eta = h - d)
+  steps / t_end -- run length
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+G = 9.81
+B_MS = 1.0 / 15.0
+WALL, SINE, SPONGE, IRREGULAR = 0, 1, 2, 3
+
+
+def base_params(nx, ny, dx, dy=None, **kw):
+    p = dict(nx=int(nx), ny=int(ny), dx=float(dx), dy=float(dy if dy is not None else dx), g=G, B=B_MS,
+             manning_n=0.0, cfl=0.2, ema_alpha=0.1, dt_init=0.0, dt_max=1.0, dt_min=1e-9, fixed_dt=0,
+             theta=1.3, eps_desing=0.0, bc=(WALL, WALL, WALL, WALL), sponge_width=(0.0, 0.0, 0.0, 0.0),
+             sponge_sigma=0.0, wave_amp=[], wave_omega=[], wave_phase=[], wave_ramp=0.0, t_end=0.0,
+             fstar_order=2)
+    p.update(kw)
+    return p
+
+
+def corner_coords(nx, ny, dx, dy):
+    x = np.arange(nx + 1) * dx
+    y = np.arange(ny + 1) * dy
+    return np.meshgrid(x, y)  # (ny+1, nx+1)
+
+
+def cell_coords(nx, ny, dx, dy):
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    return np.meshgrid(x, y)  # (ny, nx)
+
+
+def rest_state(nx, ny):
+    z = np.zeros((ny, nx))
+    return z, z.copy(), z.copy()
+
+
+def solitary_profile(x, x0, a, d):
+    """Initial-condition profile a sech^2(k (x - x0)) with k = sqrt(3a / 4d^3)
+    and the flux c * eta, c = sqrt(g (d + a)) (Boussinesq-type solitary wave)."""
+    k = math.sqrt(3.0 * a / (4.0 * d ** 3))
+    eta = a / np.cosh(k * (x - x0)) ** 2
+    c = math.sqrt(G * (d + a))
+    return eta, c * eta
+
+
+# ---------------------------------------------------------------------------
+# C1: solitary wave on a flat bed (plain method, FP64)
+# ---------------------------------------------------------------------------
+
+def solitary_flat(nx=200, ny=20, dx=0.05, depth=1.0, amp=0.1, x0=3.0, steps=300, **kw):
+    p = base_params(nx, ny, dx, **kw)
+    depth_c = np.full((ny + 1, nx + 1), float(depth))
+    X, _ = cell_coords(nx, ny, dx, p["dy"])
+    eta, P = solitary_profile(X, x0, amp, depth)
+    return dict(name=f"solitary_flat_{nx}x{ny}", params=p, depth_c=depth_c, eta=eta, P=P,
+                Q=np.zeros_like(eta), steps=steps)
+
+
+# ---------------------------------------------------------------------------
+# C2: plane beach up to dry land, sine wavemaker, Manning friction
+# ---------------------------------------------------------------------------
+
+def sloping_beach(nx=1024, ny=256, dx=0.1, h_off=0.5, x_toe=10.0, slope=1.0 / 20.0, amp=0.02, period=2.0,
+                  ramp=4.0, manning=0.015, t_end=20.0, **kw):
+    """Flat offshore depth h_off for x < x_toe, then a 1:(1/slope) beach that
+    crosses the still-water line at x_toe + h_off / slope and continues as
+    dry land; sine wavemaker on the west side, walls elsewhere."""
+    p = base_params(nx, ny, dx, manning_n=manning, bc=(SINE, WALL, WALL, WALL), wave_amp=[amp],
+                    wave_omega=[2.0 * math.pi / period], wave_phase=[0.0], wave_ramp=ramp, **kw)
+    Xc, _ = corner_coords(nx, ny, dx, p["dy"])
+    b = np.where(Xc < x_toe, -h_off, -h_off + (Xc - x_toe) * slope)
+    eta, P, Q = rest_state(nx, ny)
+    return dict(name=f"sloping_beach_{nx}x{ny}", params=p, depth_c=-b, eta=eta, P=P, Q=Q, t_end=t_end)
+
+
+# ---------------------------------------------------------------------------
+# C3: barred beach with seeded rip channels, JONSWAP irregular waves
+# ---------------------------------------------------------------------------
+
+def jonswap_components(hs, tp, gamma=3.3, n=64, fmin_ratio=0.6, fmax_ratio=2.2, rng=None):
+    """n equal-df components of a JONSWAP spectrum on [fmin, fmax] * fp with
+    amplitudes sqrt(2 S df) scaled so that 4 sqrt(m0) = Hs, random phases."""
+    fp = 1.0 / tp
+    f = np.linspace(fmin_ratio * fp, fmax_ratio * fp, n)
+    df = f[1] - f[0]
+    sig = np.where(f <= fp, 0.07, 0.09)
+    r = np.exp(-((f - fp) ** 2) / (2.0 * sig ** 2 * fp ** 2))
+    S = G ** 2 * (2.0 * math.pi) ** -4 * f ** -5 * np.exp(-1.25 * (fp / f) ** 4) * gamma ** r
+    a = np.sqrt(2.0 * S * df)
+    m0 = np.sum(a ** 2) / 2.0
+    a *= hs / (4.0 * math.sqrt(m0))
+    rng = rng if rng is not None else np.random.default_rng(0)
+    phase = rng.uniform(0.0, 2.0 * math.pi, n)
+    return a, 2.0 * math.pi * f, phase
+
+
+def rip_beach(nx=2048, ny=2048, dx=0.5, seed=190904153, hs=1.0, tp=8.0, gamma=3.3, n_waves=64,
+              sponge=48.0, manning=0.015, t_end=600.0, h_off=8.0, x_toe=300.0, x_shore=780.0,
+              bar_x=660.0, bar_amp=1.0, bar_sigma=20.0, **kw):
+    rng = np.random.default_rng(seed)
+    Ly = ny * dx
+    # rip channels: K ~ U{3..6}, min spacing 100 m (scaled for small domains)
+    K = int(rng.integers(3, 7))
+    spacing = min(100.0, Ly / (K + 1))
+    ys = []
+    while len(ys) < K:
+        y = float(rng.uniform(0.05 * Ly, 0.95 * Ly))
+        if all(abs(y - q) >= spacing for q in ys):
+            ys.append(y)
+    sig_y = rng.uniform(15.0, 30.0, K) * min(1.0, Ly / 1024.0)
+    a, om, ph = jonswap_components(hs, tp, gamma, n_waves, rng=rng)
+    p = base_params(nx, ny, dx, manning_n=manning, bc=(IRREGULAR, WALL, SPONGE, SPONGE),
+                    sponge_width=(0.0, 0.0, sponge, sponge), sponge_sigma=2.0 * math.pi / tp,
+                    wave_amp=list(a), wave_omega=list(om), wave_phase=list(ph), wave_ramp=2.0 * tp, **kw)
+    Xc, Yc = corner_coords(nx, ny, dx, p["dy"])
+    slope = h_off / (x_shore - x_toe)
+    b = np.where(Xc < x_toe, -h_off, -h_off + (Xc - x_toe) * slope)
+    cut = np.ones_like(Yc)
+    for yk, sk in zip(ys, sig_y):
+        cut *= 1.0 - np.exp(-(((Yc - yk) / sk) ** 2))
+    b = b + bar_amp * np.exp(-((Xc - bar_x) ** 2) / (2.0 * bar_sigma ** 2)) * cut
+    eta, P, Q = rest_state(nx, ny)
+    return dict(name=f"rip_beach_{nx}x{ny}", params=p, depth_c=-b, eta=eta, P=P, Q=Q, t_end=t_end,
+                rip_y=ys)
+
+
+def rip_beach_scaled(nx, ny, seed=190904153, **kw):
+    """rip_beach geometry scaled to an nx x ny grid covering the same 1024 m
+    cross-shore extent (for parity tests at small sizes)."""
+    dx = 1024.0 / nx
+    return rip_beach(nx=nx, ny=ny, dx=dx, seed=seed, **kw)
+
+
+# ---------------------------------------------------------------------------
+# C4: 64 seeded domains of uneven size; C5: Poisson request stream
+# ---------------------------------------------------------------------------
+
+def beach_of_size(nx, ny, dx=0.1, rng=None, **kw):
+    """C2-type domain scaled to nx x ny: offshore flat on the first 10 %, then
+    a 1:20 beach crossing the still-water line 10 m further."""
+    L = nx * dx
+    return sloping_beach(nx=nx, ny=ny, dx=dx, x_toe=0.1 * L, **kw)
+
+
+def solitary_of_size(nx, ny, dx=0.05, rng=None, **kw):
+    """C1-type domain scaled to nx x ny (flat 1 m bed, 0.1 m solitary wave)."""
+    x0 = 0.2 * nx * dx if rng is None else float(rng.uniform(0.15, 0.35)) * nx * dx
+    return solitary_flat(nx=nx, ny=ny, dx=dx, x0=x0, steps=None, **kw)
+
+
+def batch_mix(n=64, seed=190904154, nx_choices=None, ny_choices=None):
+    rng = np.random.default_rng(seed)
+    nx_choices = nx_choices if nx_choices is not None else list(range(256, 1537, 128))
+    ny_choices = ny_choices if ny_choices is not None else list(range(256, 513, 64))
+    out = []
+    for k in range(n):
+        nx = int(rng.choice(nx_choices))
+        ny = int(rng.choice(ny_choices))
+        if rng.uniform() < 0.5:
+            s = solitary_of_size(nx, ny, rng=rng)
+        else:
+            s = beach_of_size(nx, ny, rng=rng)
+        s["name"] = f"batch{k}_{s['name']}"
+        out.append(s)
+    return out
+
+
+def request_stream(n=200, seed=190904155, rho=0.8, capacity_cells_per_s=2.0e10, sides=None,
+                   sim_seconds=(60.0, 600.0)):
+    """Poisson arrivals of scenario requests of mixed size; returns a list of
+    (arrival_time_s, spec) sorted by arrival.  The arrival rate is set so the
+    offered load is rho times the stated capacity (cell-steps per second)."""
+    rng = np.random.default_rng(seed)
+    if sides is None:
+        lo, hi = math.log(128), math.log(2048)
+        sides = [int(round(math.exp(rng.uniform(lo, hi)) / 64.0)) * 64 for _ in range(n)]
+    reqs = []
+    work = []
+    for k in range(n):
+        side = max(128, min(2048, sides[k]))
+        dur = float(rng.uniform(*sim_seconds))
+        if rng.uniform() < 0.5:
+            s = beach_of_size(side, side, dx=0.1, t_end=dur)
+        else:
+            s = rip_beach_scaled(side, side, seed=int(rng.integers(1 << 30)), t_end=dur)
+        s["params"]["t_end"] = dur
+        s["name"] = f"req{k}_{s['name']}"
+        reqs.append(s)
+        # rough work estimate: cells x steps at CFL 0.2 and the offshore celerity
+        h = float(np.max(s["depth_c"]))
+        dt = 0.2 * s["params"]["dx"] / math.sqrt(G * h) / 2.0
+        work.append(side * side * dur / dt)
+    lam = rho * capacity_cells_per_s / float(np.mean(work))
+    t = 0.0
+    out = []
+    for s in reqs:
+        t += float(rng.exponential(1.0 / lam))
+        out.append((t, s))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# small cases used by the physics pins and parity tests
+# ---------------------------------------------------------------------------
+
+def smooth_bump_bed(nx, ny, dx, depth=1.0, amp=0.3, seed=7, n_bumps=4):
+    """Seeded smooth uneven bed, everywhere submerged (depth - bumps > 0)."""
+    rng = np.random.default_rng(seed)
+    Xc, Yc = corner_coords(nx, ny, dx, dx)
+    Lx, Ly = nx * dx, ny * dx
+    b = np.full_like(Xc, -depth)
+    for _ in range(n_bumps):
+        x0, y0 = rng.uniform(0.2, 0.8) * Lx, rng.uniform(0.2, 0.8) * Ly
+        s = rng.uniform(0.08, 0.2) * min(Lx, Ly)
+        b += rng.uniform(0.3, 1.0) * amp * np.exp(-((Xc - x0) ** 2 + (Yc - y0) ** 2) / (2 * s * s))
+    return -b
+
+
+def lake_at_rest(nx=48, ny=40, dx=0.1, seed=7, **kw):
+    p = base_params(nx, ny, dx, **kw)
+    depth_c = smooth_bump_bed(nx, ny, dx, seed=seed)
+    eta, P, Q = rest_state(nx, ny)
+    return dict(name="lake_at_rest", params=p, depth_c=depth_c, eta=eta, P=P, Q=Q)
+
+
+def closed_basin_hump(nx=64, ny=48, dx=0.1, seed=11, amp=0.05, **kw):
+    """Walls on all sides, uneven submerged bed, a Gaussian hump of water."""
+    p = base_params(nx, ny, dx, **kw)
+    depth_c = smooth_bump_bed(nx, ny, dx, seed=seed, amp=0.2)
+    X, Y = cell_coords(nx, ny, dx, dx)
+    rng = np.random.default_rng(seed)
+    x0, y0 = rng.uniform(0.3, 0.7) * nx * dx, rng.uniform(0.3, 0.7) * ny * dx
+    s = 0.1 * min(nx, ny) * dx
+    eta = amp * np.exp(-((X - x0) ** 2 + (Y - y0) ** 2) / (2 * s * s))
+    return dict(name="closed_basin_hump", params=p, depth_c=depth_c, eta=eta, P=np.zeros_like(eta),
+                Q=np.zeros_like(eta))
+
+
+def standing_wave_1d(kd, cells_per_wavelength=64, depth=1.0, rel_amp=1e-4, ny=4, n_wavelengths=1, **kw):
+    """Closed 1D basin holding n_wavelengths of a cos standing wave
+    (eta = a cos(k x), P = Q = 0), walls on all sides, flat bed."""
+    L = 2.0 * math.pi / (kd / depth) * n_wavelengths
+    nx = cells_per_wavelength * n_wavelengths
+    dx = L / nx
+    p = base_params(nx, ny, dx, **kw)
+    depth_c = np.full((ny + 1, nx + 1), float(depth))
+    X, _ = cell_coords(nx, ny, dx, dx)
+    k = kd / depth
+    eta = rel_amp * depth * np.cos(k * X)
+    return dict(name=f"standing_kd{kd}", params=p, depth_c=depth_c, eta=eta, P=np.zeros_like(eta),
+                Q=np.zeros_like(eta), k=k, L=L)
+
+
+def dam_break_dry_bed(nx=400, ny=4, dx=0.05, h_left=1.0, x_dam=None, **kw):
+    """Ritter dam break: water of depth h_left for x < x_dam over a dry,
+    horizontal bed lying at the still-water level, so d = 0 everywhere
+    (the NLSW limit of the equations, Sec. 2)."""
+    p = base_params(nx, ny, dx, **kw)
+    depth_c = np.zeros((ny + 1, nx + 1))
+    X, _ = cell_coords(nx, ny, dx, dx)
+    x_dam = x_dam if x_dam is not None else 0.5 * nx * dx
+    eta = np.where(X < x_dam, h_left, 0.0)
+    return dict(name="dam_break", params=p, depth_c=depth_c, eta=eta, P=np.zeros_like(eta),
+                Q=np.zeros_like(eta), x_dam=x_dam, h_left=h_left)
