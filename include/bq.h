@@ -1,0 +1,170 @@
+/*
+ * bq.h -- C ABI of libbq, an MI355X (gfx950) HIP implementation of one time
+ * step of the extended Boussinesq solver of Tavakkol, Son & Lynett,
+ * "Adaptive third order Adams-Bashforth time stepping for extended
+ * Boussinesq equations" (arXiv 1909.04153).
+ *
+ * The step (all of it runs in HIP kernels, enqueued on the caller's stream):
+ *   - ghost cells, two layers per side (Sec. 3.3): solid wall, sine
+ *     wavemaker, sponge layer, irregular wavemaker;
+ *   - KP07 central-upwind finite volumes for the NLSW subset with a
+ *     well-balanced bed source, central differences for the dispersive terms
+ *     and Manning friction: E, F, G of Eq. (11)-(13) (Sec. 3.1);
+ *   - Delta t from the CFL number of Eq. (22) on the current state, passed
+ *     through the lazy moving average of Eq. (47) (Sec. 3.2.2, 3.2.2.4);
+ *   - the variable-step AB3 update of w, U*, V*: Eq. (42)-(43) with the
+ *     variable-step finite differences of Eq. (44)-(46) for the time
+ *     derivatives of F*, G* (Eq. 14-15), forward Euler for the first two
+ *     steps (Sec. 3.2.1);
+ *   - the tridiagonal systems of Eq. (19)-(21) for P and Q.
+ *
+ * Conventions.  Grid nx x ny cells of dx x dy; cell (i, j) is centred at
+ * ((i + 1/2) dx, (j + 1/2) dy); host arrays are row-major with index
+ * j * nx + i.  Bathymetry is the still-water depth at the (nx+1) x (ny+1)
+ * cell corners (positive under water, negative on land), so the bottom
+ * elevation is b = -depth and the still-water level is 0 (Sec. 2:
+ * d = max(-b, 0), w = h + b, eta = h - d).
+ *
+ * Ownership.  The caller owns the device workspace passed to
+ * bq_domain_create (for instance a torch uint8 tensor on the GPU) and must
+ * keep it alive until bq_domain_free.  The library allocates nothing on the
+ * device for a domain beyond that workspace; a batch allocates its own small
+ * descriptor tables.  Host pointers passed in are only read during the call.
+ *
+ * Errors.  Every call returns 0 (BQ_OK) or a negative bq_status; nothing
+ * throws across the ABI.  bq_last_error() returns a message for the calling
+ * thread's last failure.  Numerical failures inside a step (non-finite
+ * state, Delta t below dt_min) are latched on the device per domain and
+ * reported by bq_sync; a latched domain stops advancing.  A domain (or a
+ * batch) must be driven by one host thread at a time.
+ */
+#ifndef BQ_H
+#define BQ_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BQ_ABI_VERSION 1
+#define BQ_MAX_WAVES 256
+
+typedef enum { BQ_WALL = 0, BQ_SINE = 1, BQ_SPONGE = 2, BQ_IRREGULAR = 3 } bq_bc;
+typedef enum { BQ_SIDE_W = 0, BQ_SIDE_E = 1, BQ_SIDE_S = 2, BQ_SIDE_N = 3 } bq_side;
+typedef enum { BQ_FP64 = 0, BQ_FP32 = 1 } bq_precision;
+typedef enum {
+  BQ_OK = 0,
+  BQ_EINVAL = -1,      /* bad argument */
+  BQ_ENOMEM = -2,      /* workspace smaller than bq_workspace_bytes */
+  BQ_EDEVICE = -3,     /* HIP runtime error */
+  BQ_ENONFINITE = -4,  /* NaN/Inf met by the CFL reduction (latched) */
+  BQ_EDTMIN = -5,      /* adaptive Delta t fell below dt_min (latched) */
+  BQ_ESTATE = -6,      /* call not valid in the current state */
+  BQ_EDONE = -7        /* t reached t_end; the domain no longer advances */
+} bq_status;
+
+/* Parameters of one domain.  Field order is part of the ABI. */
+typedef struct bq_params {
+  int32_t nx, ny;          /* interior cells, each >= 4 */
+  double dx, dy;           /* cell size [m] */
+  double g;                /* gravitational acceleration [m/s^2] */
+  double B;                /* dispersion coefficient of Eq. (2)-(3), 1/15 */
+  double manning_n;        /* Manning coefficient of f1, f2 [s/m^(1/3)] */
+  double cfl;              /* target CFL number of Eq. (22) */
+  double ema_alpha;        /* alpha of the lazy moving average, Eq. (47) */
+  double dt_init;          /* first Delta t; 0 = from the CFL number */
+  double dt_max, dt_min;   /* clamp / failure threshold of the adaptive step */
+  int32_t fixed_dt;        /* 1 = every step uses dt_init (uniform AB3, Eq. 16-18) */
+  double theta;            /* generalised-minmod parameter in [1, 2]; 0 = central slopes */
+  double eps_desing;       /* velocity desingularisation epsilon; 0 = max(dx^4, dy^4) */
+  int32_t bc[4];           /* bq_bc per side W, E, S, N; wavemakers on W only */
+  double sponge_width[4];  /* sponge band width per side [m] (BQ_SPONGE sides) */
+  double sponge_sigma;     /* peak damping rate of the sponge [1/s] */
+  int32_t n_waves;         /* wavemaker components (<= BQ_MAX_WAVES) */
+  const double* wave_amp;  /* host arrays of n_waves: amplitude [m], */
+  const double* wave_omega;/*   angular frequency [rad/s], */
+  const double* wave_phase;/*   phase [rad] (may be NULL = 0) */
+  double wave_ramp;        /* tau of the start-up ramp 1 - exp(-(t/tau)^2); 0 = none */
+  double t_end;            /* stop once t >= t_end (status BQ_EDONE); 0 = never */
+  int32_t fstar_order;     /* extrapolation of F*, G* in time: 2 = quadratic
+                              (Eq. 43-46), 1 = linear (stable reading for 2D
+                              dispersive cases); 0 selects 2 */
+  int32_t precision;       /* bq_precision of the field arithmetic; Delta t,
+                              the AB3/FD weights, time and mass/energy sums are
+                              FP64 in both */
+} bq_params;
+
+typedef struct bq_info {
+  double t;                /* simulated time of the current state */
+  int64_t n;               /* steps taken since bq_set_state */
+  double dt_last;          /* Delta t of the last step */
+  double dt_prev1, dt_prev2;
+  double smax;             /* max((|u|+c)/dx, (|v|+c)/dy) of the current state */
+  double mass;             /* sum of h dx dy (FP64) */
+  double energy;           /* sum of (g eta^2 / 2 [d > 0] + (P^2 + Q^2) / 2h [h > 1e-6]) dx dy */
+  int32_t status;          /* latched bq_status of the domain */
+} bq_info;
+
+typedef struct bq_domain bq_domain;
+typedef struct bq_batch bq_batch;
+
+int bq_abi_version(void);
+const char* bq_last_error(void);
+
+/* Defaults: g 9.81, B 1/15, cfl 0.2, ema_alpha 0.1, dt_max 1, dt_min 1e-9,
+ * theta 1.3, walls, fstar_order 2, FP64. */
+void bq_params_default(bq_params* p);
+
+/* Device bytes a domain with these parameters needs (pure host function). */
+int bq_workspace_bytes(const bq_params* p, size_t* bytes);
+
+/* Create a domain in the caller's device workspace; hip_stream is a
+ * hipStream_t (NULL = the null stream).  depth_c is the host corner
+ * still-water depth, (ny+1) x (nx+1) row-major.  Precomputes the static
+ * fields and the factorisation data of Eq. (19)-(21).  State: lake at rest. */
+int bq_domain_create(const bq_params* p, const double* depth_c, void* dev_workspace, size_t bytes,
+                     void* hip_stream, bq_domain** out);
+int bq_domain_free(bq_domain* d);
+
+/* Host FP64 interior arrays (nx*ny each): eta (Sec. 2: eta = h - d), P, Q.
+ * Rejects eta < -d (negative depth) with BQ_EINVAL.  Clears the AB3 history,
+ * so the next two steps are forward Euler.  Synchronous. */
+int bq_set_state(bq_domain* d, const double* eta, const double* P, const double* Q);
+
+/* Enqueue n_steps adaptive steps (asynchronous; returns launch errors only). */
+int bq_step(bq_domain* d, int32_t n_steps);
+/* Enqueue one step with a prescribed Delta t (bypasses Eq. 22 and 47). */
+int bq_step_dt(bq_domain* d, double dt);
+
+/* Wait for the domain's stream; fill *out (may be NULL) and return the
+ * latched status. */
+int bq_sync(bq_domain* d, bq_info* out);
+
+/* Synchronous read of the interior: which = 0 eta, 1 P, 2 Q, 3 w; FP64. */
+int bq_read(bq_domain* d, int32_t which, double* host_out);
+
+/* Checkpoint of the full state including the AB3 history, so a resumed run
+ * continues bit-for-bit.  bq_save with host == NULL returns the size. */
+int bq_save(bq_domain* d, void* host, size_t* bytes);
+int bq_load(bq_domain* d, const void* host, size_t bytes);
+
+/* Batches: domains of one precision advanced together, one launch per phase
+ * over a flattened tile work-list.  Domains keep their own Delta t, time and
+ * status; a halted domain is skipped.  bq_batch_set replaces the member list
+ * (attach/detach between steps).  All members must have been created on the
+ * batch's stream or be idle. */
+int bq_batch_create(bq_domain* const* doms, int32_t n, void* hip_stream, bq_batch** out);
+int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n);
+int bq_batch_step(bq_batch* b, int32_t n_steps);
+int bq_batch_sync(bq_batch* b);
+int bq_batch_free(bq_batch* b);
+
+/* Number of steps captured per hipGraph replay (0 = plain launches). */
+int bq_set_graph_steps(bq_domain* d, int32_t steps);
+int bq_batch_set_graph_steps(bq_batch* b, int32_t steps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,282 @@
+"""ctypes binding of libbq (include/bq.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; PyTorch provides the device
+workspace (a uint8 tensor) and the stream.  Importing works without a GPU;
+creating a domain needs the built library and a GPU, and fails loudly
+otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbq.so")
+
+WALL, SINE, SPONGE, IRREGULAR = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDTMIN, ESTATE, EDONE = 0, -1, -2, -3, -4, -5, -6, -7
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENONFINITE: "ENONFINITE",
+                EDTMIN: "EDTMIN", ESTATE: "ESTATE", EDONE: "EDONE"}
+
+
+class BqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("g", ctypes.c_double), ("B", ctypes.c_double), ("manning_n", ctypes.c_double),
+        ("cfl", ctypes.c_double), ("ema_alpha", ctypes.c_double), ("dt_init", ctypes.c_double),
+        ("dt_max", ctypes.c_double), ("dt_min", ctypes.c_double), ("fixed_dt", ctypes.c_int32),
+        ("theta", ctypes.c_double), ("eps_desing", ctypes.c_double),
+        ("bc", ctypes.c_int32 * 4), ("sponge_width", ctypes.c_double * 4), ("sponge_sigma", ctypes.c_double),
+        ("n_waves", ctypes.c_int32),
+        ("wave_amp", ctypes.POINTER(ctypes.c_double)), ("wave_omega", ctypes.POINTER(ctypes.c_double)),
+        ("wave_phase", ctypes.POINTER(ctypes.c_double)), ("wave_ramp", ctypes.c_double),
+        ("t_end", ctypes.c_double), ("fstar_order", ctypes.c_int32), ("precision", ctypes.c_int32),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("n", ctypes.c_int64), ("dt_last", ctypes.c_double),
+                ("dt_prev1", ctypes.c_double), ("dt_prev2", ctypes.c_double), ("smax", ctypes.c_double),
+                ("mass", ctypes.c_double), ("energy", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+EXPORTS = ["bq_abi_version", "bq_last_error", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
+           "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
+           "bq_batch_create", "bq_batch_set", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
+           "bq_set_graph_steps", "bq_batch_set_graph_steps"]
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libbq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or os.environ.get("BQ_LIBRARY", LIB_PATH)
+    if not os.path.exists(p):
+        raise RuntimeError(f"libbq.so not built ({p}); run __graft_entry__.build()")
+    L = ctypes.CDLL(p)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
+    L.bq_abi_version.restype = ctypes.c_int
+    L.bq_last_error.restype = ctypes.c_char_p
+    L.bq_params_default.argtypes = [ctypes.POINTER(Params)]
+    L.bq_params_default.restype = None
+    L.bq_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
+    L.bq_domain_create.argtypes = [ctypes.POINTER(Params), dp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.bq_domain_free.argtypes = [vp]
+    L.bq_set_state.argtypes = [vp, dp, dp, dp]
+    L.bq_step.argtypes = [vp, ip]
+    L.bq_step_dt.argtypes = [vp, ctypes.c_double]
+    L.bq_sync.argtypes = [vp, ctypes.POINTER(Info)]
+    L.bq_read.argtypes = [vp, ip, dp]
+    L.bq_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
+    L.bq_load.argtypes = [vp, vp, ctypes.c_size_t]
+    L.bq_batch_create.argtypes = [ctypes.POINTER(vp), ip, vp, ctypes.POINTER(vp)]
+    L.bq_batch_set.argtypes = [vp, ctypes.POINTER(vp), ip]
+    L.bq_batch_step.argtypes = [vp, ip]
+    L.bq_batch_sync.argtypes = [vp]
+    L.bq_batch_free.argtypes = [vp]
+    L.bq_set_graph_steps.argtypes = [vp, ip]
+    L.bq_batch_set_graph_steps.argtypes = [vp, ip]
+    if L.bq_abi_version() != 1:
+        raise RuntimeError("libbq ABI version mismatch")
+    if path is None:
+        _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != OK:
+        raise BqError(rc, load().bq_last_error().decode(errors="replace"))
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_params(params: dict, precision: int = FP64) -> tuple[Params, list]:
+    """Marshal a scenario parameter dict into the C struct; returns the struct
+    and the numpy arrays it points to (keep them alive while it is used)."""
+    p = Params()
+    load().bq_params_default(ctypes.byref(p))
+    for k in ("nx", "ny", "fixed_dt", "fstar_order"):
+        if k in params:
+            setattr(p, k, int(params[k]))
+    for k in ("dx", "dy", "g", "B", "manning_n", "cfl", "ema_alpha", "dt_init", "dt_max", "dt_min", "theta",
+              "eps_desing", "sponge_sigma", "wave_ramp", "t_end"):
+        if k in params:
+            setattr(p, k, float(params[k]))
+    for s, v in enumerate(params.get("bc", (WALL,) * 4)):
+        p.bc[s] = int(v)
+    for s, v in enumerate(params.get("sponge_width", (0.0,) * 4)):
+        p.sponge_width[s] = float(v)
+    keep = []
+    amp = np.ascontiguousarray(params.get("wave_amp", []), dtype=np.float64)
+    if len(amp):
+        om = np.ascontiguousarray(params["wave_omega"], dtype=np.float64)
+        ph = np.ascontiguousarray(params.get("wave_phase", np.zeros(len(amp))), dtype=np.float64)
+        keep += [amp, om, ph]
+        p.n_waves = len(amp)
+        p.wave_amp, p.wave_omega, p.wave_phase = _dptr(amp), _dptr(om), _dptr(ph)
+    p.precision = int(precision)
+    return p, keep
+
+
+def workspace_bytes(params: dict, precision: int = FP64) -> int:
+    p, _ = make_params(params, precision)
+    n = ctypes.c_size_t()
+    _check(load().bq_workspace_bytes(ctypes.byref(p), ctypes.byref(n)))
+    return int(n.value)
+
+
+@dataclass
+class StepInfo:
+    t: float
+    n: int
+    dt_last: float
+    dt_prev1: float
+    dt_prev2: float
+    smax: float
+    mass: float
+    energy: float
+    status: int
+
+
+def _torch():
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("libbq needs a GPU (torch.cuda.is_available() is False)")
+    return torch
+
+
+class Domain:
+    """One simulation domain living in a device workspace owned by torch."""
+
+    def __init__(self, params: dict, depth_c, precision: int = FP64, stream=None, device="cuda"):
+        torch = _torch()
+        self.params = dict(params)
+        self.precision = int(precision)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        p, keep = make_params(params, precision)
+        nbytes = workspace_bytes(params, precision)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        dc = np.ascontiguousarray(depth_c, dtype=np.float64)
+        if dc.shape != (self.ny + 1, self.nx + 1):
+            raise ValueError(f"depth_c must be ({self.ny + 1}, {self.nx + 1}), got {dc.shape}")
+        h = ctypes.c_void_p()
+        _check(load().bq_domain_create(ctypes.byref(p), _dptr(dc), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       nbytes, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bq_domain_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, eta, P, Q):
+        a = [np.ascontiguousarray(v, dtype=np.float64).reshape(self.ny, self.nx) for v in (eta, P, Q)]
+        _check(load().bq_set_state(self._h, *(_dptr(v) for v in a)))
+
+    def step(self, n: int = 1):
+        _check(load().bq_step(self._h, int(n)))
+
+    def step_dt(self, dt: float):
+        _check(load().bq_step_dt(self._h, float(dt)))
+
+    def set_graph_steps(self, k: int):
+        _check(load().bq_set_graph_steps(self._h, int(k)))
+
+    def sync(self) -> StepInfo:
+        i = Info()
+        rc = load().bq_sync(self._h, ctypes.byref(i))
+        if rc not in (OK, ENONFINITE, EDTMIN, EDONE, EINVAL):
+            _check(rc)
+        return StepInfo(i.t, i.n, i.dt_last, i.dt_prev1, i.dt_prev2, i.smax, i.mass, i.energy, i.status)
+
+    def read(self, which: str) -> np.ndarray:
+        idx = {"eta": 0, "P": 1, "Q": 2, "w": 3}[which]
+        out = np.zeros((self.ny, self.nx))
+        _check(load().bq_read(self._h, idx, _dptr(out)))
+        return out
+
+    def save(self) -> bytes:
+        n = ctypes.c_size_t()
+        _check(load().bq_save(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(load().bq_save(self._h, buf, ctypes.byref(n)))
+        return buf.raw
+
+    def load_checkpoint(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(load().bq_load(self._h, buf, len(blob)))
+
+
+class Batch:
+    """Domains of one precision advanced together by one launch per phase."""
+
+    def __init__(self, domains, stream=None):
+        torch = _torch()
+        self.domains = list(domains)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        arr = (ctypes.c_void_p * len(self.domains))(*[d.handle for d in self.domains])
+        h = ctypes.c_void_p()
+        _check(load().bq_batch_create(arr, len(self.domains), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h)))
+        self._h = h
+
+    def set(self, domains):
+        self.domains = list(domains)
+        arr = (ctypes.c_void_p * len(self.domains))(*[d.handle for d in self.domains])
+        _check(load().bq_batch_set(self._h, arr, len(self.domains)))
+
+    def step(self, n: int = 1):
+        _check(load().bq_batch_step(self._h, int(n)))
+
+    def sync(self):
+        _check(load().bq_batch_sync(self._h))
+
+    def set_graph_steps(self, k: int):
+        _check(load().bq_batch_set_graph_steps(self._h, int(k)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bq_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def domain_from_spec(spec: dict, precision: int = FP64, stream=None) -> Domain:
+    d = Domain(spec["params"], spec["depth_c"], precision=precision, stream=stream)
+    d.set_state(spec["eta"], spec["P"], spec["Q"])
+    return d

@@ -1,0 +1,942 @@
+// bq_kernels.hpp -- gfx950 kernels of one adaptive-AB3 extended-Boussinesq
+// time step (arXiv 1909.04153, Sec. 2-3).
+//
+// Data layout (per domain, all in the caller's workspace):
+//   * state fields with two ghost layers (Sec. 3.3), row-major, row pitch a
+//     multiple of 256 B and interior column 0 256-B aligned:
+//       w[2] (double-buffered), P[3], Q[3] (rings: slot n % 3 = level n);
+//   * interior-only fields: E, F, G rings (slot n % 3), local solutions
+//     xhP, xhQ, spikes of the chunked line solves, cell still-water depth;
+//   * corner still-water depth Dc with two mirrored ghost corner layers;
+//   * per-chunk boundary/interface values of the line solves, [chunk][line];
+//   * one FP64 DevState: time, Delta t history, weights, status.
+//
+// Per step (one launch each, over all domains of a batch):
+//   k_dt      Delta t from the CFL maximum (Eq. 22) and Eq. (47), AB3 weights
+//             (Eq. 42) and F*/G* weights (Eq. 43-46) in FP64, wavemaker
+//             ghost values at t_{n+1};
+//   k_rhs     LDS tile (64 x TY + halo 2): KP07 fluxes, bed source,
+//             dispersion, friction, F*/G* of the weighted P/Q history,
+//             U*^n, V*^n, AB3 update; then the chunk-local tridiagonal solves
+//             of Eq. (19)-(20) inside the tile;
+//   k_reduced per line: the chunk-interface recurrence that couples the
+//             chunk-local solutions into the exact line solution;
+//   k_final   pointwise: P, Q = local solution + spike corrections, sponge,
+//             ghost cells of the new state, CFL maximum of the new state.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bqk {
+
+enum { WALL = 0, SINE = 1, SPONGE = 2, IRREGULAR = 3 };
+enum { ST_OK = 0, ST_ENONFINITE = -4, ST_EDTMIN = -5, ST_EDONE = -7 };
+
+constexpr int TX = 64;      // tile width (cells)
+constexpr int NT = 256;     // threads per tile block
+
+struct alignas(64) DevState {
+  // committed state
+  double t;                 // time of the current state
+  double dt1, dt2, dt3;     // Delta t of the last three steps (dt1 most recent)
+  long long n;              // steps taken
+  int status;
+  int pending;              // a step was scheduled by k_dt and is not yet committed
+  // the step being taken
+  double dt;
+  double alpha[3];
+  double beta[3];
+  double t_next;
+  double gw[2], gP[2];      // wavemaker ghost values (cells -1, -2) at t_next
+  double smax_used;         // CFL maximum the step's Delta t was taken from
+  int halt;                 // 1 = kernels of this step leave the domain untouched
+  int slot;                 // n % 3 of the step being taken
+  unsigned long long smax_bits;  // running max of the speeds of the new state
+  double mass, energy;      // diagnostics (filled on demand)
+  double pad[2];
+};
+
+template <typename T>
+struct DomDev {
+  int nx, ny;
+  int pitch, xoff;          // ghosted fields: (i, j) at (j + 2) * pitch + xoff + i
+  int ipitch;               // interior fields: (i, j) at j * ipitch + i
+  int cpitch;               // corners: (ic, jc) at (jc + 2) * cpitch + ic + 2
+  int cx, cy;               // chunks per x-line / y-line
+  int mx, my;               // chunk lengths
+  int tiles_x, tiles_y;
+  int bc[4];
+  int fstar_order, fixed_dt, n_waves, any_sponge;
+  T dx, dy, g, B, Bc, gn2, theta, eps;
+  T sponge_w[4];
+  T sponge_sigma;
+  double dx_d, dy_d, g_d, cfl, ema_alpha, dt_init, dt_max, dt_min, wave_ramp, t_end;
+  T* w[2];
+  T* P[3];
+  T* Q[3];
+  T* E[3];
+  T* F[3];
+  T* G[3];
+  T* Dc;
+  T* Dbar;
+  T* xhP;
+  T* xhQ;
+  T* spxv;
+  T* spxw;
+  T* spyv;
+  T* spyw;
+  T* chx;                   // [2][cx][ny]: local solution at chunk first / last
+  T* chy;                   // [2][cy][nx]
+  T* rsx;                   // [6][cx][ny]: static interface-recurrence coefficients
+  T* rsy;                   // [6][cy][nx]
+  T* ifx;                   // [2][cx][ny]: neighbour values left / right of a chunk
+  T* ify;                   // [2][cy][nx]
+  double* wave;             // [4][n_waves]: amplitude, omega, phase, wave number
+  double* io;               // nx * ny doubles of staging for host transfers
+  DevState* st;
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T gmm(T a, T b, T c) {
+  const T lo = fmin(a, fmin(b, c));
+  const T hi = fmax(a, fmax(b, c));
+  return lo > T(0) ? lo : (hi < T(0) ? hi : T(0));
+}
+
+// limited slope (times the cell size) of q at a cell from its two neighbours
+template <typename T>
+__device__ __forceinline__ T slope(T qm, T q0, T qp, T theta) {
+  const T c = T(0.5) * (qp - qm);
+  return theta > T(0) ? gmm(theta * (q0 - qm), c, theta * (qp - q0)) : c;
+}
+
+// velocity from a flux and a depth, regularised near dry states (KP07)
+template <typename T>
+__device__ __forceinline__ T desing(T q, T h, T eps) {
+  const T h2 = h * h;
+  const T h4 = h2 * h2;
+  return T(1.4142135623730951) * h * q / sqrt(h4 + fmax(h4, eps));
+}
+
+// cell-average still-water depth from its four corners
+template <typename T>
+__device__ __forceinline__ T dbar4(T a, T b, T c, T d) {
+  return T(0.25) * (a + b + c + d);
+}
+
+template <typename T>
+__device__ __forceinline__ T dpos(T D) {
+  return fmax(D, T(0));
+}
+
+// Piecewise-linear w at a cell's low/high faces with the KP07 positivity
+// correction; Dlo/Dhi are the still-water depths at the faces (bed = -D).
+template <typename T>
+__device__ __forceinline__ void recon_w(T wm, T w0, T wp, T theta, T Dlo, T Dhi, T& wlo, T& whi) {
+  const T s = slope(wm, w0, wp, theta);
+  wlo = w0 - T(0.5) * s;
+  whi = w0 + T(0.5) * s;
+  if (whi + Dhi < T(0)) {
+    whi = -Dhi;
+    wlo = T(2) * w0 + Dhi;
+  } else if (wlo + Dlo < T(0)) {
+    wlo = -Dlo;
+    whi = T(2) * w0 + Dlo;
+  }
+}
+
+// One side of a face.  The hydrostatic pressure g h^2 / 2 is carried as its
+// departure from the still-water value g D+^2 / 2 at the face, D+ = max(D, 0):
+//   pp = g (h - D+)(h + D+) / 2,
+//   h - D+ = w (wet face below the still-water line), -D (dry there), h (land).
+// The still-water parts of the flux differences and of the well-balanced bed
+// source cancel exactly except in cells whose two faces straddle the
+// still-water line (see shore_term); keeping them would leave FP32 with a
+// difference of large numbers in deep water.
+template <typename T>
+struct Side {
+  T w, h, un, ut, qn, qt, pp;
+};
+
+template <typename T>
+__device__ __forceinline__ Side<T> make_side(T w, T qn, T qt, T Dface, T eps, T g) {
+  Side<T> s;
+  s.w = w;
+  s.h = fmax(w + Dface, T(0));
+  s.un = desing(qn, s.h, eps);
+  s.ut = desing(qt, s.h, eps);
+  s.qn = s.h * s.un;
+  s.qt = s.h * s.ut;
+  const T Dp = fmax(Dface, T(0));
+  const T dev = Dface > T(0) ? (s.h > T(0) ? w : -Dface) : s.h;
+  s.pp = T(0.5) * g * dev * (s.h + Dp);
+  return s;
+}
+
+// central-upwind flux normal to a face, components (mass, normal momentum,
+// tangential momentum); the normal momentum flux excludes g D^2 / 2
+template <typename T>
+__device__ __forceinline__ void cu_flux(const Side<T>& L, const Side<T>& R, T g, T Dface, T& f0, T& fn, T& ft) {
+  const T cL = sqrt(g * L.h), cR = sqrt(g * R.h);
+  const T ap = fmax(fmax(L.un + cL, R.un + cR), T(0));
+  const T am = fmin(fmin(L.un - cL, R.un - cR), T(0));
+  const T den = ap - am;
+  if (den == T(0)) {
+    // both sides dry and at rest: the full flux is zero
+    const T Dp = fmax(Dface, T(0));
+    f0 = ft = T(0);
+    fn = -T(0.5) * g * Dp * Dp;
+    return;
+  }
+  const T inv = T(1) / den;
+  const T dis = ap * am * inv;
+  const T pL = L.qn * L.un + L.pp;
+  const T pR = R.qn * R.un + R.pp;
+  f0 = (ap * L.qn - am * R.qn) * inv + dis * (R.w - L.w);
+  fn = (ap * pL - am * pR) * inv + dis * (R.qn - L.qn);
+  ft = (ap * L.qn * L.ut - am * R.qn * R.ut) * inv + dis * (R.qt - L.qt);
+}
+
+// departure of a face depth from the face's still-water depth D+ (as above)
+template <typename T>
+__device__ __forceinline__ T face_dev(T wf, T Df) {
+  const T h = fmax(wf + Df, T(0));
+  return Df > T(0) ? (h > T(0) ? wf : -Df) : h;
+}
+
+// still-water remainder of (bed source - pressure flux difference) in a cell
+// whose low/high faces have still-water depths Dl, Dh: zero unless exactly
+// one of them is below the still-water line
+template <typename T>
+__device__ __forceinline__ T shore_term(T Dl, T Dh, T g) {
+  if ((Dl > T(0)) == (Dh > T(0))) return T(0);
+  const T pl = fmax(Dl, T(0)), ph = fmax(Dh, T(0));
+  return T(0.5) * g * ((Dh - Dl) * (ph + pl) - (ph * ph - pl * pl));
+}
+
+// Coefficients of Eq. (21) at a cell from the still-water depths of the cell
+// and its two neighbours along the line (spacing h).
+template <typename T>
+__device__ __forceinline__ void tri_coef(T dm, T d0, T dp, T h, T Bc, T& a, T& b, T& c) {
+  const T dd = (dp - dm) / (T(2) * h);
+  const T k = Bc * d0 * d0 / (h * h);
+  const T s = d0 * dd / (T(6) * h);
+  a = s - k;
+  b = T(1) + T(2) * k;
+  c = -s - k;
+}
+
+// Chunk-local tridiagonal solve (zero coupling to the neighbouring chunks)
+// of the m (<= M) unknowns of one chunk.  dl[k * ds], k = 0..m+1, are the
+// still-water depths of the chunk's cells with one neighbour on each side.
+// fold_lo / fold_hi fold the odd mirror of a wall into the first / last
+// diagonal.  rhs (stride rs) is overwritten with the solution; piv (stride
+// rs) receives the reciprocal pivots.
+template <typename T, int M>
+__device__ __forceinline__ void chunk_solve(const T* dl, int ds, int m, T h, T Bc, bool fold_lo, bool fold_hi, T* rhs,
+                                            T* piv, int rs) {
+  T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
+  for (int k = 0; k < m; ++k) {
+    T a, b, c;
+    tri_coef(dl[k * ds], dl[(k + 1) * ds], dl[(k + 2) * ds], h, Bc, a, b, c);
+    if (k == 0 && fold_lo) b -= a;
+    if (k == m - 1 && fold_hi) b -= c;
+    const T r = rhs[k * rs];
+    T u, y;
+    if (k == 0) {
+      u = b;
+      y = r;
+    } else {
+      const T l = a * iu_prev;
+      u = b - l * c_prev;
+      y = r - l * y_prev;
+    }
+    const T iu = T(1) / u;
+    piv[k * rs] = iu;
+    rhs[k * rs] = y;
+    y_prev = y;
+    iu_prev = iu;
+    c_prev = c;
+  }
+  T x_next = T(0);
+  for (int k = m - 1; k >= 0; --k) {
+    T a, b, c;
+    tri_coef(dl[k * ds], dl[(k + 1) * ds], dl[(k + 2) * ds], h, Bc, a, b, c);
+    const T y = rhs[k * rs];
+    const T x = (k == m - 1) ? y * piv[k * rs] : (y - c * x_next) * piv[k * rs];
+    rhs[k * rs] = x;
+    x_next = x;
+  }
+}
+
+// chunk_solve on raw cell-average still-water depths (d = max(D, 0))
+template <typename T, int M>
+__device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, T h, T Bc, bool fold_lo, bool fold_hi,
+                                               T* rhs, T* piv, int rs) {
+  struct DV {
+    const T* p;
+    int s;
+  };
+  T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
+  for (int k = 0; k < m; ++k) {
+    T a, b, c;
+    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), h, Bc, a, b, c);
+    if (k == 0 && fold_lo) b -= a;
+    if (k == m - 1 && fold_hi) b -= c;
+    const T r = rhs[k * rs];
+    T u, y;
+    if (k == 0) {
+      u = b;
+      y = r;
+    } else {
+      const T l = a * iu_prev;
+      u = b - l * c_prev;
+      y = r - l * y_prev;
+    }
+    const T iu = T(1) / u;
+    piv[k * rs] = iu;
+    rhs[k * rs] = y;
+    y_prev = y;
+    iu_prev = iu;
+    c_prev = c;
+  }
+  T x_next = T(0);
+  for (int k = m - 1; k >= 0; --k) {
+    T a, b, c;
+    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), h, Bc, a, b, c);
+    const T y = rhs[k * rs];
+    const T x = (k == m - 1) ? y * piv[k * rs] : (y - c * x_next) * piv[k * rs];
+    rhs[k * rs] = x;
+    x_next = x;
+  }
+}
+
+// locate the domain of a flattened index with a prefix table (nd + 1 entries)
+__device__ __forceinline__ int find_domain(const int* prefix, int nd, int idx) {
+  int lo = 0, hi = nd;  // prefix[lo] <= idx < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= idx) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// k_dt: Delta t and weights of the step (one block per domain)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void commit(DevState* st) {
+  if (st->pending) {
+    st->t = st->t_next;
+    st->dt3 = st->dt2;
+    st->dt2 = st->dt1;
+    st->dt1 = st->dt;
+    st->n += 1;
+    st->pending = 0;
+  }
+}
+
+template <typename T>
+__device__ void wave_ghosts(const DomDev<T>& D, double t, double* gw, double* gP) {
+  // surface and flux of the incident wave train at the centres of ghost
+  // cells -1 and -2 (x = -dx/2, -3dx/2); only thread 0's result is used
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  const double r = D.wave_ramp > 0.0 ? 1.0 - exp(-(t / D.wave_ramp) * (t / D.wave_ramp)) : 1.0;
+  const int nw = D.n_waves;
+  for (int m = tid; m < nw; m += 64) {
+    const double amp = D.wave[m], om = D.wave[nw + m], ph = D.wave[2 * nw + m], k = D.wave[3 * nw + m];
+    const double s1 = r * amp * sin(om * t + 0.5 * k * D.dx_d + ph);
+    const double s2 = r * amp * sin(om * t + 1.5 * k * D.dx_d + ph);
+    a0 += s1;
+    a1 += om / k * s1;
+    a2 += s2;
+    a3 += om / k * s2;
+  }
+  red[0][tid] = a0; red[1][tid] = a1; red[2][tid] = a2; red[3][tid] = a3;
+  __syncthreads();
+  if (tid == 0) {
+    double s[4] = {0, 0, 0, 0};
+    for (int q = 0; q < 64; ++q)
+      for (int c = 0; c < 4; ++c) s[c] += red[c][q];
+    gw[0] = s[0]; gP[0] = s[1]; gw[1] = s[2]; gP[1] = s[3];
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, double dt_prescribed) {
+  const DomDev<T>& D = doms[blockIdx.x];
+  DevState* st = D.st;
+  __shared__ int go;
+  __shared__ double tn;
+  if (threadIdx.x == 0) {
+    commit(st);
+    go = 0;
+    st->halt = 1;
+    if (st->status == ST_OK) {
+      if (D.t_end > 0.0 && st->t >= D.t_end) {
+        st->status = ST_EDONE;
+      } else {
+        const double s = __longlong_as_double((long long)st->smax_bits);
+        if (!(s <= 1.79e308)) {
+          st->status = ST_ENONFINITE;
+        } else {
+          const long long n = st->n;
+          double dt;
+          bool ok = true;
+          if (dt_prescribed > 0.0) {
+            dt = dt_prescribed;
+          } else if (D.fixed_dt) {
+            dt = D.dt_init;
+          } else {
+            const double cand = s > 0.0 ? D.cfl / s : D.dt_max;
+            if (n == 0) dt = D.dt_init > 0.0 ? D.dt_init : cand;
+            else dt = cand <= st->dt1 ? cand : D.ema_alpha * cand + (1.0 - D.ema_alpha) * st->dt1;
+            dt = fmin(dt, D.dt_max);
+            if (dt < D.dt_min) {
+              st->status = ST_EDTMIN;
+              ok = false;
+            }
+          }
+          if (ok) {
+            const double h0 = dt, h1 = st->dt1, h2 = st->dt2;
+            double a0 = h0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+            if (n == 1) {
+              b0 = h0 / h1;
+              b1 = -b0;
+            } else if (n >= 2) {
+              // Eq. (42): integral over [t_n, t_n + h0] of the quadratic
+              // through the three last nodes
+              const double r1 = h0 / h1, s12 = h1 + h2;
+              a0 = h0 / 6.0 * (r1 * (2.0 * h0 + 6.0 * h1 + 3.0 * h2) / s12 + 6.0);
+              a1 = -h0 / 6.0 * (r1 * (2.0 * h0 + 3.0 * h1 + 3.0 * h2) / h2);
+              a2 = h0 / 6.0 * ((h0 / h2) * (2.0 * h0 + 3.0 * h1) / s12);
+              if (D.fstar_order == 1) {
+                b0 = r1;
+                b1 = -r1;
+              } else {
+                // Eq. (43) with (44)-(46) sum to the increment of the quadratic
+                // through (t_{n-k}, F*^{n-k}) from t_n to t_n + h0
+                b0 = (h0 + h1) * (h0 + s12) / (h1 * s12) - 1.0;
+                b1 = -h0 * (h0 + s12) / (h1 * h2);
+                b2 = h0 * (h0 + h1) / (h2 * s12);
+              }
+            }
+            st->dt = dt;
+            st->alpha[0] = a0; st->alpha[1] = a1; st->alpha[2] = a2;
+            st->beta[0] = b0; st->beta[1] = b1; st->beta[2] = b2;
+            st->t_next = st->t + dt;
+            st->smax_used = s;
+            st->slot = (int)(n % 3);
+            st->smax_bits = 0ull;
+            st->pending = 1;
+            st->halt = 0;
+            go = 1;
+            tn = st->t_next;
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (go && D.n_waves > 0 && (D.bc[0] == SINE || D.bc[0] == IRREGULAR)) {
+    double gw[2], gP[2];
+    wave_ghosts(D, tn, gw, gP);
+    if (threadIdx.x == 0) {
+      st->gw[0] = gw[0]; st->gw[1] = gw[1]; st->gP[0] = gP[0]; st->gP[1] = gP[1];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_commit(const DomDev<T>* __restrict__ doms, int nd) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d < nd) commit(doms[d].st);
+}
+
+// ---------------------------------------------------------------------------
+// k_rhs: fused spatial operator, AB3 update and chunk-local line solves
+// ---------------------------------------------------------------------------
+
+template <typename T, int TY, int MX>
+struct RhsSmem {
+  static constexpr int WX = TX + 4, WY = TY + 4;      // radius-2 tiles
+  static constexpr int BX = TX + 2, BY = TY + 2;      // radius-1 tiles
+  static constexpr int CXN = TX + 5, CYN = TY + 5;    // corners
+  T w[WY * WX];
+  T p[WY * WX];
+  T q[WY * WX];
+  T db[WY * WX];                                      // cell still-water depth
+  T pt[BY * BX];                                      // sum_k beta_k P^{n-k}
+  T qt[BY * BX];
+  T dc[CYN * CXN];
+  union {
+    struct {
+      T fx[3][TY * (TX + 1)];
+      T fy[3][(TY + 1) * TX];
+    } f;
+    struct {
+      T u[TY * TX];
+      T v[TY * TX];
+      T pu[TY * TX];
+      T pv[TY * TX];
+    } s;
+  } x;
+};
+
+template <typename T, int TY, int MX>
+__global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_prefix,
+                                           int nd) {
+  using S = RhsSmem<T, TY, MX>;
+  constexpr int WX = S::WX, BX = S::BX, CXN = S::CXN;
+  constexpr int CPT = (TX * TY) / NT;   // cells per thread
+  static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
+  __shared__ S sm;
+  const int dom = find_domain(tile_prefix, nd, blockIdx.x);
+  const DomDev<T>& D = doms[dom];
+  const DevState* st = D.st;
+  if (st->halt) return;
+  const int tile = blockIdx.x - tile_prefix[dom];
+  const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
+  const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
+  const int slot = st->slot;
+  const int s1 = slot == 0 ? 2 : slot - 1, s2 = slot == 2 ? 0 : slot + 1;
+  const T* __restrict__ w = D.w[st->n & 1];
+  const T* __restrict__ Pn = D.P[slot];
+  const T* __restrict__ Qn = D.Q[slot];
+  const T beta0 = (T)st->beta[0], beta1 = (T)st->beta[1], beta2 = (T)st->beta[2];
+  const bool hist = st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
+  const int pitch = D.pitch, xoff = D.xoff;
+
+  // ---- phase 0: stage the tile and its halo in LDS -----------------------
+  for (int e = tid; e < S::WY * WX; e += NT) {
+    const int r = e / WX, c = e - r * WX;
+    const int i = min(max(i0 + c - 2, -2), nx + 1), j = min(max(j0 + r - 2, -2), ny + 1);
+    const size_t g = (size_t)(j + 2) * pitch + xoff + i;
+    sm.w[e] = w[g];
+    sm.p[e] = Pn[g];
+    sm.q[e] = Qn[g];
+  }
+  for (int e = tid; e < S::CYN * CXN; e += NT) {
+    const int r = e / CXN, c = e - r * CXN;
+    const int ic = min(i0 + c - 2, nx + 2), jc = min(j0 + r - 2, ny + 2);
+    sm.dc[e] = D.Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
+  }
+  for (int e = tid; e < S::BY * BX; e += NT) {
+    const int r = e / BX, c = e - r * BX;
+    const int i = min(max(i0 + c - 1, -2), nx + 1), j = min(max(j0 + r - 1, -2), ny + 1);
+    const size_t g = (size_t)(j + 2) * pitch + xoff + i;
+    T pv = T(0), qv = T(0);
+    if (hist) {
+      pv = beta0 * Pn[g] + beta1 * D.P[s1][g] + beta2 * D.P[s2][g];
+      qv = beta0 * Qn[g] + beta1 * D.Q[s1][g] + beta2 * D.Q[s2][g];
+    }
+    sm.pt[e] = pv;
+    sm.qt[e] = qv;
+  }
+  __syncthreads();
+  for (int e = tid; e < S::WY * WX; e += NT) {
+    const int r = e / WX, c = e - r * WX;
+    sm.db[e] = dbar4(sm.dc[r * CXN + c], sm.dc[r * CXN + c + 1], sm.dc[(r + 1) * CXN + c],
+                     sm.dc[(r + 1) * CXN + c + 1]);
+  }
+
+  const T g = D.g, eps = D.eps, theta = D.theta;
+  // ---- phase 1: face fluxes ----------------------------------------------
+  for (int e = tid; e < TY * (TX + 1); e += NT) {
+    const int r = e / (TX + 1), f = e - r * (TX + 1);
+    const int row = (r + 2) * WX;
+    // cells L = column f + 1, R = column f + 2 of the radius-2 tile
+    const T* cw = sm.dc + (r + 2) * CXN;          // corners of the face row
+    const T* cn = sm.dc + (r + 3) * CXN;
+    const T Dl = T(0.5) * (cw[f + 1] + cn[f + 1]);  // face between L-1 and L
+    const T Df = T(0.5) * (cw[f + 2] + cn[f + 2]);  // the face
+    const T Dr = T(0.5) * (cw[f + 3] + cn[f + 3]);  // face between R and R+1
+    T wLl, wLh, wRl, wRh;
+    recon_w(sm.w[row + f], sm.w[row + f + 1], sm.w[row + f + 2], theta, Dl, Df, wLl, wLh);
+    recon_w(sm.w[row + f + 1], sm.w[row + f + 2], sm.w[row + f + 3], theta, Df, Dr, wRl, wRh);
+    const T sPL = slope(sm.p[row + f], sm.p[row + f + 1], sm.p[row + f + 2], theta);
+    const T sPR = slope(sm.p[row + f + 1], sm.p[row + f + 2], sm.p[row + f + 3], theta);
+    const T sQL = slope(sm.q[row + f], sm.q[row + f + 1], sm.q[row + f + 2], theta);
+    const T sQR = slope(sm.q[row + f + 1], sm.q[row + f + 2], sm.q[row + f + 3], theta);
+    const Side<T> L = make_side(wLh, sm.p[row + f + 1] + T(0.5) * sPL, sm.q[row + f + 1] + T(0.5) * sQL, Df, eps, g);
+    const Side<T> R = make_side(wRl, sm.p[row + f + 2] - T(0.5) * sPR, sm.q[row + f + 2] - T(0.5) * sQR, Df, eps, g);
+    T f0, fn, ft;
+    cu_flux(L, R, g, Df, f0, fn, ft);
+    sm.x.f.fx[0][e] = f0;
+    sm.x.f.fx[1][e] = fn;
+    sm.x.f.fx[2][e] = ft;
+  }
+  for (int e = tid; e < (TY + 1) * TX; e += NT) {
+    const int gy = e / TX, c = e - gy * TX;
+    const int col = c + 2;
+    // cells S = row gy + 1, N = row gy + 2 of the radius-2 tile
+    const T Ds = T(0.5) * (sm.dc[(gy + 1) * CXN + col] + sm.dc[(gy + 1) * CXN + col + 1]);
+    const T Df = T(0.5) * (sm.dc[(gy + 2) * CXN + col] + sm.dc[(gy + 2) * CXN + col + 1]);
+    const T Dn = T(0.5) * (sm.dc[(gy + 3) * CXN + col] + sm.dc[(gy + 3) * CXN + col + 1]);
+    const int r0 = gy * WX + col, r1 = r0 + WX, r2 = r1 + WX, r3 = r2 + WX;
+    T wSl, wSh, wNl, wNh;
+    recon_w(sm.w[r0], sm.w[r1], sm.w[r2], theta, Ds, Df, wSl, wSh);
+    recon_w(sm.w[r1], sm.w[r2], sm.w[r3], theta, Df, Dn, wNl, wNh);
+    const T sQS = slope(sm.q[r0], sm.q[r1], sm.q[r2], theta);
+    const T sQN = slope(sm.q[r1], sm.q[r2], sm.q[r3], theta);
+    const T sPS = slope(sm.p[r0], sm.p[r1], sm.p[r2], theta);
+    const T sPN = slope(sm.p[r1], sm.p[r2], sm.p[r3], theta);
+    // normal = Q, tangential = P
+    const Side<T> Sd = make_side(wSh, sm.q[r1] + T(0.5) * sQS, sm.p[r1] + T(0.5) * sPS, Df, eps, g);
+    const Side<T> Nd = make_side(wNl, sm.q[r2] - T(0.5) * sQN, sm.p[r2] - T(0.5) * sPN, Df, eps, g);
+    T f0, fn, ft;
+    cu_flux(Sd, Nd, g, Df, f0, fn, ft);
+    sm.x.f.fy[0][e] = f0;
+    sm.x.f.fy[1][e] = ft;   // x-momentum flux through a y-face
+    sm.x.f.fy[2][e] = fn;   // y-momentum flux through a y-face
+  }
+  __syncthreads();
+
+  // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
+  const T dx = D.dx, dy = D.dy, B = D.B, Bc = D.Bc, gn2 = D.gn2;
+  const double al0 = st->alpha[0], al1 = st->alpha[1], al2 = st->alpha[2];
+  const T a0 = (T)al0, a1 = (T)al1, a2 = (T)al2;
+  T* __restrict__ wn = D.w[(st->n + 1) & 1];
+  T* __restrict__ E0 = D.E[slot];
+  T* __restrict__ F0 = D.F[slot];
+  T* __restrict__ G0 = D.G[slot];
+  const T* __restrict__ E1 = D.E[s1];
+  const T* __restrict__ F1 = D.F[s1];
+  const T* __restrict__ G1 = D.G[s1];
+  const T* __restrict__ E2 = D.E[s2];
+  const T* __restrict__ F2 = D.F[s2];
+  const T* __restrict__ G2 = D.G[s2];
+  T ures[CPT], vres[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int e = tid + q * NT;
+    const int r = e / TX, c = e - r * TX;
+    const int i = i0 + c, j = j0 + r;
+    ures[q] = T(0);
+    vres[q] = T(0);
+    if (i >= nx || j >= ny) continue;
+    const int C0 = (r + 2) * WX + c + 2;   // radius-2 tile index of the cell
+    const int fxw = r * (TX + 1) + c, fyS = r * TX + c;
+    T e_ = -(sm.x.f.fx[0][fxw + 1] - sm.x.f.fx[0][fxw]) / dx - (sm.x.f.fy[0][fyS + TX] - sm.x.f.fy[0][fyS]) / dy;
+    T f_ = -(sm.x.f.fx[1][fxw + 1] - sm.x.f.fx[1][fxw]) / dx - (sm.x.f.fy[1][fyS + TX] - sm.x.f.fy[1][fyS]) / dy;
+    T g_ = -(sm.x.f.fx[2][fxw + 1] - sm.x.f.fx[2][fxw]) / dx - (sm.x.f.fy[2][fyS + TX] - sm.x.f.fy[2][fyS]) / dy;
+    // well-balanced bed slope source -g h b_x with h the mean of the cell's
+    // own face depths; only the departure of those depths from the face
+    // still-water depths remains once the still-water parts cancel against
+    // the pressure fluxes
+    {
+      const T* cr = sm.dc + (r + 2) * CXN + c + 2;   // corner (i, j)
+      const T Dw = T(0.5) * (cr[0] + cr[CXN]), De = T(0.5) * (cr[1] + cr[CXN + 1]);
+      const T Ds = T(0.5) * (cr[0] + cr[1]), Dn = T(0.5) * (cr[CXN] + cr[CXN + 1]);
+      T wl, wh;
+      recon_w(sm.w[C0 - 1], sm.w[C0], sm.w[C0 + 1], theta, Dw, De, wl, wh);
+      f_ += g * (De - Dw) / dx * (T(0.5) * (face_dev(wh, De) + face_dev(wl, Dw))) + shore_term(Dw, De, g) / dx;
+      recon_w(sm.w[C0 - WX], sm.w[C0], sm.w[C0 + WX], theta, Ds, Dn, wl, wh);
+      g_ += g * (Dn - Ds) / dy * (T(0.5) * (face_dev(wh, Dn) + face_dev(wl, Ds))) + shore_term(Ds, Dn, g) / dy;
+    }
+    const T Db = sm.db[C0];
+    const T d0 = dpos(Db);
+    const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
+    const T dym = dpos(sm.db[C0 - WX]), dyp = dpos(sm.db[C0 + WX]);
+    const T ddx = (dxp - dxm) / (T(2) * dx), ddy = (dyp - dym) / (T(2) * dy);
+    // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0)
+    if (d0 > T(0)) {
+#define ETA(o) (sm.w[C0 + (o)] + fmin(sm.db[C0 + (o)], T(0)))
+      const T e00 = ETA(0);
+      const T exm = ETA(-1), exp_ = ETA(1), eym = ETA(-WX), eyp = ETA(WX);
+      const T emm = ETA(-WX - 1), epm = ETA(-WX + 1), emp = ETA(WX - 1), epp = ETA(WX + 1);
+      const T exm2 = ETA(-2), exp2 = ETA(2), eym2 = ETA(-2 * WX), eyp2 = ETA(2 * WX);
+#undef ETA
+      const T exx = (exp_ - T(2) * e00 + exm) / (dx * dx);
+      const T eyy = (eyp - T(2) * e00 + eym) / (dy * dy);
+      const T exy = ((epp - epm) - (emp - emm)) / (T(4) * dx * dy);
+      const T exxx = ((exp2 - exm2) - T(2) * (exp_ - exm)) / (T(2) * dx * dx * dx);
+      const T eyyy = ((eyp2 - eym2) - T(2) * (eyp - eym)) / (T(2) * dy * dy * dy);
+      const T exyy = ((epp - T(2) * exp_ + epm) - (emp - T(2) * exm + emm)) / (T(2) * dx * dy * dy);
+      const T exxy = ((epp - T(2) * eyp + emp) - (epm - T(2) * eym + emm)) / (T(2) * dx * dx * dy);
+      const T bg = B * g * d0 * d0;
+      f_ += bg * d0 * (exxx + exyy) + bg * (ddx * (T(2) * exx + eyy) + ddy * exy);
+      g_ += bg * d0 * (eyyy + exxy) + bg * (ddy * (T(2) * eyy + exx) + ddx * exy);
+    }
+    // Manning friction f1, f2 at the cell centre
+    const T h = fmax(sm.w[C0] + Db, T(0));
+    const T Pc = sm.p[C0], Qc = sm.q[C0];
+    if (h > T(0) && gn2 > T(0)) {
+      const T u = desing(Pc, h, eps), v = desing(Qc, h, eps);
+      const T k = gn2 * sqrt(u * u + v * v) / cbrt(h);
+      f_ -= k * u;
+      g_ -= k * v;
+    }
+    // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k}) (Eq. 14-15 are linear)
+    const int B0 = (r + 1) * BX + c + 1;
+    const T qy = (sm.qt[B0 + BX] - sm.qt[B0 - BX]) / (T(2) * dy);
+    const T qx = (sm.qt[B0 + 1] - sm.qt[B0 - 1]) / (T(2) * dx);
+    const T qxy = ((sm.qt[B0 + BX + 1] - sm.qt[B0 - BX + 1]) - (sm.qt[B0 + BX - 1] - sm.qt[B0 - BX - 1])) /
+                  (T(4) * dx * dy);
+    const T py = (sm.pt[B0 + BX] - sm.pt[B0 - BX]) / (T(2) * dy);
+    const T px = (sm.pt[B0 + 1] - sm.pt[B0 - 1]) / (T(2) * dx);
+    const T pxy = ((sm.pt[B0 + BX + 1] - sm.pt[B0 - BX + 1]) - (sm.pt[B0 + BX - 1] - sm.pt[B0 - BX - 1])) /
+                  (T(4) * dx * dy);
+    const T fs = d0 * ddx * qy / T(6) + d0 * ddy * qx / T(6) + Bc * d0 * d0 * qxy;
+    const T gs = d0 * ddx * py / T(6) + d0 * ddy * px / T(6) + Bc * d0 * d0 * pxy;
+    // U*^n, V*^n: rows of Eq. (19)-(20)
+    T ax, bx, cx, ay, by, cy;
+    tri_coef(dxm, d0, dxp, dx, Bc, ax, bx, cx);
+    tri_coef(dym, d0, dyp, dy, Bc, ay, by, cy);
+    // (a + b + c = 1: written around the centre value to keep FP32 digits)
+    const T Un = Pc + (ax * (sm.p[C0 - 1] - Pc) + cx * (sm.p[C0 + 1] - Pc));
+    const T Vn = Qc + (ay * (sm.q[C0 - WX] - Qc) + cy * (sm.q[C0 + WX] - Qc));
+    (void)bx;
+    (void)by;
+    // Eq. (42)-(43)
+    const size_t ii = (size_t)j * D.ipitch + i;
+    const T e1 = E1[ii], e2 = E2[ii], f1 = F1[ii], f2 = F2[ii], g1 = G1[ii], g2 = G2[ii];
+    E0[ii] = e_;
+    F0[ii] = f_;
+    G0[ii] = g_;
+    wn[(size_t)(j + 2) * pitch + xoff + i] = sm.w[C0] + (a0 * e_ + a1 * e1 + a2 * e2);
+    ures[q] = Un + (a0 * f_ + a1 * f1 + a2 * f2) + fs;
+    vres[q] = Vn + (a0 * g_ + a1 * g1 + a2 * g2) + gs;
+  }
+  __syncthreads();  // fluxes consumed; the union now holds U*, V*
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int e = tid + q * NT;
+    sm.x.s.u[e] = ures[q];
+    sm.x.s.v[e] = vres[q];
+  }
+  __syncthreads();
+
+  // ---- phase 3: chunk-local solves of Eq. (19) (x) and Eq. (20) (y) -------
+  constexpr int NCX = TX / MX;                  // x-chunks per tile row
+  static_assert(TX % MX == 0, "chunks must tile the tile width");
+  static_assert(TY * NCX <= 64, "x-chunk solvers must fit one wave");
+  const bool wave_w = (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
+  if (tid < TY * NCX) {
+    const int r = tid / NCX, qc = tid - r * NCX;
+    const int j = j0 + r, is = i0 + qc * MX;
+    if (j < ny && is < nx) {
+      const int m = min(MX, nx - is);
+      // depths of cells is-1 .. is+m (tile columns qc*MX+1 ..)
+      T* dlx = sm.db + (r + 2) * WX + qc * MX + 1;
+      T* rhs = sm.x.s.u + r * TX + qc * MX;
+      if (is == 0 && wave_w) {
+        T a, b, c;
+        tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), dx, Bc, a, b, c);
+        rhs[0] -= a * (T)st->gP[0];   // Dirichlet ghost P_{-1}(t_{n+1})
+      }
+      chunk_solve_db<T, MX>(dlx, 1, m, dx, Bc, is == 0 && !wave_w, is + m == nx, rhs, sm.x.s.pu + r * TX + qc * MX, 1);
+      const int cgl = is / MX;
+      D.chx[(size_t)cgl * ny + j] = rhs[0];
+      D.chx[((size_t)D.cx + cgl) * ny + j] = rhs[m - 1];
+    }
+  } else if (tid >= 64 && tid < 64 + TX) {
+    const int c = tid - 64;
+    const int i = i0 + c;
+    if (i < nx && j0 < ny) {
+      const int m = min(TY, ny - j0);
+      T* dly = sm.db + WX + c + 2;        // depths of rows j0-1 .. j0+m
+      T* rhs = sm.x.s.v + c;
+      chunk_solve_db<T, TY>(dly, WX, m, dy, Bc, j0 == 0, j0 + m == ny, rhs, sm.x.s.pv + c, TX);
+      const int cgl = j0 / TY;
+      D.chy[(size_t)cgl * nx + i] = rhs[0];
+      D.chy[((size_t)D.cy + cgl) * nx + i] = rhs[(m - 1) * TX];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int e = tid + q * NT;
+    const int r = e / TX, c = e - r * TX;
+    const int i = i0 + c, j = j0 + r;
+    if (i < nx && j < ny) {
+      const size_t ii = (size_t)j * D.ipitch + i;
+      D.xhP[ii] = sm.x.s.u[e];
+      D.xhQ[ii] = sm.x.s.v[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_reduced: per line, couple the chunk-local solutions (one thread per line)
+// ---------------------------------------------------------------------------
+//
+// For chunk c with local solution xh, left spike v and right spike w, the
+// exact solution is x = xh + v * X_{e}(c-1) + w * X_{s}(c+1).  With
+// sigma_c = x_first(c) and alpha_c = x_last(c) written as affine functions
+// of x_first(c+1), a forward sweep gives
+//   sigma_c = k1 xh_s + k2 alpha_{c-1},  alpha_c = xh_e + m1 alpha_{c-1} + m2 sigma_c
+// and a backward sweep X_s(c) = sigma_c + tau_c X_s(c+1),
+// X_e(c) = alpha_c + gamma_c X_s(c+1).  (k1, k2, m1, m2, tau, gamma) are
+// static and precomputed.
+
+template <typename T>
+__device__ __forceinline__ void reduce_line(int C, int L, int line, const T* __restrict__ ch, const T* __restrict__ rs,
+                                            T* __restrict__ itf) {
+  const size_t CL = (size_t)C * L;
+  T al = T(0);
+  for (int c = 0; c < C; ++c) {
+    const size_t o = (size_t)c * L + line;
+    const T xs = ch[o], xe = ch[CL + o];
+    const T sg = rs[o] * xs + rs[CL + o] * al;
+    al = xe + rs[2 * CL + o] * al + rs[3 * CL + o] * sg;
+    itf[o] = sg;          // temporarily sigma_c, alpha_c
+    itf[CL + o] = al;
+  }
+  T xs_next = T(0);
+  for (int c = C - 1; c >= 0; --c) {
+    const size_t o = (size_t)c * L + line;
+    const T sg = itf[o], a = itf[CL + o];
+    const T Xs = sg + rs[4 * CL + o] * xs_next;
+    const T Xe = a + rs[5 * CL + o] * xs_next;
+    itf[CL + o] = xs_next;                    // right neighbour of chunk c
+    if (c + 1 < C) itf[o + L] = Xe;          // left neighbour of chunk c + 1
+    xs_next = Xs;
+    (void)Xe;
+  }
+  itf[line] = T(0);                           // chunk 0 has no left neighbour
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ doms, const int* __restrict__ line_prefix,
+                                                int nd) {
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= line_prefix[nd]) return;
+  const int dom = find_domain(line_prefix, nd, gid);
+  const DomDev<T>& D = doms[dom];
+  if (D.st->halt) return;
+  const int l = gid - line_prefix[dom];
+  if (l < D.ny) reduce_line(D.cx, D.ny, l, D.chx, D.rsx, D.ifx);
+  else reduce_line(D.cy, D.nx, l - D.ny, D.chy, D.rsy, D.ify);
+}
+
+// ---------------------------------------------------------------------------
+// k_final: spike corrections, sponge, ghost cells, CFL maximum
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void put3(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T vw, T vp, T vq) {
+  const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
+  w[g] = vw;
+  P[g] = vp;
+  Q[g] = vq;
+}
+
+template <typename T, int TY, int MX>
+__global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_prefix,
+                                             int nd) {
+  const int dom = find_domain(tile_prefix, nd, blockIdx.x);
+  const DomDev<T>& D = doms[dom];
+  DevState* st = D.st;
+  if (st->halt) return;
+  const int tile = blockIdx.x - tile_prefix[dom];
+  const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
+  const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
+  const int ns = st->slot == 2 ? 0 : st->slot + 1;    // slot of level n + 1
+  T* __restrict__ w = D.w[(st->n + 1) & 1];
+  T* __restrict__ P = D.P[ns];
+  T* __restrict__ Q = D.Q[ns];
+  const T dx = D.dx, dy = D.dy, g = D.g, eps = D.eps;
+  const double dt = st->dt;
+  double smax = 0.0;
+  constexpr int CPT = (TX * TY) / NT;
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int e = tid + q * NT;
+    const int r = e / TX, c = e - r * TX;
+    const int i = i0 + c, j = j0 + r;
+    if (i >= nx || j >= ny) continue;
+    const size_t ii = (size_t)j * D.ipitch + i;
+    const int qx = i / MX, qy = j / TY;
+    const size_t ox = (size_t)qx * ny + j, oy = (size_t)qy * nx + i;
+    const size_t CLx = (size_t)D.cx * ny, CLy = (size_t)D.cy * nx;
+    T p = D.xhP[ii] + D.spxv[ii] * D.ifx[ox] + D.spxw[ii] * D.ifx[CLx + ox];
+    T qv = D.xhQ[ii] + D.spyv[ii] * D.ify[oy] + D.spyw[ii] * D.ify[CLy + oy];
+    const size_t gidx = (size_t)(j + 2) * D.pitch + D.xoff + i;
+    T wv = w[gidx];
+    const T Db = D.Dbar[ii];
+    if (D.any_sponge && Db > T(0)) {
+      const T dist[4] = {(T(i) + T(0.5)) * dx, (T(nx - i) - T(0.5)) * dx, (T(j) + T(0.5)) * dy,
+                         (T(ny - j) - T(0.5)) * dy};
+      T sig = T(0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const T Ls = D.sponge_w[s];
+        if (D.bc[s] == SPONGE && Ls > T(0) && dist[s] < Ls) {
+          const T z = (Ls - dist[s]) / Ls;
+          sig += D.sponge_sigma * z * z;
+        }
+      }
+      if (sig > T(0)) {
+        const T fac = exp(-sig * (T)dt);
+        wv *= fac;
+        p *= fac;
+        qv *= fac;
+        w[gidx] = wv;
+      }
+    }
+    P[gidx] = p;
+    Q[gidx] = qv;
+    // Eq. (22) speeds of the new state
+    const T h = fmax(wv + Db, T(0));
+    const T u = desing(p, h, eps), v = desing(qv, h, eps);
+    const T cel = sqrt(g * h);
+    T s = fmax((fabs(u) + cel) / dx, (fabs(v) + cel) / dy);
+    double sd = (double)s;
+    if (sd != sd) sd = __longlong_as_double(0x7ff0000000000000ll);
+    smax = fmax(smax, sd);
+    // ghost cells of the new state: x sides for interior rows, then y sides
+    // for all columns (corners mirror the x-ghosts)
+    const bool xg = i < 2 || i >= nx - 2, yg = j < 2 || j >= ny - 2;
+    if (xg || yg) {
+      T gwv = wv, gpv = p, gqv = qv;
+      int gi = i;
+      bool have_x = false;
+      if (i < 2) {
+        gi = -1 - i;
+        have_x = true;
+        if (D.bc[0] == SINE || D.bc[0] == IRREGULAR) {
+          gwv = (T)st->gw[i];
+          gpv = (T)st->gP[i];
+          gqv = T(0);
+        } else {
+          gpv = -p;
+        }
+        put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
+      }
+      if (i >= nx - 2) {
+        const int gie = 2 * nx - 1 - i;
+        put3(D, w, P, Q, gie, j, wv, -p, qv);
+        if (!have_x) {
+          gi = gie;
+          gwv = wv; gpv = -p; gqv = qv;
+          have_x = true;
+        }
+      }
+      if (yg) {
+        const int gj = j < 2 ? -1 - j : 2 * ny - 1 - j;
+        put3(D, w, P, Q, i, gj, wv, p, -qv);
+        if (have_x) put3(D, w, P, Q, gi, gj, gwv, gpv, -gqv);
+      }
+    }
+  }
+  // block max -> one atomic per block
+  __shared__ double red[NT / 64];
+  for (int o = 32; o > 0; o >>= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = smax;
+  __syncthreads();
+  if (tid == 0) {
+    double m = red[0];
+    for (int k = 1; k < NT / 64; ++k) m = fmax(m, red[k]);
+    atomicMax(&st->smax_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+}  // namespace bqk

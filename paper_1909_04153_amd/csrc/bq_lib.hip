@@ -1,0 +1,994 @@
+// bq_lib.hip -- host side of libbq (C ABI in include/bq.h) plus the set-up,
+// state-transfer and diagnostic kernels.  The per-step kernels live in
+// bq_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "bq.h"
+#include "bq_kernels.hpp"
+
+using namespace bqk;
+
+// ---------------------------------------------------------------------------
+// tile configuration per precision
+// ---------------------------------------------------------------------------
+template <typename T> struct Cfg;
+template <> struct Cfg<float> {
+  static constexpr int TY = 16;
+  static constexpr int MX = 32;
+};
+template <> struct Cfg<double> {
+  static constexpr int TY = 8;
+  static constexpr int MX = 32;
+};
+
+static thread_local char g_err[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess) return fail(BQ_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+static size_t rup(size_t v, size_t a) { return (v + a - 1) / a * a; }
+static int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// set-up kernels
+// ---------------------------------------------------------------------------
+
+// corner still-water depth with two mirrored ghost layers, from io (FP64
+// (ny+1) x (nx+1) host copy)
+template <typename T>
+__global__ void k_setup_corners(const DomDev<T>* Dp) {
+  const DomDev<T>& D = *Dp;
+  const int w = D.nx + 5, h = D.ny + 5;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= w * h) return;
+  const int ic = e % w - 2, jc = e / w - 2;
+  const int mi = ic < 0 ? -ic : (ic > D.nx ? 2 * D.nx - ic : ic);
+  const int mj = jc < 0 ? -jc : (jc > D.ny ? 2 * D.ny - jc : jc);
+  D.Dc[(size_t)(jc + 2) * D.cpitch + ic + 2] = (T)D.io[(size_t)mj * (D.nx + 1) + mi];
+}
+
+template <typename T>
+__device__ __forceinline__ T corner(const DomDev<T>& D, int ic, int jc) {
+  return D.Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
+}
+
+template <typename T>
+__device__ __forceinline__ T cellD(const DomDev<T>& D, int i, int j) {
+  return dbar4(corner(D, i, j), corner(D, i + 1, j), corner(D, i, j + 1), corner(D, i + 1, j + 1));
+}
+
+template <typename T>
+__global__ void k_setup_cells(const DomDev<T>* Dp) {
+  const DomDev<T>& D = *Dp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D.nx * D.ny) return;
+  const int i = e % D.nx, j = e / D.nx;
+  D.Dbar[(size_t)j * D.ipitch + i] = cellD(D, i, j);
+}
+
+// spikes of the chunk-local systems: responses to a unit value of the
+// neighbour just left (v) and right (w) of the chunk; boundary values of the
+// spikes go to rs[0..3] (v_first, v_last, w_first, w_last)
+template <typename T, int M>
+__global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
+  const DomDev<T>& D = *Dp;
+  const int L = dir == 0 ? D.ny : D.nx;           // lines
+  const int C = dir == 0 ? D.cx : D.cy;           // chunks per line
+  const int n = dir == 0 ? D.nx : D.ny;           // unknowns per line
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L * C) return;
+  const int line = e % L, c = e / L;
+  const int s = c * M, m = min(M, n - s);
+  const T h = dir == 0 ? D.dx : D.dy;
+  T Dl[M + 2], r[M], piv[M];
+  for (int k = 0; k < m + 2; ++k) {
+    const int q = s - 1 + k;
+    Dl[k] = dir == 0 ? cellD(D, q, line) : cellD(D, line, q);
+  }
+  const bool wave_w = dir == 0 && (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
+  const bool fold_lo = s == 0 && !wave_w, fold_hi = s + m == n;
+  T a0, b0, c0, am, bm, cm;
+  tri_coef(dpos(Dl[0]), dpos(Dl[1]), dpos(Dl[2]), h, D.Bc, a0, b0, c0);
+  tri_coef(dpos(Dl[m - 1]), dpos(Dl[m]), dpos(Dl[m + 1]), h, D.Bc, am, bm, cm);
+  T* sv = dir == 0 ? D.spxv : D.spyv;
+  T* sw = dir == 0 ? D.spxw : D.spyw;
+  T* rs = dir == 0 ? D.rsx : D.rsy;
+  const size_t CL = (size_t)C * L, o = (size_t)c * L + line;
+  // left spike
+  for (int k = 0; k < m; ++k) r[k] = T(0);
+  if (c > 0) {
+    r[0] = -a0;
+    chunk_solve_db<T, M>(Dl, 1, m, h, D.Bc, fold_lo, fold_hi, r, piv, 1);
+  }
+  for (int k = 0; k < m; ++k) {
+    const int q = s + k;
+    sv[dir == 0 ? (size_t)line * D.ipitch + q : (size_t)q * D.ipitch + line] = r[k];
+  }
+  rs[o] = r[0];
+  rs[CL + o] = r[m - 1];
+  // right spike
+  for (int k = 0; k < m; ++k) r[k] = T(0);
+  if (c < C - 1) {
+    r[m - 1] = -cm;
+    chunk_solve_db<T, M>(Dl, 1, m, h, D.Bc, fold_lo, fold_hi, r, piv, 1);
+  }
+  for (int k = 0; k < m; ++k) {
+    const int q = s + k;
+    sw[dir == 0 ? (size_t)line * D.ipitch + q : (size_t)q * D.ipitch + line] = r[k];
+  }
+  rs[2 * CL + o] = r[0];
+  rs[3 * CL + o] = r[m - 1];
+}
+
+// static coefficients of the interface recurrence (see reduce_line)
+template <typename T>
+__global__ void k_setup_reduced(const DomDev<T>* Dp, int dir) {
+  const DomDev<T>& D = *Dp;
+  const int L = dir == 0 ? D.ny : D.nx;
+  const int C = dir == 0 ? D.cx : D.cy;
+  const int line = blockIdx.x * blockDim.x + threadIdx.x;
+  if (line >= L) return;
+  T* rs = dir == 0 ? D.rsx : D.rsy;
+  const size_t CL = (size_t)C * L;
+  T gprev = T(0);
+  for (int c = 0; c < C; ++c) {
+    const size_t o = (size_t)c * L + line;
+    const T vs = rs[o], ve = rs[CL + o], ws = rs[2 * CL + o], we = rs[3 * CL + o];
+    const T kap = T(1) / (T(1) - vs * gprev);
+    const T tau = kap * ws;
+    const T gam = ve * gprev * tau + we;
+    rs[o] = kap;
+    rs[CL + o] = kap * vs;
+    rs[2 * CL + o] = ve;
+    rs[3 * CL + o] = ve * gprev;
+    rs[4 * CL + o] = tau;
+    rs[5 * CL + o] = gam;
+    gprev = gam;
+  }
+}
+
+// wave numbers of the wavemaker components: the linear dispersion relation of
+// Eq. (1)-(3) on a flat bed is a quadratic in k^2,
+//   g B d^3 K^2 + (g d - w^2 (B + 1/3) d^2) K - w^2 = 0,  K = k^2,
+// with exactly one positive root; d = mean still-water depth of column 0.
+template <typename T>
+__global__ void k_setup_waves(const DomDev<T>* Dp, double B) {
+  const DomDev<T>& D = *Dp;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double dsum = 0.0;
+  for (int j = 0; j < D.ny; ++j) dsum += (double)dpos(D.Dbar[(size_t)j * D.ipitch]);
+  const double d = dsum / D.ny;
+  const int nw = D.n_waves;
+  for (int m = 0; m < nw; ++m) {
+    const double om = D.wave[nw + m];
+    double k = 0.0;
+    if (d > 0.0 && om > 0.0) {
+      const double a = D.g_d * B * d * d * d;
+      const double b = D.g_d * d - om * om * (B + 1.0 / 3.0) * d * d;
+      const double disc = sqrt(b * b + 4.0 * a * om * om);
+      const double K = b >= 0.0 ? 2.0 * om * om / (b + disc) : (disc - b) / (2.0 * a);
+      k = sqrt(K);
+    }
+    D.wave[3 * nw + m] = k;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// state transfer, ghosts and diagnostics
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__device__ void ghost_cell(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T wv, T p, T qv, const double* gw,
+                           const double* gP) {
+  const int nx = D.nx, ny = D.ny;
+  const bool yg = j < 2 || j >= ny - 2;
+  T gwv = wv, gpv = p, gqv = qv;
+  int gi = 0;
+  bool have_x = false;
+  if (i < 2) {
+    gi = -1 - i;
+    have_x = true;
+    if (D.bc[0] == SINE || D.bc[0] == IRREGULAR) {
+      gwv = (T)gw[i];
+      gpv = (T)gP[i];
+      gqv = T(0);
+    } else {
+      gpv = -p;
+    }
+    put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
+  } else if (i >= nx - 2) {
+    gi = 2 * nx - 1 - i;
+    have_x = true;
+    gpv = -p;
+    put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
+  }
+  if (yg) {
+    const int gj = j < 2 ? -1 - j : 2 * ny - 1 - j;
+    put3(D, w, P, Q, i, gj, wv, p, -qv);
+    if (have_x) put3(D, w, P, Q, gi, gj, gwv, gpv, -gqv);
+  }
+}
+
+// scatter io (FP64 interior) into level 0: which 0 = eta -> w, 1 = P, 2 = Q
+template <typename T>
+__global__ void k_scatter(const DomDev<T>* Dp, int which, int* bad) {
+  const DomDev<T>& D = *Dp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D.nx * D.ny) return;
+  const int i = e % D.nx, j = e / D.nx;
+  const double v = D.io[e];
+  const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
+  if (which == 0) {
+    const double Db = (double)D.Dbar[(size_t)j * D.ipitch + i];
+    const double d = Db > 0.0 ? Db : 0.0;
+    if (!(v + d >= 0.0)) atomicOr(bad, 1);
+    // w = h + b with h = eta + d, b = -Dbar
+    D.w[0][g] = (T)(v + d - Db);
+  } else if (which == 1) {
+    D.P[0][g] = (T)v;
+  } else {
+    D.Q[0][g] = (T)v;
+  }
+}
+
+// ghosts of level 0 at t = 0 and the CFL maximum of the initial state
+template <typename T>
+__global__ void __launch_bounds__(256) k_init_ghosts(const DomDev<T>* Dp) {
+  const DomDev<T>& D = *Dp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  double sm = 0.0;
+  if (e < D.nx * D.ny) {
+    const int i = e % D.nx, j = e / D.nx;
+    const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
+    const T wv = D.w[0][g], p = D.P[0][g], qv = D.Q[0][g];
+    ghost_cell(D, D.w[0], D.P[0], D.Q[0], i, j, wv, p, qv, D.st->gw, D.st->gP);
+    const T h = fmax(wv + D.Dbar[(size_t)j * D.ipitch + i], T(0));
+    const T u = desing(p, h, D.eps), v = desing(qv, h, D.eps);
+    const T c = sqrt(D.g * h);
+    double s = (double)fmax((fabs(u) + c) / D.dx, (fabs(v) + c) / D.dy);
+    if (s != s) s = __longlong_as_double(0x7ff0000000000000ll);
+    sm = s;
+  }
+  for (int o = 32; o > 0; o >>= 1) sm = fmax(sm, __shfl_xor(sm, o, 64));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    atomicMax(&D.st->smax_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// wavemaker ghost values at t = 0 (one block)
+template <typename T>
+__global__ void __launch_bounds__(64) k_init_waves(const DomDev<T>* Dp) {
+  const DomDev<T>& D = *Dp;
+  double gw[2], gP[2];
+  wave_ghosts(D, D.st->t, gw, gP);
+  if (threadIdx.x == 0) {
+    D.st->gw[0] = gw[0]; D.st->gw[1] = gw[1]; D.st->gP[0] = gP[0]; D.st->gP[1] = gP[1];
+  }
+}
+
+// gather the current level into io: which 0 eta, 1 P, 2 Q, 3 w
+template <typename T>
+__global__ void k_gather(const DomDev<T>* Dp, int which, int wslot, int pslot) {
+  const DomDev<T>& D = *Dp;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= D.nx * D.ny) return;
+  const int i = e % D.nx, j = e / D.nx;
+  const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
+  double v;
+  if (which == 0 || which == 3) {
+    const double wv = (double)D.w[wslot][g];
+    const double Db = (double)D.Dbar[(size_t)j * D.ipitch + i];
+    v = which == 3 ? wv : (wv + Db) - (Db > 0.0 ? Db : 0.0);
+  } else {
+    v = (double)(which == 1 ? D.P[pslot][g] : D.Q[pslot][g]);
+  }
+  D.io[e] = v;
+}
+
+// FP64 mass and energy: fixed partition and fixed-order tree (one block)
+template <typename T>
+__global__ void __launch_bounds__(256) k_diag(const DomDev<T>* Dp, int wslot, int pslot) {
+  const DomDev<T>& D = *Dp;
+  const int n = D.nx * D.ny;
+  double m = 0.0, en = 0.0;
+  for (int e = threadIdx.x; e < n; e += 256) {
+    const int i = e % D.nx, j = e / D.nx;
+    const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
+    const double Db = (double)D.Dbar[(size_t)j * D.ipitch + i];
+    const double h = (double)D.w[wslot][g] + Db;
+    const double d = Db > 0.0 ? Db : 0.0;
+    m += h;
+    double ec = 0.0;
+    if (d > 0.0) ec += 0.5 * D.g_d * (h - d) * (h - d);
+    if (h > 1e-6) {
+      const double p = (double)D.P[pslot][g], q = (double)D.Q[pslot][g];
+      ec += 0.5 * (p * p + q * q) / h;
+    }
+    en += ec;
+  }
+  __shared__ double sm[256], se[256];
+  sm[threadIdx.x] = m;
+  se[threadIdx.x] = en;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] += sm[threadIdx.x + s];
+      se[threadIdx.x] += se[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    D.st->mass = sm[0] * D.dx_d * D.dy_d;
+    D.st->energy = se[0] * D.dx_d * D.dy_d;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host objects
+// ---------------------------------------------------------------------------
+
+struct Launch {
+  // device tables of one launch group (a domain or a batch)
+  void* table = nullptr;        // DomDev<T>[nd]
+  int* tile_prefix = nullptr;   // nd + 1
+  int* line_prefix = nullptr;   // nd + 1
+  int nd = 0, tiles = 0, lines = 0;
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;          // steps per replay (0 = none)
+  int graph_built = 0;          // steps captured in `graph`
+};
+
+struct bq_domain {
+  bq_params p;
+  std::vector<double> wamp, womg, wph;
+  int precision = BQ_FP64;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int nx = 0, ny = 0;
+  DomDev<float> df;
+  DomDev<double> dd;
+  void* ddev = nullptr;         // device DomDev<T>
+  DevState* st = nullptr;
+  Launch L;                     // tables in the workspace
+  int graph_steps = 16;
+};
+
+struct bq_batch {
+  std::vector<bq_domain*> doms;
+  int precision = BQ_FP64;
+  hipStream_t stream = nullptr;
+  void* mem = nullptr;          // table + prefixes
+  size_t mem_bytes = 0;
+  Launch L;
+  int graph_steps = 16;
+};
+
+// layout of a domain in its workspace
+struct Layout {
+  size_t off_state, off_desc, off_tp, off_lp;
+  size_t off_w, off_P, off_Q, off_E, off_F, off_G;
+  size_t off_Dc, off_Dbar, off_xhP, off_xhQ, off_spxv, off_spxw, off_spyv, off_spyw;
+  size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
+  size_t ghosted, interior, total;
+  int pitch, xoff, ipitch, cpitch, cx, cy, tiles_x, tiles_y, TY, MX;
+};
+
+template <typename T>
+static Layout layout_for(const bq_params* p) {
+  Layout L{};
+  const int nx = p->nx, ny = p->ny;
+  const int A = 256 / (int)sizeof(T);
+  L.TY = Cfg<T>::TY;
+  L.MX = Cfg<T>::MX;
+  L.xoff = A;
+  L.pitch = (int)rup((size_t)A + nx + 2, (size_t)A);
+  L.ipitch = (int)rup((size_t)nx, (size_t)A);
+  L.cpitch = (int)rup((size_t)nx + 5, 64);
+  L.cx = cdiv(nx, L.MX);
+  L.cy = cdiv(ny, L.TY);
+  L.tiles_x = cdiv(nx, TX);
+  L.tiles_y = cdiv(ny, L.TY);
+  L.ghosted = (size_t)(ny + 4) * L.pitch * sizeof(T);
+  L.interior = (size_t)ny * L.ipitch * sizeof(T);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = rup(o + bytes, 256);
+    return at;
+  };
+  L.off_state = take(sizeof(DevState));
+  L.off_desc = take(sizeof(DomDev<T>));
+  L.off_tp = take(2 * sizeof(int));
+  L.off_lp = take(2 * sizeof(int));
+  L.off_w = take(2 * L.ghosted);
+  L.off_P = take(3 * L.ghosted);
+  L.off_Q = take(3 * L.ghosted);
+  L.off_E = take(3 * L.interior);
+  L.off_F = take(3 * L.interior);
+  L.off_G = take(3 * L.interior);
+  L.off_Dc = take((size_t)(ny + 5) * L.cpitch * sizeof(T));
+  L.off_Dbar = take(L.interior);
+  L.off_xhP = take(L.interior);
+  L.off_xhQ = take(L.interior);
+  L.off_spxv = take(L.interior);
+  L.off_spxw = take(L.interior);
+  L.off_spyv = take(L.interior);
+  L.off_spyw = take(L.interior);
+  L.off_chx = take(2 * (size_t)L.cx * ny * sizeof(T));
+  L.off_chy = take(2 * (size_t)L.cy * nx * sizeof(T));
+  L.off_rsx = take(6 * (size_t)L.cx * ny * sizeof(T));
+  L.off_rsy = take(6 * (size_t)L.cy * nx * sizeof(T));
+  L.off_ifx = take(2 * (size_t)L.cx * ny * sizeof(T));
+  L.off_ify = take(2 * (size_t)L.cy * nx * sizeof(T));
+  L.off_wave = take(4 * (size_t)(p->n_waves > 0 ? p->n_waves : 1) * sizeof(double));
+  L.off_io = take((size_t)(nx + 1) * (ny + 1) * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+static int check_params(const bq_params* p) {
+  if (!p) return fail(BQ_EINVAL, "params is NULL");
+  if (p->nx < 4 || p->ny < 4) return fail(BQ_EINVAL, "nx, ny must be >= 4 (got %d, %d)", p->nx, p->ny);
+  if ((double)p->nx * p->ny > 2.0e9) return fail(BQ_EINVAL, "domain too large");
+  if (!(p->dx > 0) || !(p->dy > 0)) return fail(BQ_EINVAL, "dx, dy must be > 0");
+  if (!(p->g > 0)) return fail(BQ_EINVAL, "g must be > 0");
+  if (!(p->cfl > 0) || !(p->dt_max > 0) || !(p->dt_min >= 0)) return fail(BQ_EINVAL, "bad cfl / dt_max / dt_min");
+  if (!(p->ema_alpha > 0 && p->ema_alpha <= 1)) return fail(BQ_EINVAL, "ema_alpha must be in (0, 1]");
+  if (p->fixed_dt && !(p->dt_init > 0)) return fail(BQ_EINVAL, "fixed_dt needs dt_init > 0");
+  if (!(p->theta == 0.0 || (p->theta >= 1.0 && p->theta <= 2.0))) return fail(BQ_EINVAL, "theta must be 0 or in [1, 2]");
+  for (int s = 0; s < 4; ++s) {
+    if (p->bc[s] < 0 || p->bc[s] > 3) return fail(BQ_EINVAL, "bad boundary type on side %d", s);
+    if (s > 0 && (p->bc[s] == BQ_SINE || p->bc[s] == BQ_IRREGULAR))
+      return fail(BQ_EINVAL, "wavemakers are supported on the west side only");
+  }
+  const bool wave = p->bc[0] == BQ_SINE || p->bc[0] == BQ_IRREGULAR;
+  if (p->n_waves < 0 || p->n_waves > BQ_MAX_WAVES) return fail(BQ_EINVAL, "n_waves out of range");
+  if (wave && (p->n_waves < 1 || !p->wave_amp || !p->wave_omega))
+    return fail(BQ_EINVAL, "a wavemaker needs n_waves >= 1 with amplitudes and frequencies");
+  if (p->fstar_order < 0 || p->fstar_order > 2) return fail(BQ_EINVAL, "fstar_order must be 0, 1 or 2");
+  if (p->precision != BQ_FP64 && p->precision != BQ_FP32) return fail(BQ_EINVAL, "bad precision");
+  return BQ_OK;
+}
+
+template <typename T>
+static DomDev<T>& desc(bq_domain* d);
+template <>
+DomDev<float>& desc<float>(bq_domain* d) { return d->df; }
+template <>
+DomDev<double>& desc<double>(bq_domain* d) { return d->dd; }
+
+template <typename T>
+static int create_t(bq_domain* d, const double* depth_c) {
+  const bq_params* p = &d->p;
+  const Layout Ly = layout_for<T>(p);
+  if (d->ws_bytes < Ly.total) return fail(BQ_ENOMEM, "workspace of %zu bytes, need %zu", d->ws_bytes, Ly.total);
+  char* b = d->ws;
+  DomDev<T>& D = desc<T>(d);
+  memset(&D, 0, sizeof(D));
+  D.nx = p->nx;
+  D.ny = p->ny;
+  D.pitch = Ly.pitch;
+  D.xoff = Ly.xoff;
+  D.ipitch = Ly.ipitch;
+  D.cpitch = Ly.cpitch;
+  D.cx = Ly.cx;
+  D.cy = Ly.cy;
+  D.mx = Ly.MX;
+  D.my = Ly.TY;
+  D.tiles_x = Ly.tiles_x;
+  D.tiles_y = Ly.tiles_y;
+  for (int s = 0; s < 4; ++s) {
+    D.bc[s] = p->bc[s];
+    D.sponge_w[s] = (T)p->sponge_width[s];
+    if (p->bc[s] == BQ_SPONGE && p->sponge_width[s] > 0.0 && p->sponge_sigma > 0.0) D.any_sponge = 1;
+  }
+  D.fstar_order = p->fstar_order == 1 ? 1 : 2;
+  D.fixed_dt = p->fixed_dt;
+  const bool wave = p->bc[0] == BQ_SINE || p->bc[0] == BQ_IRREGULAR;
+  D.n_waves = wave ? p->n_waves : 0;
+  D.dx = (T)p->dx;
+  D.dy = (T)p->dy;
+  D.g = (T)p->g;
+  D.B = (T)p->B;
+  D.Bc = (T)(p->B + 1.0 / 3.0);
+  D.gn2 = (T)(p->g * p->manning_n * p->manning_n);
+  D.theta = (T)p->theta;
+  const double eps = p->eps_desing > 0 ? p->eps_desing : fmax(pow(p->dx, 4), pow(p->dy, 4));
+  D.eps = (T)eps;
+  D.sponge_sigma = (T)p->sponge_sigma;
+  D.dx_d = p->dx;
+  D.dy_d = p->dy;
+  D.g_d = p->g;
+  D.cfl = p->cfl;
+  D.ema_alpha = p->ema_alpha;
+  D.dt_init = p->dt_init;
+  D.dt_max = p->dt_max;
+  D.dt_min = p->dt_min;
+  D.wave_ramp = p->wave_ramp;
+  D.t_end = p->t_end;
+  for (int k = 0; k < 2; ++k) D.w[k] = (T*)(b + Ly.off_w + k * Ly.ghosted);
+  for (int k = 0; k < 3; ++k) {
+    D.P[k] = (T*)(b + Ly.off_P + k * Ly.ghosted);
+    D.Q[k] = (T*)(b + Ly.off_Q + k * Ly.ghosted);
+    D.E[k] = (T*)(b + Ly.off_E + k * Ly.interior);
+    D.F[k] = (T*)(b + Ly.off_F + k * Ly.interior);
+    D.G[k] = (T*)(b + Ly.off_G + k * Ly.interior);
+  }
+  D.Dc = (T*)(b + Ly.off_Dc);
+  D.Dbar = (T*)(b + Ly.off_Dbar);
+  D.xhP = (T*)(b + Ly.off_xhP);
+  D.xhQ = (T*)(b + Ly.off_xhQ);
+  D.spxv = (T*)(b + Ly.off_spxv);
+  D.spxw = (T*)(b + Ly.off_spxw);
+  D.spyv = (T*)(b + Ly.off_spyv);
+  D.spyw = (T*)(b + Ly.off_spyw);
+  D.chx = (T*)(b + Ly.off_chx);
+  D.chy = (T*)(b + Ly.off_chy);
+  D.rsx = (T*)(b + Ly.off_rsx);
+  D.rsy = (T*)(b + Ly.off_rsy);
+  D.ifx = (T*)(b + Ly.off_ifx);
+  D.ify = (T*)(b + Ly.off_ify);
+  D.wave = (double*)(b + Ly.off_wave);
+  D.io = (double*)(b + Ly.off_io);
+  D.st = (DevState*)(b + Ly.off_state);
+  d->st = D.st;
+  d->ddev = b + Ly.off_desc;
+  hipStream_t s = d->stream;
+  HIPCHK(hipMemsetAsync(d->ws, 0, Ly.total, s));
+  HIPCHK(hipMemcpyAsync(d->ddev, &D, sizeof(D), hipMemcpyHostToDevice, s));
+  // tables of the single-domain launch group
+  d->L.table = d->ddev;
+  d->L.tile_prefix = (int*)(b + Ly.off_tp);
+  d->L.line_prefix = (int*)(b + Ly.off_lp);
+  d->L.nd = 1;
+  d->L.tiles = Ly.tiles_x * Ly.tiles_y;
+  d->L.lines = p->nx + p->ny;
+  const int tp[2] = {0, d->L.tiles}, lp[2] = {0, d->L.lines};
+  HIPCHK(hipMemcpyAsync(d->L.tile_prefix, tp, sizeof(tp), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d->L.line_prefix, lp, sizeof(lp), hipMemcpyHostToDevice, s));
+  if (D.n_waves > 0) {
+    std::vector<double> wv(4 * (size_t)D.n_waves, 0.0);
+    for (int m = 0; m < D.n_waves; ++m) {
+      wv[m] = d->wamp[m];
+      wv[D.n_waves + m] = d->womg[m];
+      wv[2 * D.n_waves + m] = d->wph[m];
+    }
+    HIPCHK(hipMemcpyAsync(D.wave, wv.data(), wv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  const size_t nc = (size_t)(p->nx + 1) * (p->ny + 1);
+  HIPCHK(hipMemcpyAsync(D.io, depth_c, nc * sizeof(double), hipMemcpyHostToDevice, s));
+  const DomDev<T>* Dd = (const DomDev<T>*)d->ddev;
+  const int ncorn = (p->nx + 5) * (p->ny + 5);
+  k_setup_corners<T><<<cdiv(ncorn, 256), 256, 0, s>>>(Dd);
+  k_setup_cells<T><<<cdiv(p->nx * p->ny, 256), 256, 0, s>>>(Dd);
+  k_setup_spikes<T, Cfg<T>::MX><<<cdiv(p->ny * Ly.cx, 64), 64, 0, s>>>(Dd, 0);
+  k_setup_spikes<T, Cfg<T>::TY><<<cdiv(p->nx * Ly.cy, 64), 64, 0, s>>>(Dd, 1);
+  k_setup_reduced<T><<<cdiv(p->ny, 64), 64, 0, s>>>(Dd, 0);
+  k_setup_reduced<T><<<cdiv(p->nx, 64), 64, 0, s>>>(Dd, 1);
+  if (D.n_waves > 0) k_setup_waves<T><<<1, 64, 0, s>>>(Dd, p->B);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  return BQ_OK;
+}
+
+template <typename T>
+static int set_state_t(bq_domain* d, const double* eta, const double* P, const double* Q) {
+  DomDev<T>& D = desc<T>(d);
+  const DomDev<T>* Dd = (const DomDev<T>*)d->ddev;
+  hipStream_t s = d->stream;
+  const size_t n = (size_t)d->nx * d->ny;
+  const Layout Ly = layout_for<T>(&d->p);
+  // clear all levels and histories
+  HIPCHK(hipMemsetAsync(d->ws + Ly.off_w, 0, Ly.off_Dc - Ly.off_w, s));
+  int* flag = (int*)((char*)D.io + n * sizeof(double));
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), s));
+  const double* src[3] = {eta, P, Q};
+  for (int k = 0; k < 3; ++k) {
+    HIPCHK(hipMemcpyAsync(D.io, src[k], n * sizeof(double), hipMemcpyHostToDevice, s));
+    k_scatter<T><<<cdiv((int)n, 256), 256, 0, s>>>(Dd, k, flag);
+  }
+  DevState h;
+  memset(&h, 0, sizeof(h));
+  HIPCHK(hipMemcpyAsync(d->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
+  if (D.n_waves > 0) k_init_waves<T><<<1, 64, 0, s>>>(Dd);
+  k_init_ghosts<T><<<cdiv((int)n, 256), 256, 0, s>>>(Dd);
+  HIPCHK(hipGetLastError());
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hflag) {
+    // leave a consistent lake-at-rest-free state: mark as failed
+    h.status = BQ_EINVAL;
+    HIPCHK(hipMemcpy(d->st, &h, sizeof(h), hipMemcpyHostToDevice));
+    return fail(BQ_EINVAL, "eta < -d (negative depth) in the initial state");
+  }
+  return BQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stepping
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void enqueue_step(const Launch& L, hipStream_t s, double dt_prescribed) {
+  constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
+  const DomDev<T>* tab = (const DomDev<T>*)L.table;
+  k_dt<T><<<L.nd, 64, 0, s>>>(tab, dt_prescribed);
+  k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+  k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_prefix, L.nd);
+  k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+}
+
+template <typename T>
+static void enqueue_commit(const Launch& L, hipStream_t s) {
+  k_commit<T><<<cdiv(L.nd, 64), 64, 0, s>>>((const DomDev<T>*)L.table, L.nd);
+}
+
+template <typename T>
+static int run_steps(Launch& L, hipStream_t s, int n_steps, int graph_steps) {
+  if (n_steps <= 0) return BQ_OK;
+  int left = n_steps;
+  if (graph_steps > 0 && n_steps >= graph_steps) {
+    if (L.graph && L.graph_built != graph_steps) {
+      HIPCHK(hipGraphExecDestroy(L.graph));
+      L.graph = nullptr;
+    }
+    if (!L.graph) {
+      hipGraph_t g;
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int k = 0; k < graph_steps; ++k) enqueue_step<T>(L, s, 0.0);
+      HIPCHK(hipStreamEndCapture(s, &g));
+      HIPCHK(hipGraphInstantiate(&L.graph, g, nullptr, nullptr, 0));
+      HIPCHK(hipGraphDestroy(g));
+      L.graph_built = graph_steps;
+    }
+    while (left >= graph_steps) {
+      HIPCHK(hipGraphLaunch(L.graph, s));
+      left -= graph_steps;
+    }
+  }
+  for (int k = 0; k < left; ++k) enqueue_step<T>(L, s, 0.0);
+  enqueue_commit<T>(L, s);
+  HIPCHK(hipGetLastError());
+  return BQ_OK;
+}
+
+template <typename T>
+static int step_dt_t(bq_domain* d, double dt) {
+  enqueue_step<T>(d->L, d->stream, dt);
+  enqueue_commit<T>(d->L, d->stream);
+  HIPCHK(hipGetLastError());
+  return BQ_OK;
+}
+
+template <typename T>
+static int sync_t(bq_domain* d, bq_info* out) {
+  DevState h;
+  HIPCHK(hipMemcpyAsync(&h, d->st, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  if (out) {
+    k_diag<T><<<1, 256, 0, d->stream>>>((const DomDev<T>*)d->ddev, (int)(h.n & 1), (int)(h.n % 3));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&h, d->st, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+    HIPCHK(hipStreamSynchronize(d->stream));
+    out->t = h.t;
+    out->n = h.n;
+    out->dt_last = h.dt1;
+    out->dt_prev1 = h.dt2;
+    out->dt_prev2 = h.dt3;
+    out->smax = __builtin_bit_cast(double, h.smax_bits);
+    out->mass = h.mass;
+    out->energy = h.energy;
+    out->status = h.status;
+  }
+  return h.status;
+}
+
+template <typename T>
+static int read_t(bq_domain* d, int which, double* out) {
+  DevState h;
+  HIPCHK(hipMemcpyAsync(&h, d->st, sizeof(h), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  const int n = d->nx * d->ny;
+  k_gather<T><<<cdiv(n, 256), 256, 0, d->stream>>>((const DomDev<T>*)d->ddev, which, (int)(h.n & 1),
+                                                  (int)(h.n % 3));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(out, desc<T>(d).io, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return BQ_OK;
+}
+
+// checkpoint: header + DevState + w, P, Q, E, F, G regions (the dynamic state)
+struct CkptHeader {
+  uint64_t magic;
+  int32_t nx, ny, precision, version;
+  uint64_t state_bytes, field_bytes;
+};
+static const uint64_t CKPT_MAGIC = 0x42515354'45503031ull;
+
+template <typename T>
+static size_t ckpt_bytes(const bq_domain* d) {
+  const Layout Ly = layout_for<T>(&d->p);
+  return sizeof(CkptHeader) + sizeof(DevState) + (Ly.off_Dc - Ly.off_w);
+}
+
+template <typename T>
+static int save_t(bq_domain* d, void* host, size_t* bytes) {
+  const size_t need = ckpt_bytes<T>(d);
+  if (!host) {
+    *bytes = need;
+    return BQ_OK;
+  }
+  if (*bytes < need) return fail(BQ_EINVAL, "checkpoint buffer of %zu bytes, need %zu", *bytes, need);
+  const Layout Ly = layout_for<T>(&d->p);
+  CkptHeader hd{CKPT_MAGIC, d->nx, d->ny, d->precision, 1, sizeof(DevState), Ly.off_Dc - Ly.off_w};
+  char* o = (char*)host;
+  memcpy(o, &hd, sizeof(hd));
+  HIPCHK(hipMemcpyAsync(o + sizeof(hd), d->st, sizeof(DevState), hipMemcpyDeviceToHost, d->stream));
+  HIPCHK(hipMemcpyAsync(o + sizeof(hd) + sizeof(DevState), d->ws + Ly.off_w, hd.field_bytes, hipMemcpyDeviceToHost,
+                        d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  *bytes = need;
+  return BQ_OK;
+}
+
+template <typename T>
+static int load_t(bq_domain* d, const void* host, size_t bytes) {
+  const Layout Ly = layout_for<T>(&d->p);
+  CkptHeader hd;
+  if (bytes < sizeof(hd)) return fail(BQ_EINVAL, "checkpoint too small");
+  memcpy(&hd, host, sizeof(hd));
+  if (hd.magic != CKPT_MAGIC || hd.nx != d->nx || hd.ny != d->ny || hd.precision != d->precision ||
+      hd.state_bytes != sizeof(DevState) || hd.field_bytes != Ly.off_Dc - Ly.off_w ||
+      bytes < ckpt_bytes<T>(d))
+    return fail(BQ_EINVAL, "checkpoint does not match this domain");
+  const char* o = (const char*)host;
+  HIPCHK(hipMemcpyAsync(d->st, o + sizeof(hd), sizeof(DevState), hipMemcpyHostToDevice, d->stream));
+  HIPCHK(hipMemcpyAsync(d->ws + Ly.off_w, o + sizeof(hd) + sizeof(DevState), hd.field_bytes, hipMemcpyHostToDevice,
+                        d->stream));
+  HIPCHK(hipStreamSynchronize(d->stream));
+  return BQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static int batch_build_t(bq_batch* b) {
+  const int nd = (int)b->doms.size();
+  std::vector<DomDev<T>> tab(nd);
+  std::vector<int> tp(nd + 1), lp(nd + 1);
+  tp[0] = lp[0] = 0;
+  for (int k = 0; k < nd; ++k) {
+    tab[k] = desc<T>(b->doms[k]);
+    tp[k + 1] = tp[k] + tab[k].tiles_x * tab[k].tiles_y;
+    lp[k + 1] = lp[k] + tab[k].nx + tab[k].ny;
+  }
+  const size_t tb = rup(sizeof(DomDev<T>) * (size_t)nd, 256), pb = rup(sizeof(int) * (size_t)(nd + 1), 256);
+  const size_t need = tb + 2 * pb;
+  if (need > b->mem_bytes) {
+    if (b->mem) HIPCHK(hipFree(b->mem));
+    b->mem = nullptr;
+    HIPCHK(hipMalloc(&b->mem, need));
+    b->mem_bytes = need;
+  }
+  char* m = (char*)b->mem;
+  HIPCHK(hipMemcpyAsync(m, tab.data(), sizeof(DomDev<T>) * nd, hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipMemcpyAsync(m + tb, tp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipMemcpyAsync(m + tb + pb, lp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (b->L.graph) {
+    HIPCHK(hipGraphExecDestroy(b->L.graph));
+    b->L.graph = nullptr;
+    b->L.graph_built = 0;
+  }
+  b->L.table = m;
+  b->L.tile_prefix = (int*)(m + tb);
+  b->L.line_prefix = (int*)(m + tb + pb);
+  b->L.nd = nd;
+  b->L.tiles = tp[nd];
+  b->L.lines = lp[nd];
+  return BQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+#define DISPATCH(prec, fn, ...) ((prec) == BQ_FP32 ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
+
+extern "C" {
+
+int bq_abi_version(void) { return BQ_ABI_VERSION; }
+
+const char* bq_last_error(void) { return g_err; }
+
+void bq_params_default(bq_params* p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->g = 9.81;
+  p->B = 1.0 / 15.0;
+  p->cfl = 0.2;
+  p->ema_alpha = 0.1;
+  p->dt_max = 1.0;
+  p->dt_min = 1e-9;
+  p->theta = 1.3;
+  p->fstar_order = 2;
+  p->precision = BQ_FP64;
+}
+
+int bq_workspace_bytes(const bq_params* p, size_t* bytes) {
+  const int rc = check_params(p);
+  if (rc) return rc;
+  if (!bytes) return fail(BQ_EINVAL, "bytes is NULL");
+  *bytes = p->precision == BQ_FP32 ? layout_for<float>(p).total : layout_for<double>(p).total;
+  return BQ_OK;
+}
+
+int bq_domain_create(const bq_params* p, const double* depth_c, void* dev_workspace, size_t bytes, void* hip_stream,
+                     bq_domain** out) {
+  int rc = check_params(p);
+  if (rc) return rc;
+  if (!depth_c || !dev_workspace || !out) return fail(BQ_EINVAL, "NULL argument");
+  if (((uintptr_t)dev_workspace) % 256 != 0) return fail(BQ_EINVAL, "workspace must be 256-byte aligned");
+  bq_domain* d = new (std::nothrow) bq_domain();
+  if (!d) return fail(BQ_EINVAL, "out of host memory");
+  d->p = *p;
+  const bool wave = p->bc[0] == BQ_SINE || p->bc[0] == BQ_IRREGULAR;
+  if (wave) {
+    d->wamp.assign(p->wave_amp, p->wave_amp + p->n_waves);
+    d->womg.assign(p->wave_omega, p->wave_omega + p->n_waves);
+    d->wph.assign(p->n_waves, 0.0);
+    if (p->wave_phase) d->wph.assign(p->wave_phase, p->wave_phase + p->n_waves);
+  }
+  d->p.wave_amp = d->p.wave_omega = d->p.wave_phase = nullptr;
+  d->precision = p->precision;
+  d->stream = (hipStream_t)hip_stream;
+  d->ws = (char*)dev_workspace;
+  d->ws_bytes = bytes;
+  d->nx = p->nx;
+  d->ny = p->ny;
+  rc = DISPATCH(d->precision, create_t, d, depth_c);
+  if (rc) {
+    delete d;
+    return rc;
+  }
+  // lake at rest
+  std::vector<double> z((size_t)p->nx * p->ny, 0.0);
+  rc = bq_set_state(d, z.data(), z.data(), z.data());
+  if (rc) {
+    delete d;
+    return rc;
+  }
+  *out = d;
+  return BQ_OK;
+}
+
+int bq_domain_free(bq_domain* d) {
+  if (!d) return fail(BQ_EINVAL, "NULL domain");
+  if (d->L.graph) (void)hipGraphExecDestroy(d->L.graph);
+  delete d;
+  return BQ_OK;
+}
+
+int bq_set_state(bq_domain* d, const double* eta, const double* P, const double* Q) {
+  if (!d || !eta || !P || !Q) return fail(BQ_EINVAL, "NULL argument");
+  return DISPATCH(d->precision, set_state_t, d, eta, P, Q);
+}
+
+int bq_step(bq_domain* d, int32_t n_steps) {
+  if (!d) return fail(BQ_EINVAL, "NULL domain");
+  if (n_steps < 0) return fail(BQ_EINVAL, "n_steps < 0");
+  return DISPATCH(d->precision, run_steps, d->L, d->stream, n_steps, d->graph_steps);
+}
+
+int bq_step_dt(bq_domain* d, double dt) {
+  if (!d) return fail(BQ_EINVAL, "NULL domain");
+  if (!(dt > 0.0)) return fail(BQ_EINVAL, "dt must be > 0");
+  return DISPATCH(d->precision, step_dt_t, d, dt);
+}
+
+int bq_sync(bq_domain* d, bq_info* out) {
+  if (!d) return fail(BQ_EINVAL, "NULL domain");
+  return DISPATCH(d->precision, sync_t, d, out);
+}
+
+int bq_read(bq_domain* d, int32_t which, double* host_out) {
+  if (!d || !host_out) return fail(BQ_EINVAL, "NULL argument");
+  if (which < 0 || which > 3) return fail(BQ_EINVAL, "which must be 0..3");
+  return DISPATCH(d->precision, read_t, d, which, host_out);
+}
+
+int bq_save(bq_domain* d, void* host, size_t* bytes) {
+  if (!d || !bytes) return fail(BQ_EINVAL, "NULL argument");
+  return DISPATCH(d->precision, save_t, d, host, bytes);
+}
+
+int bq_load(bq_domain* d, const void* host, size_t bytes) {
+  if (!d || !host) return fail(BQ_EINVAL, "NULL argument");
+  return DISPATCH(d->precision, load_t, d, host, bytes);
+}
+
+int bq_set_graph_steps(bq_domain* d, int32_t steps) {
+  if (!d || steps < 0) return fail(BQ_EINVAL, "bad argument");
+  d->graph_steps = steps;
+  return BQ_OK;
+}
+
+int bq_batch_create(bq_domain* const* doms, int32_t n, void* hip_stream, bq_batch** out) {
+  if (!out) return fail(BQ_EINVAL, "NULL argument");
+  bq_batch* b = new (std::nothrow) bq_batch();
+  if (!b) return fail(BQ_EINVAL, "out of host memory");
+  b->stream = (hipStream_t)hip_stream;
+  const int rc = bq_batch_set(b, doms, n);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return BQ_OK;
+}
+
+int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n) {
+  if (!b || n < 1 || !doms) return fail(BQ_EINVAL, "a batch needs at least one domain");
+  const int prec = doms[0]->precision;
+  for (int k = 0; k < n; ++k) {
+    if (!doms[k]) return fail(BQ_EINVAL, "NULL domain in batch");
+    if (doms[k]->precision != prec) return fail(BQ_EINVAL, "batch members must share one precision");
+  }
+  b->doms.assign(doms, doms + n);
+  b->precision = prec;
+  return DISPATCH(prec, batch_build_t, b);
+}
+
+int bq_batch_step(bq_batch* b, int32_t n_steps) {
+  if (!b) return fail(BQ_EINVAL, "NULL batch");
+  if (n_steps < 0) return fail(BQ_EINVAL, "n_steps < 0");
+  return DISPATCH(b->precision, run_steps, b->L, b->stream, n_steps, b->graph_steps);
+}
+
+int bq_batch_sync(bq_batch* b) {
+  if (!b) return fail(BQ_EINVAL, "NULL batch");
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return BQ_OK;
+}
+
+int bq_batch_set_graph_steps(bq_batch* b, int32_t steps) {
+  if (!b || steps < 0) return fail(BQ_EINVAL, "bad argument");
+  b->graph_steps = steps;
+  return BQ_OK;
+}
+
+int bq_batch_free(bq_batch* b) {
+  if (!b) return fail(BQ_EINVAL, "NULL batch");
+  if (b->L.graph) (void)hipGraphExecDestroy(b->L.graph);
+  if (b->mem) (void)hipFree(b->mem);
+  delete b;
+  return BQ_OK;
+}
+
+}  // extern "C"
