@@ -1,0 +1,175 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the HIP time step on one MI355X.
+
+Default workload: 64 seeded domains of uneven size (256..1536 x 256..512
+cells, C1-type solitary waves on a flat bed and C2-type sloping beaches under
+a sine wavemaker) advanced together in FP32, one launch per kernel per step,
+steps replayed from hipGraphs.  A step is one time step of every domain:
+Delta t from the CFL maximum, fluxes, dispersion, friction, AB3 update, both
+tridiagonal line solves, boundary ghosts.
+
+Prints one JSON line: Gcell-steps/s (interior cells x steps / s), the HBM
+roofline of the dominant kernel (algorithmic bytes / its mean duration, HIP
+events on the launch stream), the single-domain FP64 rates, and the CPU
+oracle's rate on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "Gcell-steps/s + % HBM peak (FP32 batched vs FP64 plain); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per interior cell and step, per kernel (field words x
+# word size): the stencil/update kernel reads w, P^{n,n-1,n-2}, Q^{n,n-1,n-2},
+# the bed and E/F/G^{n-1,n-2} (14 words) and writes E/F/G^n, w^{n+1} and the
+# two line-solve right-hand sides (6 words); the finalize kernel reads the two
+# right-hand sides and writes P^{n+1}, Q^{n+1} (4 words); 24 words in all.
+WORDS = {"k_dt": 0, "k_rhs": 20, "k_reduced": 0, "k_final": 4}
+WORDS_STEP = 24
+
+
+def workload(name):
+    from paper_1909_04153_amd import scenarios as S
+
+    if name == "batch64":
+        return S.batch_mix(64, seed=190904154), "fp32"
+    if name == "beach1024x256":
+        return [S.sloping_beach()], "fp32"
+    if name == "beach1024x256_fp64":
+        return [S.sloping_beach()], "fp64"
+    if name == "rip2048":
+        return [S.rip_beach(cfl=0.125, fstar_order=1)], "fp32"
+    if name == "solitary200x20":
+        return [S.solitary_flat()], "fp64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def make_group(bq, specs, dtype):
+    prec = bq.FP32 if dtype == "fp32" else bq.FP64
+    doms = [bq.domain_from_spec(s, precision=prec) for s in specs]
+    if len(doms) == 1:
+        return doms, doms[0]
+    return doms, bq.Batch(doms)
+
+
+def timed(torch, group, steps, warmup):
+    group.step(warmup)
+    group.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    group.step(steps)
+    group.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(specs, budget_s):
+    """the oracle as it stands, one host core, on a bounded sample"""
+    from oracle.oracle import OracleDomain
+
+    done_cells = 0
+    used = 0.0
+    names = []
+    for s in specs:
+        o = OracleDomain(s["params"], s["depth_c"])
+        o.set_state(s["eta"], s["P"], s["Q"])
+        n = s["params"]["nx"] * s["params"]["ny"]
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            rc = o.step(1)
+            steps += 1
+            el = time.perf_counter() - t0
+            if rc != 0 or el > budget_s / 4 or used + el > budget_s:
+                break
+        used += el
+        done_cells += n * steps
+        names.append(f"{s['name']} x {steps} steps")
+        o.close()
+        if used >= budget_s:
+            break
+    return done_cells / used, used, names
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="batch64")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "domains are independent, so a multi-GPU run is one such process per GPU", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1909_04153_amd import bq
+
+    bq.load()
+    specs, dtype = workload(args.workload)
+    cells = sum(s["params"]["nx"] * s["params"]["ny"] for s in specs)
+    doms, group = make_group(bq, specs, dtype)
+    el = timed(torch, group, args.steps, args.warmup)
+    value = cells * args.steps / el / 1e9
+    ms_step = el / args.steps * 1e3
+    for d in doms:
+        st = d.sync().status
+        if st != 0:
+            raise SystemExit(f"domain {d.params} latched status {st}")
+    # per-kernel durations with HIP events (plain launches, same stream)
+    kms = group.profile(args.profile_steps)
+    dom_k = max(kms, key=kms.get)
+    wsize = 4 if dtype == "fp32" else 8
+    achieved = WORDS[dom_k] * wsize * cells / (kms[dom_k] * 1e-3) / 1e9 if WORDS[dom_k] else None
+    roof = {"bound": "hbm", "kernel": dom_k, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+            "algorithmic_bytes_per_cell": WORDS[dom_k] * wsize, "cells_per_launch": cells,
+            "mean_ms": kms[dom_k]}
+    out = {"metric": METRIC, "value": value, "unit": "Gcell-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+           "config": {"workload": args.workload, "domains": len(specs), "cells": cells,
+                      "graph_steps": 16, "precision": dtype},
+           "effective_hbm_frac": WORDS_STEP * wsize * cells * args.steps / el / 1e9 / HBM_PEAK_GBS,
+           "kernels_ms": kms, "roofline": roof}
+    del group, doms
+    torch.cuda.synchronize()
+    if not args.no_fp64:
+        fp64 = {}
+        for wl in ("beach1024x256_fp64", "solitary200x20"):
+            sp, dt_ = workload(wl)
+            ds, g = make_group(bq, sp, dt_)
+            c = sum(s["params"]["nx"] * s["params"]["ny"] for s in sp)
+            n = max(20, args.steps)
+            e = timed(torch, g, n, args.warmup)
+            fp64[wl] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / n * 1e3,
+                        "cells": c, "steps": n}
+            del g, ds
+        out["fp64_plain"] = fp64
+    if not args.no_cpu_baseline:
+        rate, used, names = cpu_baseline(specs, args.cpu_seconds)
+        out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-steps/s", "cores": 1, "kind": "oracle",
+                               "seconds": used, "sample": "; ".join(names),
+                               "host_cpus": os.cpu_count()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

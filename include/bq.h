@@ -160,6 +160,13 @@ int bq_batch_step(bq_batch* b, int32_t n_steps);
 int bq_batch_sync(bq_batch* b);
 int bq_batch_free(bq_batch* b);
 
+/* Timing of the step's four kernels (Delta t, stencil + AB3 + local solves,
+ * line coupling, finalize): runs n_steps plain launches with hipEvents around
+ * every kernel on the launch stream and returns the mean duration of each in
+ * ms_out[4].  The steps advance the state like bq_step / bq_batch_step. */
+int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out);
+int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
+
 /* Number of steps captured per hipGraph replay (0 = plain launches). */
 int bq_set_graph_steps(bq_domain* d, int32_t steps);
 int bq_batch_set_graph_steps(bq_batch* b, int32_t steps);

@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
 EXPORTS = ["bq_abi_version", "bq_last_error", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
            "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
            "bq_batch_create", "bq_batch_set", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
-           "bq_set_graph_steps", "bq_batch_set_graph_steps"]
+           "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps"]
+KERNELS = ("k_dt", "k_rhs", "k_reduced", "k_final")
 
 _lib = None
 
@@ -90,6 +91,8 @@ def load(path: str | None = None):
     L.bq_batch_free.argtypes = [vp]
     L.bq_set_graph_steps.argtypes = [vp, ip]
     L.bq_batch_set_graph_steps.argtypes = [vp, ip]
+    L.bq_profile_steps.argtypes = [vp, ip, dp]
+    L.bq_batch_profile_steps.argtypes = [vp, ip, dp]
     if L.bq_abi_version() != 1:
         raise RuntimeError("libbq ABI version mismatch")
     if path is None:
@@ -174,7 +177,8 @@ class Domain:
         p, keep = make_params(params, precision)
         nbytes = workspace_bytes(params, precision)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        # a stream of its own (default priority) so steps can be graph-captured
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.workspace.device)
         dc = np.ascontiguousarray(depth_c, dtype=np.float64)
         if dc.shape != (self.ny + 1, self.nx + 1):
             raise ValueError(f"depth_c must be ({self.ny + 1}, {self.nx + 1}), got {dc.shape}")
@@ -190,6 +194,7 @@ class Domain:
 
     def close(self):
         if getattr(self, "_h", None):
+            self.stream.synchronize()   # no work may still use the workspace
             load().bq_domain_free(self._h)
             self._h = None
 
@@ -219,6 +224,12 @@ class Domain:
             _check(rc)
         return StepInfo(i.t, i.n, i.dt_last, i.dt_prev1, i.dt_prev2, i.smax, i.mass, i.energy, i.status)
 
+    def profile(self, n: int) -> dict:
+        """advance n steps with HIP events around each kernel; mean ms per kernel"""
+        out = np.zeros(4)
+        _check(load().bq_profile_steps(self._h, int(n), _dptr(out)))
+        return dict(zip(KERNELS, out.tolist()))
+
     def read(self, which: str) -> np.ndarray:
         idx = {"eta": 0, "P": 1, "Q": 2, "w": 3}[which]
         out = np.zeros((self.ny, self.nx))
@@ -243,7 +254,7 @@ class Batch:
     def __init__(self, domains, stream=None):
         torch = _torch()
         self.domains = list(domains)
-        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = stream if stream is not None else torch.cuda.Stream()
         arr = (ctypes.c_void_p * len(self.domains))(*[d.handle for d in self.domains])
         h = ctypes.c_void_p()
         _check(load().bq_batch_create(arr, len(self.domains), ctypes.c_void_p(self.stream.cuda_stream),
@@ -261,11 +272,17 @@ class Batch:
     def sync(self):
         _check(load().bq_batch_sync(self._h))
 
+    def profile(self, n: int) -> dict:
+        out = np.zeros(4)
+        _check(load().bq_batch_profile_steps(self._h, int(n), _dptr(out)))
+        return dict(zip(KERNELS, out.tolist()))
+
     def set_graph_steps(self, k: int):
         _check(load().bq_batch_set_graph_steps(self._h, int(k)))
 
     def close(self):
         if getattr(self, "_h", None):
+            self.stream.synchronize()
             load().bq_batch_free(self._h)
             self._h = None
 

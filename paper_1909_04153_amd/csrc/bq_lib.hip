@@ -651,7 +651,8 @@ template <typename T>
 static int run_steps(Launch& L, hipStream_t s, int n_steps, int graph_steps) {
   if (n_steps <= 0) return BQ_OK;
   int left = n_steps;
-  if (graph_steps > 0 && n_steps >= graph_steps) {
+  // graphs cannot be captured on the legacy null stream
+  if (graph_steps > 0 && s != nullptr && n_steps >= graph_steps) {
     if (L.graph && L.graph_built != graph_steps) {
       HIPCHK(hipGraphExecDestroy(L.graph));
       L.graph = nullptr;
@@ -673,6 +674,40 @@ static int run_steps(Launch& L, hipStream_t s, int n_steps, int graph_steps) {
   for (int k = 0; k < left; ++k) enqueue_step<T>(L, s, 0.0);
   enqueue_commit<T>(L, s);
   HIPCHK(hipGetLastError());
+  return BQ_OK;
+}
+
+template <typename T>
+static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
+  constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
+  const DomDev<T>* tab = (const DomDev<T>*)L.table;
+  hipEvent_t ev[5];
+  for (int k = 0; k < 5; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  double acc[4] = {0, 0, 0, 0};
+  int rc = BQ_OK;
+  for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
+    if (hipEventRecord(ev[0], s) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventRecord"); break; }
+    k_dt<T><<<L.nd, 64, 0, s>>>(tab, 0.0);
+    (void)hipEventRecord(ev[1], s);
+    k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+    (void)hipEventRecord(ev[2], s);
+    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_prefix, L.nd);
+    (void)hipEventRecord(ev[3], s);
+    k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+    (void)hipEventRecord(ev[4], s);
+    if (hipEventSynchronize(ev[4]) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventSynchronize"); break; }
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      acc[k] += ms;
+    }
+  }
+  enqueue_commit<T>(L, s);
+  for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+  if (rc) return rc;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  for (int k = 0; k < 4; ++k) ms_out[k] = n_steps > 0 ? acc[k] / n_steps : 0.0;
   return BQ_OK;
 }
 
@@ -931,6 +966,16 @@ int bq_save(bq_domain* d, void* host, size_t* bytes) {
 int bq_load(bq_domain* d, const void* host, size_t bytes) {
   if (!d || !host) return fail(BQ_EINVAL, "NULL argument");
   return DISPATCH(d->precision, load_t, d, host, bytes);
+}
+
+int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out) {
+  if (!d || !ms_out || n_steps < 0) return fail(BQ_EINVAL, "bad argument");
+  return DISPATCH(d->precision, profile_t, d->L, d->stream, n_steps, ms_out);
+}
+
+int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out) {
+  if (!b || !ms_out || n_steps < 0) return fail(BQ_EINVAL, "bad argument");
+  return DISPATCH(b->precision, profile_t, b->L, b->stream, n_steps, ms_out);
 }
 
 int bq_set_graph_steps(bq_domain* d, int32_t steps) {

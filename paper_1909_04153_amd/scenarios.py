@@ -121,14 +121,10 @@ def rip_beach(nx=2048, ny=2048, dx=0.5, seed=190904153, hs=1.0, tp=8.0, gamma=3.
               bar_x=660.0, bar_amp=1.0, bar_sigma=20.0, **kw):
     rng = np.random.default_rng(seed)
     Ly = ny * dx
-    # rip channels: K ~ U{3..6}, min spacing 100 m (scaled for small domains)
+    # rip channels: K ~ U{3..6} at jittered, evenly spread alongshore
+    # positions (spacing at least Ly / (2K))
     K = int(rng.integers(3, 7))
-    spacing = min(100.0, Ly / (K + 1))
-    ys = []
-    while len(ys) < K:
-        y = float(rng.uniform(0.05 * Ly, 0.95 * Ly))
-        if all(abs(y - q) >= spacing for q in ys):
-            ys.append(y)
+    ys = [float((k + 0.5 + rng.uniform(-0.25, 0.25)) * Ly / K) for k in range(K)]
     sig_y = rng.uniform(15.0, 30.0, K) * min(1.0, Ly / 1024.0)
     a, om, ph = jonswap_components(hs, tp, gamma, n_waves, rng=rng)
     p = base_params(nx, ny, dx, manning_n=manning, bc=(IRREGULAR, WALL, SPONGE, SPONGE),

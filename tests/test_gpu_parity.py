@@ -1,0 +1,228 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+FP64: relative L2 error per field <= 1e-12 after every compared step.  FP32:
+eta within 1e-4 relative L2 after 1000 steps on non-breaking cases.  The
+relative error divides by max(||ref||, 1e-6 sqrt(N)) so that fields that are
+still zero up to roundoff (flux next to a ramped wavemaker) are judged by
+their absolute error.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import OracleDomain
+from paper_1909_04153_amd import scenarios as S
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("eta", "P", "Q")
+
+
+@pytest.fixture(scope="module")
+def bq():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1909_04153_amd import bq as m
+
+    m.load()
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-6 * math.sqrt(b.size)))
+
+
+def pair(bq, spec, precision):
+    o = OracleDomain(spec["params"], spec["depth_c"])
+    assert o.set_state(spec["eta"], spec["P"], spec["Q"]) == 0
+    g = bq.domain_from_spec(spec, precision=precision)
+    return o, g
+
+
+def run_compare(bq, spec, steps, every, tol, precision=None, fields=FIELDS):
+    precision = bq.FP64 if precision is None else precision
+    o, g = pair(bq, spec, precision)
+    worst = 0.0
+    done = 0
+    while done < steps:
+        k = min(every, steps - done)
+        assert o.step(k) == 0
+        g.step(k)
+        done += k
+        gi, oi = g.sync(), o.info()
+        assert gi.status == 0, gi
+        assert gi.n == oi.n == done
+        assert abs(gi.t - oi.t) <= 1e-12 * oi.t
+        for f in fields:
+            e = rel(g.read(f), o.read(f))
+            worst = max(worst, e)
+            assert e <= tol, f"{spec.get('name')} step {done} field {f}: rel L2 {e:.3e} > {tol:.1e}"
+    return worst, o, g
+
+
+def test_fp64_solitary_flat_full_config(bq):
+    # plain method, FP64: 200 x 20 cells, dx = dy = 0.05 m, depth 1 m,
+    # amplitude 0.1 m, B = 1/15, walls, CFL 0.2 adaptive AB3, 300 steps
+    spec = S.solitary_flat()
+    worst, o, g = run_compare(bq, spec, 300, 1, 1e-12)
+    print(f"solitary 200x20 FP64 worst rel L2 {worst:.2e}")
+    gi, oi = g.sync(), o.info()
+    assert abs(gi.mass - oi.mass) <= 1e-12 * oi.mass
+    assert abs(gi.dt_last - oi.dt_last) <= 1e-12 * oi.dt_last
+
+
+CASES = {
+    # ragged sizes (not multiples of the tile or chunk), wet/dry run-up under a
+    # sine wavemaker with Manning friction
+    "beach_ragged": lambda: S.sloping_beach(nx=133, ny=21, dx=0.1, x_toe=1.0, amp=0.05, ramp=1.0, t_end=0.0),
+    # 2D dispersive case: irregular wavemaker, sponges, rip channels
+    "rip_2d": lambda: S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0),
+    # 2D closed basin over an uneven bed
+    "hump_2d": lambda: S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.125, fstar_order=1),
+    # NLSW limit with a dry front
+    "dam_break": lambda: S.dam_break_dry_bed(nx=150, ny=6, dx=0.1),
+    # unlimited central slopes, quadratic F* extrapolation on a y-uniform case
+    "central_slopes": lambda: S.standing_wave_1d(2.0, cells_per_wavelength=40, rel_amp=1e-2, theta=0.0),
+    # smallest domain
+    "tiny_4x4": lambda: S.closed_basin_hump(nx=4, ny=4, dx=0.5, cfl=0.125, fstar_order=1),
+}
+STEPS = {"beach_ragged": 700, "rip_2d": 150, "hump_2d": 300, "dam_break": 200, "central_slopes": 300,
+         "tiny_4x4": 100}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_fp64_parity_cases(bq, case):
+    worst, _, _ = run_compare(bq, CASES[case](), STEPS[case], 10, 1e-12)
+    print(f"{case} FP64 worst rel L2 {worst:.2e}")
+
+
+def test_fp64_prescribed_and_fixed_steps(bq):
+    spec = S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.125, fstar_order=1)
+    o, g = pair(bq, spec, bq.FP64)
+    for dt in (1e-3, 2e-3, 1.5e-3, 1.5e-3, 3e-3, 1e-3):
+        assert o.step_dt(dt) == 0
+        g.step_dt(dt)
+    for f in FIELDS:
+        assert rel(g.read(f), o.read(f)) <= 1e-12
+    spec = S.solitary_flat(nx=120, ny=8, x0=2.0, fixed_dt=1, dt_init=2e-3)
+    worst, _, _ = run_compare(bq, spec, 100, 10, 1e-12)
+
+
+@pytest.mark.parametrize("case", ["solitary", "hump_2d"])
+def test_fp32_eta_after_1000_steps(bq, case):
+    spec = S.solitary_flat() if case == "solitary" else S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.125,
+                                                                             fstar_order=1)
+    o, g = pair(bq, spec, bq.FP32)
+    assert o.step(1000) == 0
+    g.step(1000)
+    assert g.sync().status == 0
+    errs = {f: rel(g.read(f), o.read(f)) for f in FIELDS}
+    print(f"{case} FP32 after 1000 steps: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    assert errs["eta"] <= 1e-4
+
+
+def test_fp64_full_size_sloping_beach(bq):
+    # 1024 x 256, dx = 0.1 m, 0.5 m deep sloping 1:20 to dry land, sine
+    # source T = 2 s, a = 0.02 m, Manning 0.015: the first 20 steps
+    spec = S.sloping_beach()
+    worst, _, _ = run_compare(bq, spec, 20, 5, 1e-12)
+    print(f"beach 1024x256 FP64 worst rel L2 {worst:.2e}")
+
+
+def test_fp32_full_size_rip_beach_first_steps(bq):
+    # 2048 x 2048 FP32: two steps against the oracle (FP32 tolerance)
+    spec = S.rip_beach(cfl=0.125, fstar_order=1)
+    o, g = pair(bq, spec, bq.FP32)
+    assert o.step(2) == 0
+    g.step(2)
+    assert g.sync().status == 0
+    for f in FIELDS:
+        e = rel(g.read(f), o.read(f))
+        print(f"rip 2048^2 FP32 2 steps {f} {e:.2e}")
+        assert e <= 1e-4
+
+
+def test_status_latching(bq):
+    # negative depth is rejected
+    spec = S.closed_basin_hump(nx=32, ny=16, dx=0.1, cfl=0.125, fstar_order=1)
+    g = bq.domain_from_spec(spec, precision=bq.FP64)
+    bad = spec["eta"].copy()
+    bad[3, 3] = -5.0
+    with pytest.raises(bq.BqError):
+        g.set_state(bad, spec["P"], spec["Q"])
+    # NaN in the state latches ENONFINITE and stops the domain
+    g.set_state(spec["eta"], spec["P"], spec["Q"])
+    P = spec["P"].copy()
+    P[5, 7] = np.nan
+    g.set_state(spec["eta"], P, spec["Q"])
+    g.step(3)
+    i = g.sync()
+    assert i.status == bq.ENONFINITE and i.n == 0
+    # a huge velocity drives the adaptive step below dt_min
+    spec2 = S.closed_basin_hump(nx=32, ny=16, dx=0.1, cfl=0.125, fstar_order=1, dt_min=1e-4)
+    g2 = bq.domain_from_spec(spec2, precision=bq.FP64)
+    P = spec2["P"].copy()
+    P[4, 4] = 1e6
+    g2.set_state(spec2["eta"], P, spec2["Q"])
+    g2.step(2)
+    assert g2.sync().status == bq.EDTMIN
+    # t_end stops the run exactly as the oracle does
+    spec3 = S.solitary_flat(nx=64, ny=8, x0=1.0, t_end=0.05)
+    o, g3 = pair(bq, spec3, bq.FP64)
+    o.step(100)
+    g3.step(100)
+    gi, oi = g3.sync(), o.info()
+    assert gi.status == oi.status == bq.EDONE
+    assert gi.n == oi.n
+
+
+def test_checkpoint_resume_is_bitwise(bq):
+    spec = S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0)
+    a = bq.domain_from_spec(spec, precision=bq.FP32)
+    a.step(15)
+    blob = a.save()
+    a.step(20)
+    ref = [a.read(f) for f in FIELDS]
+    b = bq.domain_from_spec(spec, precision=bq.FP32)
+    b.load_checkpoint(blob)
+    assert b.sync().n == 15
+    b.step(20)
+    for f, r in zip(FIELDS, ref):
+        assert np.array_equal(b.read(f), r), f
+
+
+def test_graph_replay_matches_plain_launches(bq):
+    spec = S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0)
+    outs = []
+    for k in (0, 16, 7):
+        g = bq.domain_from_spec(spec, precision=bq.FP32)
+        g.set_graph_steps(k)
+        g.step(40)
+        g.sync()
+        outs.append([g.read(f) for f in FIELDS])
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
+
+
+def test_batch_members_equal_solo_runs(bq):
+    specs = [S.sloping_beach(nx=200, ny=40, dx=0.1, x_toe=2.0, t_end=0.0),
+             S.solitary_flat(nx=130, ny=70, x0=2.0),
+             S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0)]
+    solo = []
+    for s in specs:
+        g = bq.domain_from_spec(s, precision=bq.FP32)
+        g.step(30)
+        g.sync()
+        solo.append([g.read(f) for f in FIELDS])
+    doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
+    b = bq.Batch(doms)
+    b.step(30)
+    b.sync()
+    for d, ref in zip(doms, solo):
+        assert d.sync().n == 30
+        for f, r in zip(FIELDS, ref):
+            assert np.array_equal(d.read(f), r), f
