@@ -101,6 +101,38 @@ def cpu_baseline(specs, budget_s):
     return done_cells / used, used, names
 
 
+def serve_run(bq, seconds):
+    """a short Poisson request stream (mixed sizes 128..1024, 2..12 s simulated
+    each) through the continuous-batching loop"""
+    from paper_1909_04153_amd import scenarios as S
+    from paper_1909_04153_amd import serve
+
+    rng = np.random.default_rng(190904155)
+    n = 48
+    reqs = []
+    t = 0.0
+    for k in range(n):
+        side = int(round(math.exp(rng.uniform(math.log(128), math.log(1024))) / 64.0)) * 64
+        dur = float(rng.uniform(2.0, 12.0))
+        if rng.uniform() < 0.5:
+            spec = S.beach_of_size(side, side, dx=0.1, t_end=dur)
+        else:
+            spec = S.rip_beach_scaled(side, side, seed=int(rng.integers(1 << 30)), t_end=dur, cfl=0.125,
+                                      fstar_order=1)
+        spec["params"]["t_end"] = dur
+        t += float(rng.exponential(seconds / n / 2.0))
+        reqs.append(serve.Request(k, spec, arrival=t))
+    budget = 16 << 30
+    srv = serve.Server(budget, max_slots=32, precision=bq.FP32, chunk_steps=16)
+    stats = srv.run(reqs, max_wall=4.0 * seconds)
+    out = stats.summary(skip_before=0.1 * t)
+    out["cell_steps_per_s"] = out["cell_steps_per_s"] / 1e9 if out["cell_steps_per_s"] else None
+    out["unit_throughput"] = "Gcell-steps/s"
+    out["hbm_budget_bytes"] = budget
+    out["peak_resident_bytes"] = srv.peak_used
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +143,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="also run the request loop for about this long and report p50/p99")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (5 times), for counter calibration")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -119,6 +155,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20)
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.ones(n, dtype=torch.uint8, device="cuda")
+        for _ in range(5):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "repeats": 5}))
+        return
 
     from paper_1909_04153_amd import bq
 
@@ -163,6 +209,8 @@ def main():
                         "cells": c, "steps": n}
             del g, ds
         out["fp64_plain"] = fp64
+    if args.serve_seconds > 0:
+        out["serving"] = serve_run(bq, args.serve_seconds)
     if not args.no_cpu_baseline:
         rate, used, names = cpu_baseline(specs, args.cpu_seconds)
         out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-steps/s", "cores": 1, "kind": "oracle",

@@ -528,19 +528,21 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const int ic = min(i0 + c - 2, nx + 2), jc = min(j0 + r - 2, ny + 2);
     sm.dc[e] = D.Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
   }
+  __syncthreads();
+  // weighted P/Q history (level n from the staged tile, older levels from HBM)
   for (int e = tid; e < S::BY * BX; e += NT) {
     const int r = e / BX, c = e - r * BX;
     const int i = min(max(i0 + c - 1, -2), nx + 1), j = min(max(j0 + r - 1, -2), ny + 1);
     const size_t g = (size_t)(j + 2) * pitch + xoff + i;
+    const int t2 = (r + 1) * WX + c + 1;        // same cell in the radius-2 tile
     T pv = T(0), qv = T(0);
     if (hist) {
-      pv = beta0 * Pn[g] + beta1 * D.P[s1][g] + beta2 * D.P[s2][g];
-      qv = beta0 * Qn[g] + beta1 * D.Q[s1][g] + beta2 * D.Q[s2][g];
+      pv = beta0 * sm.p[t2] + beta1 * D.P[s1][g] + beta2 * D.P[s2][g];
+      qv = beta0 * sm.q[t2] + beta1 * D.Q[s1][g] + beta2 * D.Q[s2][g];
     }
     sm.pt[e] = pv;
     sm.qt[e] = qv;
   }
-  __syncthreads();
   for (int e = tid; e < S::WY * WX; e += NT) {
     const int r = e / WX, c = e - r * WX;
     sm.db[e] = dbar4(sm.dc[r * CXN + c], sm.dc[r * CXN + c + 1], sm.dc[(r + 1) * CXN + c],
