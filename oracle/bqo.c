@@ -491,8 +491,9 @@ static double max_speed(const bqo_domain* d) {
       const double u = desing(P[CI(d, i, j)], h, d->eps);
       const double v = desing(Q[CI(d, i, j)], h, d->eps);
       const double c = sqrt(d->p.g * h);
-      const double sc = fmax((fabs(u) + c) / d->p.dx, (fabs(v) + c) / d->p.dy);
-      if (sc != sc) return INFINITY;
+      const double sx = (fabs(u) + c) / d->p.dx, sy = (fabs(v) + c) / d->p.dy;
+      if (sx != sx || sy != sy) return INFINITY;
+      const double sc = fmax(sx, sy);
       if (sc > s) s = sc;
     }
   return s;

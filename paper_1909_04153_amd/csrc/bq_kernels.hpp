@@ -16,9 +16,9 @@
 //             (Eq. 42) and F*/G* weights (Eq. 43-46) in FP64, wavemaker
 //             ghost values at t_{n+1};
 //   k_rhs     LDS tile (64 x TY + halo 2): KP07 fluxes, bed source,
-//             dispersion, friction, F*/G* of the weighted P/Q history,
-//             U*^n, V*^n, AB3 update; then the chunk-local tridiagonal solves
-//             of Eq. (19)-(20) inside the tile;
+//             dispersion, friction, F*/G* of the weighted P/Q history, AB3
+//             update of w and of U*, V* (as increments); then the chunk-local
+//             tridiagonal solves of Eq. (19)-(20) for the P, Q increments;
 //   k_reduced per line: the chunk-interface recurrence that couples the
 //             chunk-local solutions into the exact line solution;
 //   k_final   pointwise: P, Q = local solution + spike corrections, sponge,
@@ -68,6 +68,10 @@ struct DomDev {
   int bc[4];
   int fstar_order, fixed_dt, n_waves, any_sponge;
   T dx, dy, g, B, Bc, gn2, theta, eps;
+  // reciprocals of the grid spacing combinations used by the stencils
+  T idx, idy, i2dx, i2dy, idx2, idy2, i4dxdy, i2dx3, i2dy3, i2dxdy2, i2dx2dy;
+  // constants of the Eq. (21) coefficients per direction: 1/(2h), (B+1/3)/h^2, 1/(6h)
+  T tcx[3], tcy[3];
   T sponge_w[4];
   T sponge_sigma;
   double dx_d, dy_d, g_d, cfl, ema_alpha, dt_init, dt_max, dt_min, wave_ramp, t_end;
@@ -100,6 +104,32 @@ struct DomDev {
 // small helpers
 // ---------------------------------------------------------------------------
 
+// Field pointers live in the per-domain descriptor in device memory, so the
+// compiler cannot tell they address global memory and would emit flat
+// accesses (which also wait on the LDS counter); name the address space.
+template <typename T>
+using gp = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gp<T> gbl(T* p) {
+  return (gp<T>)p;
+}
+
+// Square root, reciprocal and cube root.  FP64 uses the correctly rounded
+// operations (parity with the FP64 oracle at 1e-12); FP32 uses the hardware
+// transcendental instructions (about 1 ulp), whose error is far below the
+// FP32 path's own rounding of the state.
+template <typename T> __device__ __forceinline__ T fsqrt(T x);
+template <typename T> __device__ __forceinline__ T frcp(T x);
+template <typename T> __device__ __forceinline__ T frcbrt(T x);   // x^(-1/3), x > 0
+template <> __device__ __forceinline__ double fsqrt<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ double frcp<double>(double x) { return 1.0 / x; }
+template <> __device__ __forceinline__ double frcbrt<double>(double x) { return 1.0 / cbrt(x); }
+template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ float frcbrt<float>(float x) {
+  return __builtin_amdgcn_exp2f(-0.33333333f * __builtin_amdgcn_logf(x));
+}
+
 template <typename T>
 __device__ __forceinline__ T gmm(T a, T b, T c) {
   const T lo = fmin(a, fmin(b, c));
@@ -114,12 +144,20 @@ __device__ __forceinline__ T slope(T qm, T q0, T qp, T theta) {
   return theta > T(0) ? gmm(theta * (q0 - qm), c, theta * (qp - q0)) : c;
 }
 
-// velocity from a flux and a depth, regularised near dry states (KP07)
+// Velocity factor of the KP07 desingularisation, u = q * vfac(h):
+//   sqrt(2) h / sqrt(h^4 + max(h^4, eps)),
+// which is exactly 1/h when h^4 >= eps (taken directly there).
 template <typename T>
-__device__ __forceinline__ T desing(T q, T h, T eps) {
+__device__ __forceinline__ T vfac(T h, T eps) {
   const T h2 = h * h;
   const T h4 = h2 * h2;
-  return T(1.4142135623730951) * h * q / sqrt(h4 + fmax(h4, eps));
+  if (h4 >= eps) return frcp(h);
+  return T(1.4142135623730951) * h * frcp(fsqrt(h4 + eps));
+}
+
+template <typename T>
+__device__ __forceinline__ T desing(T q, T h, T eps) {
+  return q * vfac(h, eps);
 }
 
 // cell-average still-water depth from its four corners
@@ -167,8 +205,9 @@ __device__ __forceinline__ Side<T> make_side(T w, T qn, T qt, T Dface, T eps, T 
   Side<T> s;
   s.w = w;
   s.h = fmax(w + Dface, T(0));
-  s.un = desing(qn, s.h, eps);
-  s.ut = desing(qt, s.h, eps);
+  const T vf = vfac(s.h, eps);
+  s.un = qn * vf;
+  s.ut = qt * vf;
   s.qn = s.h * s.un;
   s.qt = s.h * s.ut;
   const T Dp = fmax(Dface, T(0));
@@ -181,7 +220,7 @@ __device__ __forceinline__ Side<T> make_side(T w, T qn, T qt, T Dface, T eps, T 
 // tangential momentum); the normal momentum flux excludes g D^2 / 2
 template <typename T>
 __device__ __forceinline__ void cu_flux(const Side<T>& L, const Side<T>& R, T g, T Dface, T& f0, T& fn, T& ft) {
-  const T cL = sqrt(g * L.h), cR = sqrt(g * R.h);
+  const T cL = fsqrt(g * L.h), cR = fsqrt(g * R.h);
   const T ap = fmax(fmax(L.un + cL, R.un + cR), T(0));
   const T am = fmin(fmin(L.un - cL, R.un - cR), T(0));
   const T den = ap - am;
@@ -192,7 +231,7 @@ __device__ __forceinline__ void cu_flux(const Side<T>& L, const Side<T>& R, T g,
     fn = -T(0.5) * g * Dp * Dp;
     return;
   }
-  const T inv = T(1) / den;
+  const T inv = frcp(den);
   const T dis = ap * am * inv;
   const T pL = L.qn * L.un + L.pp;
   const T pR = R.qn * R.un + R.pp;
@@ -219,99 +258,65 @@ __device__ __forceinline__ T shore_term(T Dl, T Dh, T g) {
 }
 
 // Coefficients of Eq. (21) at a cell from the still-water depths of the cell
-// and its two neighbours along the line (spacing h).
+// and its two neighbours along the line; tc = (1/(2h), (B+1/3)/h^2, 1/(6h)).
 template <typename T>
-__device__ __forceinline__ void tri_coef(T dm, T d0, T dp, T h, T Bc, T& a, T& b, T& c) {
-  const T dd = (dp - dm) / (T(2) * h);
-  const T k = Bc * d0 * d0 / (h * h);
-  const T s = d0 * dd / (T(6) * h);
+__device__ __forceinline__ void tri_coef(T dm, T d0, T dp, const T* tc, T& a, T& b, T& c) {
+  const T dd = (dp - dm) * tc[0];
+  const T k = tc[1] * d0 * d0;
+  const T s = d0 * dd * tc[2];
   a = s - k;
   b = T(1) + T(2) * k;
   c = -s - k;
 }
 
 // Chunk-local tridiagonal solve (zero coupling to the neighbouring chunks)
-// of the m (<= M) unknowns of one chunk.  dl[k * ds], k = 0..m+1, are the
-// still-water depths of the chunk's cells with one neighbour on each side.
+// of the m (<= M) unknowns of one chunk.  Dl[k * ds], k = 0..m+1, are the
+// cell-average still-water depths of the chunk's cells with one neighbour on
+// each side (d = max(D, 0)); tc are the Eq. (21) constants of the direction.
 // fold_lo / fold_hi fold the odd mirror of a wall into the first / last
-// diagonal.  rhs (stride rs) is overwritten with the solution; piv (stride
-// rs) receives the reciprocal pivots.
+// diagonal.  rhs (stride rs) is overwritten with the solution; the reciprocal
+// pivots stay in registers (the loops are unrolled over M).
 template <typename T, int M>
-__device__ __forceinline__ void chunk_solve(const T* dl, int ds, int m, T h, T Bc, bool fold_lo, bool fold_hi, T* rhs,
-                                            T* piv, int rs) {
+__device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                               T* rhs, int rs) {
+  T piv[M];
   T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
-  for (int k = 0; k < m; ++k) {
-    T a, b, c;
-    tri_coef(dl[k * ds], dl[(k + 1) * ds], dl[(k + 2) * ds], h, Bc, a, b, c);
-    if (k == 0 && fold_lo) b -= a;
-    if (k == m - 1 && fold_hi) b -= c;
-    const T r = rhs[k * rs];
-    T u, y;
-    if (k == 0) {
-      u = b;
-      y = r;
-    } else {
-      const T l = a * iu_prev;
-      u = b - l * c_prev;
-      y = r - l * y_prev;
+#pragma unroll
+  for (int k = 0; k < M; ++k) {
+    if (k < m) {
+      T a, b, c;
+      tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+      if (k == 0 && fold_lo) b -= a;
+      if (k == m - 1 && fold_hi) b -= c;
+      const T r = rhs[k * rs];
+      T u, y;
+      if (k == 0) {
+        u = b;
+        y = r;
+      } else {
+        const T l = a * iu_prev;
+        u = b - l * c_prev;
+        y = r - l * y_prev;
+      }
+      const T iu = frcp(u);
+      piv[k] = iu;
+      rhs[k * rs] = y;
+      y_prev = y;
+      iu_prev = iu;
+      c_prev = c;
     }
-    const T iu = T(1) / u;
-    piv[k * rs] = iu;
-    rhs[k * rs] = y;
-    y_prev = y;
-    iu_prev = iu;
-    c_prev = c;
   }
   T x_next = T(0);
-  for (int k = m - 1; k >= 0; --k) {
-    T a, b, c;
-    tri_coef(dl[k * ds], dl[(k + 1) * ds], dl[(k + 2) * ds], h, Bc, a, b, c);
-    const T y = rhs[k * rs];
-    const T x = (k == m - 1) ? y * piv[k * rs] : (y - c * x_next) * piv[k * rs];
-    rhs[k * rs] = x;
-    x_next = x;
-  }
-}
-
-// chunk_solve on raw cell-average still-water depths (d = max(D, 0))
-template <typename T, int M>
-__device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, T h, T Bc, bool fold_lo, bool fold_hi,
-                                               T* rhs, T* piv, int rs) {
-  struct DV {
-    const T* p;
-    int s;
-  };
-  T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
-  for (int k = 0; k < m; ++k) {
-    T a, b, c;
-    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), h, Bc, a, b, c);
-    if (k == 0 && fold_lo) b -= a;
-    if (k == m - 1 && fold_hi) b -= c;
-    const T r = rhs[k * rs];
-    T u, y;
-    if (k == 0) {
-      u = b;
-      y = r;
-    } else {
-      const T l = a * iu_prev;
-      u = b - l * c_prev;
-      y = r - l * y_prev;
+#pragma unroll
+  for (int k = M - 1; k >= 0; --k) {
+    if (k < m) {
+      T a, b, c;
+      tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+      const T y = rhs[k * rs];
+      const T x = (k == m - 1) ? y * piv[k] : (y - c * x_next) * piv[k];
+      rhs[k * rs] = x;
+      x_next = x;
     }
-    const T iu = T(1) / u;
-    piv[k * rs] = iu;
-    rhs[k * rs] = y;
-    y_prev = y;
-    iu_prev = iu;
-    c_prev = c;
-  }
-  T x_next = T(0);
-  for (int k = m - 1; k >= 0; --k) {
-    T a, b, c;
-    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), h, Bc, a, b, c);
-    const T y = rhs[k * rs];
-    const T x = (k == m - 1) ? y * piv[k * rs] : (y - c * x_next) * piv[k * rs];
-    rhs[k * rs] = x;
-    x_next = x;
   }
 }
 
@@ -469,6 +474,7 @@ struct RhsSmem {
   static constexpr int WX = TX + 4, WY = TY + 4;      // radius-2 tiles
   static constexpr int BX = TX + 2, BY = TY + 2;      // radius-1 tiles
   static constexpr int CXN = TX + 5, CYN = TY + 5;    // corners
+  static constexpr int TXP = TX + 1;                  // padded row of the solve buffers
   T w[WY * WX];
   T p[WY * WX];
   T q[WY * WX];
@@ -476,16 +482,13 @@ struct RhsSmem {
   T pt[BY * BX];                                      // sum_k beta_k P^{n-k}
   T qt[BY * BX];
   T dc[CYN * CXN];
+  static constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
+  static constexpr int NF = NFX > NFY ? NFX : NFY;
   union {
+    T f[3][NF];                                       // x-face, then y-face fluxes
     struct {
-      T fx[3][TY * (TX + 1)];
-      T fy[3][(TY + 1) * TX];
-    } f;
-    struct {
-      T u[TY * TX];
-      T v[TY * TX];
-      T pu[TY * TX];
-      T pv[TY * TX];
+      T u[TY * TXP];
+      T v[TY * TXP];
     } s;
   } x;
 };
@@ -494,8 +497,11 @@ template <typename T, int TY, int MX>
 __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_prefix,
                                            int nd) {
   using S = RhsSmem<T, TY, MX>;
-  constexpr int WX = S::WX, BX = S::BX, CXN = S::CXN;
-  constexpr int CPT = (TX * TY) / NT;   // cells per thread
+  constexpr int WX = S::WX, BX = S::BX, CXN = S::CXN, TXP = S::TXP;
+  constexpr int NWW = (S::WY * WX + NT - 1) / NT;     // staging rounds per array
+  constexpr int NWC = (S::CYN * CXN + NT - 1) / NT;
+  constexpr int NWB = (S::BY * BX + NT - 1) / NT;
+  constexpr int CPT = (TX * TY) / NT;                 // cells per thread
   static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
   __shared__ S sm;
   const int dom = find_domain(tile_prefix, nd, blockIdx.x);
@@ -507,41 +513,94 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int slot = st->slot;
   const int s1 = slot == 0 ? 2 : slot - 1, s2 = slot == 2 ? 0 : slot + 1;
-  const T* __restrict__ w = D.w[st->n & 1];
-  const T* __restrict__ Pn = D.P[slot];
-  const T* __restrict__ Qn = D.Q[slot];
+  const gp<const T> w = gbl((const T*)D.w[st->n & 1]);
+  const gp<const T> Pn = gbl((const T*)D.P[slot]);
+  const gp<const T> Qn = gbl((const T*)D.Q[slot]);
+  const gp<const T> P1 = gbl((const T*)D.P[s1]);
+  const gp<const T> P2 = gbl((const T*)D.P[s2]);
+  const gp<const T> Q1 = gbl((const T*)D.Q[s1]);
+  const gp<const T> Q2 = gbl((const T*)D.Q[s2]);
+  const gp<const T> Dc = gbl((const T*)D.Dc);
   const T beta0 = (T)st->beta[0], beta1 = (T)st->beta[1], beta2 = (T)st->beta[2];
   const bool hist = st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
-  const int pitch = D.pitch, xoff = D.xoff;
+  const int pitch = D.pitch, xoff = D.xoff, ipitch = D.ipitch;
 
-  // ---- phase 0: stage the tile and its halo in LDS -----------------------
-  for (int e = tid; e < S::WY * WX; e += NT) {
+  // ---- phase 0: issue every load of the tile before the first LDS store ----
+  // E, F, G history of this thread's cells (consumed in phase 2)
+  T he1[CPT], he2[CPT], hf1[CPT], hf2[CPT], hg1[CPT], hg2[CPT];
+  {
+    const gp<const T> E1 = gbl((const T*)D.E[s1]);
+    const gp<const T> E2 = gbl((const T*)D.E[s2]);
+    const gp<const T> F1 = gbl((const T*)D.F[s1]);
+    const gp<const T> F2 = gbl((const T*)D.F[s2]);
+    const gp<const T> G1 = gbl((const T*)D.G[s1]);
+    const gp<const T> G2 = gbl((const T*)D.G[s2]);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int e = tid + q * NT;
+      const int r = e / TX, c = e - r * TX;
+      const int i = min(i0 + c, nx - 1), j = min(j0 + r, ny - 1);
+      const size_t ii = (size_t)j * ipitch + i;
+      he1[q] = E1[ii]; he2[q] = E2[ii];
+      hf1[q] = F1[ii]; hf2[q] = F2[ii];
+      hg1[q] = G1[ii]; hg2[q] = G2[ii];
+    }
+  }
+  T rw[NWW], rp[NWW], rq[NWW], rc[NWC], h1p[NWB], h2p[NWB], h1q[NWB], h2q[NWB];
+#pragma unroll
+  for (int k = 0; k < NWW; ++k) {
+    const int e = min(tid + k * NT, S::WY * WX - 1);
     const int r = e / WX, c = e - r * WX;
     const int i = min(max(i0 + c - 2, -2), nx + 1), j = min(max(j0 + r - 2, -2), ny + 1);
     const size_t g = (size_t)(j + 2) * pitch + xoff + i;
-    sm.w[e] = w[g];
-    sm.p[e] = Pn[g];
-    sm.q[e] = Qn[g];
+    rw[k] = w[g];
+    rp[k] = Pn[g];
+    rq[k] = Qn[g];
   }
-  for (int e = tid; e < S::CYN * CXN; e += NT) {
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) {
+    const int e = min(tid + k * NT, S::CYN * CXN - 1);
     const int r = e / CXN, c = e - r * CXN;
     const int ic = min(i0 + c - 2, nx + 2), jc = min(j0 + r - 2, ny + 2);
-    sm.dc[e] = D.Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
+    rc[k] = Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
+  }
+#pragma unroll
+  for (int k = 0; k < NWB; ++k) {
+    h1p[k] = h2p[k] = h1q[k] = h2q[k] = T(0);
+    if (hist) {
+      const int e = min(tid + k * NT, S::BY * BX - 1);
+      const int r = e / BX, c = e - r * BX;
+      const int i = min(max(i0 + c - 1, -2), nx + 1), j = min(max(j0 + r - 1, -2), ny + 1);
+      const size_t g = (size_t)(j + 2) * pitch + xoff + i;
+      h1p[k] = P1[g]; h2p[k] = P2[g];
+      h1q[k] = Q1[g]; h2q[k] = Q2[g];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NWW; ++k) {
+    const int e = tid + k * NT;
+    if (e < S::WY * WX) {
+      sm.w[e] = rw[k];
+      sm.p[e] = rp[k];
+      sm.q[e] = rq[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) {
+    const int e = tid + k * NT;
+    if (e < S::CYN * CXN) sm.dc[e] = rc[k];
   }
   __syncthreads();
-  // weighted P/Q history (level n from the staged tile, older levels from HBM)
-  for (int e = tid; e < S::BY * BX; e += NT) {
-    const int r = e / BX, c = e - r * BX;
-    const int i = min(max(i0 + c - 1, -2), nx + 1), j = min(max(j0 + r - 1, -2), ny + 1);
-    const size_t g = (size_t)(j + 2) * pitch + xoff + i;
-    const int t2 = (r + 1) * WX + c + 1;        // same cell in the radius-2 tile
-    T pv = T(0), qv = T(0);
-    if (hist) {
-      pv = beta0 * sm.p[t2] + beta1 * D.P[s1][g] + beta2 * D.P[s2][g];
-      qv = beta0 * sm.q[t2] + beta1 * D.Q[s1][g] + beta2 * D.Q[s2][g];
+  // weighted P/Q history (level n from the staged tile) and cell depths
+#pragma unroll
+  for (int k = 0; k < NWB; ++k) {
+    const int e = tid + k * NT;
+    if (e < S::BY * BX) {
+      const int r = e / BX, c = e - r * BX;
+      const int t2 = (r + 1) * WX + c + 1;    // same cell in the radius-2 tile
+      sm.pt[e] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
+      sm.qt[e] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
     }
-    sm.pt[e] = pv;
-    sm.qt[e] = qv;
   }
   for (int e = tid; e < S::WY * WX; e += NT) {
     const int r = e / WX, c = e - r * WX;
@@ -571,10 +630,27 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const Side<T> R = make_side(wRl, sm.p[row + f + 2] - T(0.5) * sPR, sm.q[row + f + 2] - T(0.5) * sQR, Df, eps, g);
     T f0, fn, ft;
     cu_flux(L, R, g, Df, f0, fn, ft);
-    sm.x.f.fx[0][e] = f0;
-    sm.x.f.fx[1][e] = fn;
-    sm.x.f.fx[2][e] = ft;
+    sm.x.f[0][e] = f0;
+    sm.x.f[1][e] = fn;
+    sm.x.f[2][e] = ft;
   }
+  __syncthreads();
+  // x-flux differences of this thread's cells, then the buffer takes the
+  // y-face fluxes
+  T acc_e[CPT], acc_f[CPT], acc_g[CPT];
+  {
+    const T idx = D.idx;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int e = tid + q * NT;
+      const int r = e / TX, c = e - r * TX;
+      const int fxw = r * (TX + 1) + c;
+      acc_e[q] = -(sm.x.f[0][fxw + 1] - sm.x.f[0][fxw]) * idx;
+      acc_f[q] = -(sm.x.f[1][fxw + 1] - sm.x.f[1][fxw]) * idx;
+      acc_g[q] = -(sm.x.f[2][fxw + 1] - sm.x.f[2][fxw]) * idx;
+    }
+  }
+  __syncthreads();
   for (int e = tid; e < (TY + 1) * TX; e += NT) {
     const int gy = e / TX, c = e - gy * TX;
     const int col = c + 2;
@@ -595,26 +671,19 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const Side<T> Nd = make_side(wNl, sm.q[r2] - T(0.5) * sQN, sm.p[r2] - T(0.5) * sPN, Df, eps, g);
     T f0, fn, ft;
     cu_flux(Sd, Nd, g, Df, f0, fn, ft);
-    sm.x.f.fy[0][e] = f0;
-    sm.x.f.fy[1][e] = ft;   // x-momentum flux through a y-face
-    sm.x.f.fy[2][e] = fn;   // y-momentum flux through a y-face
+    sm.x.f[0][e] = f0;
+    sm.x.f[1][e] = ft;   // x-momentum flux through a y-face
+    sm.x.f[2][e] = fn;   // y-momentum flux through a y-face
   }
   __syncthreads();
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
-  const T dx = D.dx, dy = D.dy, B = D.B, Bc = D.Bc, gn2 = D.gn2;
-  const double al0 = st->alpha[0], al1 = st->alpha[1], al2 = st->alpha[2];
-  const T a0 = (T)al0, a1 = (T)al1, a2 = (T)al2;
-  T* __restrict__ wn = D.w[(st->n + 1) & 1];
-  T* __restrict__ E0 = D.E[slot];
-  T* __restrict__ F0 = D.F[slot];
-  T* __restrict__ G0 = D.G[slot];
-  const T* __restrict__ E1 = D.E[s1];
-  const T* __restrict__ F1 = D.F[s1];
-  const T* __restrict__ G1 = D.G[s1];
-  const T* __restrict__ E2 = D.E[s2];
-  const T* __restrict__ F2 = D.F[s2];
-  const T* __restrict__ G2 = D.G[s2];
+  const T idx = D.idx, idy = D.idy, B = D.B, Bc = D.Bc, gn2 = D.gn2;
+  const T a0 = (T)st->alpha[0], a1 = (T)st->alpha[1], a2 = (T)st->alpha[2];
+  const gp<T> wn = gbl(D.w[(st->n + 1) & 1]);
+  const gp<T> E0 = gbl(D.E[slot]);
+  const gp<T> F0 = gbl(D.F[slot]);
+  const gp<T> G0 = gbl(D.G[slot]);
   T ures[CPT], vres[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
@@ -625,10 +694,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     vres[q] = T(0);
     if (i >= nx || j >= ny) continue;
     const int C0 = (r + 2) * WX + c + 2;   // radius-2 tile index of the cell
-    const int fxw = r * (TX + 1) + c, fyS = r * TX + c;
-    T e_ = -(sm.x.f.fx[0][fxw + 1] - sm.x.f.fx[0][fxw]) / dx - (sm.x.f.fy[0][fyS + TX] - sm.x.f.fy[0][fyS]) / dy;
-    T f_ = -(sm.x.f.fx[1][fxw + 1] - sm.x.f.fx[1][fxw]) / dx - (sm.x.f.fy[1][fyS + TX] - sm.x.f.fy[1][fyS]) / dy;
-    T g_ = -(sm.x.f.fx[2][fxw + 1] - sm.x.f.fx[2][fxw]) / dx - (sm.x.f.fy[2][fyS + TX] - sm.x.f.fy[2][fyS]) / dy;
+    const int fyS = r * TX + c;
+    T e_ = acc_e[q] - (sm.x.f[0][fyS + TX] - sm.x.f[0][fyS]) * idy;
+    T f_ = acc_f[q] - (sm.x.f[1][fyS + TX] - sm.x.f[1][fyS]) * idy;
+    T g_ = acc_g[q] - (sm.x.f[2][fyS + TX] - sm.x.f[2][fyS]) * idy;
     // well-balanced bed slope source -g h b_x with h the mean of the cell's
     // own face depths; only the departure of those depths from the face
     // still-water depths remains once the still-water parts cancel against
@@ -639,15 +708,15 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       const T Ds = T(0.5) * (cr[0] + cr[1]), Dn = T(0.5) * (cr[CXN] + cr[CXN + 1]);
       T wl, wh;
       recon_w(sm.w[C0 - 1], sm.w[C0], sm.w[C0 + 1], theta, Dw, De, wl, wh);
-      f_ += g * (De - Dw) / dx * (T(0.5) * (face_dev(wh, De) + face_dev(wl, Dw))) + shore_term(Dw, De, g) / dx;
+      f_ += (g * (De - Dw) * (T(0.5) * (face_dev(wh, De) + face_dev(wl, Dw))) + shore_term(Dw, De, g)) * idx;
       recon_w(sm.w[C0 - WX], sm.w[C0], sm.w[C0 + WX], theta, Ds, Dn, wl, wh);
-      g_ += g * (Dn - Ds) / dy * (T(0.5) * (face_dev(wh, Dn) + face_dev(wl, Ds))) + shore_term(Ds, Dn, g) / dy;
+      g_ += (g * (Dn - Ds) * (T(0.5) * (face_dev(wh, Dn) + face_dev(wl, Ds))) + shore_term(Ds, Dn, g)) * idy;
     }
     const T Db = sm.db[C0];
     const T d0 = dpos(Db);
     const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
     const T dym = dpos(sm.db[C0 - WX]), dyp = dpos(sm.db[C0 + WX]);
-    const T ddx = (dxp - dxm) / (T(2) * dx), ddy = (dyp - dym) / (T(2) * dy);
+    const T ddx = (dxp - dxm) * D.i2dx, ddy = (dyp - dym) * D.i2dy;
     // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0)
     if (d0 > T(0)) {
 #define ETA(o) (sm.w[C0 + (o)] + fmin(sm.db[C0 + (o)], T(0)))
@@ -656,13 +725,13 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       const T emm = ETA(-WX - 1), epm = ETA(-WX + 1), emp = ETA(WX - 1), epp = ETA(WX + 1);
       const T exm2 = ETA(-2), exp2 = ETA(2), eym2 = ETA(-2 * WX), eyp2 = ETA(2 * WX);
 #undef ETA
-      const T exx = (exp_ - T(2) * e00 + exm) / (dx * dx);
-      const T eyy = (eyp - T(2) * e00 + eym) / (dy * dy);
-      const T exy = ((epp - epm) - (emp - emm)) / (T(4) * dx * dy);
-      const T exxx = ((exp2 - exm2) - T(2) * (exp_ - exm)) / (T(2) * dx * dx * dx);
-      const T eyyy = ((eyp2 - eym2) - T(2) * (eyp - eym)) / (T(2) * dy * dy * dy);
-      const T exyy = ((epp - T(2) * exp_ + epm) - (emp - T(2) * exm + emm)) / (T(2) * dx * dy * dy);
-      const T exxy = ((epp - T(2) * eyp + emp) - (epm - T(2) * eym + emm)) / (T(2) * dx * dx * dy);
+      const T exx = (exp_ - T(2) * e00 + exm) * D.idx2;
+      const T eyy = (eyp - T(2) * e00 + eym) * D.idy2;
+      const T exy = ((epp - epm) - (emp - emm)) * D.i4dxdy;
+      const T exxx = ((exp2 - exm2) - T(2) * (exp_ - exm)) * D.i2dx3;
+      const T eyyy = ((eyp2 - eym2) - T(2) * (eyp - eym)) * D.i2dy3;
+      const T exyy = ((epp - T(2) * exp_ + epm) - (emp - T(2) * exm + emm)) * D.i2dxdy2;
+      const T exxy = ((epp - T(2) * eyp + emp) - (epm - T(2) * eym + emm)) * D.i2dx2dy;
       const T bg = B * g * d0 * d0;
       f_ += bg * d0 * (exxx + exyy) + bg * (ddx * (T(2) * exx + eyy) + ddy * exy);
       g_ += bg * d0 * (eyyy + exxy) + bg * (ddy * (T(2) * eyy + exx) + ddx * exy);
@@ -671,48 +740,41 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const T h = fmax(sm.w[C0] + Db, T(0));
     const T Pc = sm.p[C0], Qc = sm.q[C0];
     if (h > T(0) && gn2 > T(0)) {
-      const T u = desing(Pc, h, eps), v = desing(Qc, h, eps);
-      const T k = gn2 * sqrt(u * u + v * v) / cbrt(h);
+      const T vf = vfac(h, eps);
+      const T u = Pc * vf, v = Qc * vf;
+      const T k = gn2 * fsqrt(u * u + v * v) * frcbrt(h);
       f_ -= k * u;
       g_ -= k * v;
     }
     // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k}) (Eq. 14-15 are linear)
     const int B0 = (r + 1) * BX + c + 1;
-    const T qy = (sm.qt[B0 + BX] - sm.qt[B0 - BX]) / (T(2) * dy);
-    const T qx = (sm.qt[B0 + 1] - sm.qt[B0 - 1]) / (T(2) * dx);
-    const T qxy = ((sm.qt[B0 + BX + 1] - sm.qt[B0 - BX + 1]) - (sm.qt[B0 + BX - 1] - sm.qt[B0 - BX - 1])) /
-                  (T(4) * dx * dy);
-    const T py = (sm.pt[B0 + BX] - sm.pt[B0 - BX]) / (T(2) * dy);
-    const T px = (sm.pt[B0 + 1] - sm.pt[B0 - 1]) / (T(2) * dx);
-    const T pxy = ((sm.pt[B0 + BX + 1] - sm.pt[B0 - BX + 1]) - (sm.pt[B0 + BX - 1] - sm.pt[B0 - BX - 1])) /
-                  (T(4) * dx * dy);
-    const T fs = d0 * ddx * qy / T(6) + d0 * ddy * qx / T(6) + Bc * d0 * d0 * qxy;
-    const T gs = d0 * ddx * py / T(6) + d0 * ddy * px / T(6) + Bc * d0 * d0 * pxy;
-    // U*^n, V*^n: rows of Eq. (19)-(20)
-    T ax, bx, cx, ay, by, cy;
-    tri_coef(dxm, d0, dxp, dx, Bc, ax, bx, cx);
-    tri_coef(dym, d0, dyp, dy, Bc, ay, by, cy);
-    // (a + b + c = 1: written around the centre value to keep FP32 digits)
-    const T Un = Pc + (ax * (sm.p[C0 - 1] - Pc) + cx * (sm.p[C0 + 1] - Pc));
-    const T Vn = Qc + (ay * (sm.q[C0 - WX] - Qc) + cy * (sm.q[C0 + WX] - Qc));
-    (void)bx;
-    (void)by;
+    const T qy = (sm.qt[B0 + BX] - sm.qt[B0 - BX]) * D.i2dy;
+    const T qx = (sm.qt[B0 + 1] - sm.qt[B0 - 1]) * D.i2dx;
+    const T qxy = ((sm.qt[B0 + BX + 1] - sm.qt[B0 - BX + 1]) - (sm.qt[B0 + BX - 1] - sm.qt[B0 - BX - 1])) * D.i4dxdy;
+    const T py = (sm.pt[B0 + BX] - sm.pt[B0 - BX]) * D.i2dy;
+    const T px = (sm.pt[B0 + 1] - sm.pt[B0 - 1]) * D.i2dx;
+    const T pxy = ((sm.pt[B0 + BX + 1] - sm.pt[B0 - BX + 1]) - (sm.pt[B0 + BX - 1] - sm.pt[B0 - BX - 1])) * D.i4dxdy;
+    const T fs = d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
+    const T gs = d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
     // Eq. (42)-(43)
-    const size_t ii = (size_t)j * D.ipitch + i;
-    const T e1 = E1[ii], e2 = E2[ii], f1 = F1[ii], f2 = F2[ii], g1 = G1[ii], g2 = G2[ii];
+    const size_t ii = (size_t)j * ipitch + i;
     E0[ii] = e_;
     F0[ii] = f_;
     G0[ii] = g_;
-    wn[(size_t)(j + 2) * pitch + xoff + i] = sm.w[C0] + (a0 * e_ + a1 * e1 + a2 * e2);
-    ures[q] = Un + (a0 * f_ + a1 * f1 + a2 * f2) + fs;
-    vres[q] = Vn + (a0 * g_ + a1 * g1 + a2 * g2) + gs;
+    wn[(size_t)(j + 2) * pitch + xoff + i] = sm.w[C0] + (a0 * e_ + a1 * he1[q] + a2 * he2[q]);
+    // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
+    // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
+    // U*^n = T P^n with the same matrix
+    ures[q] = (a0 * f_ + a1 * hf1[q] + a2 * hf2[q]) + fs;
+    vres[q] = (a0 * g_ + a1 * hg1[q] + a2 * hg2[q]) + gs;
   }
   __syncthreads();  // fluxes consumed; the union now holds U*, V*
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int e = tid + q * NT;
-    sm.x.s.u[e] = ures[q];
-    sm.x.s.v[e] = vres[q];
+    const int r = e / TX, c = e - r * TX;
+    sm.x.s.u[r * TXP + c] = ures[q];
+    sm.x.s.v[r * TXP + c] = vres[q];
   }
   __syncthreads();
 
@@ -727,29 +789,32 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
       // depths of cells is-1 .. is+m (tile columns qc*MX+1 ..)
-      T* dlx = sm.db + (r + 2) * WX + qc * MX + 1;
-      T* rhs = sm.x.s.u + r * TX + qc * MX;
+      const T* dlx = sm.db + (r + 2) * WX + qc * MX + 1;
+      T* rhs = sm.x.s.u + r * TXP + qc * MX;
       if (is == 0 && wave_w) {
+        // Dirichlet ghost: the increment of P_{-1} from t_n to t_{n+1}
         T a, b, c;
-        tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), dx, Bc, a, b, c);
-        rhs[0] -= a * (T)st->gP[0];   // Dirichlet ghost P_{-1}(t_{n+1})
+        tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c);
+        rhs[0] -= a * ((T)st->gP[0] - sm.p[(r + 2) * WX + 1]);
       }
-      chunk_solve_db<T, MX>(dlx, 1, m, dx, Bc, is == 0 && !wave_w, is + m == nx, rhs, sm.x.s.pu + r * TX + qc * MX, 1);
+      chunk_solve_db<T, MX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs, 1);
       const int cgl = is / MX;
-      D.chx[(size_t)cgl * ny + j] = rhs[0];
-      D.chx[((size_t)D.cx + cgl) * ny + j] = rhs[m - 1];
+      const gp<T> chx = gbl(D.chx);
+      chx[(size_t)cgl * ny + j] = rhs[0];
+      chx[((size_t)D.cx + cgl) * ny + j] = rhs[m - 1];
     }
   } else if (tid >= 64 && tid < 64 + TX) {
     const int c = tid - 64;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
-      T* dly = sm.db + WX + c + 2;        // depths of rows j0-1 .. j0+m
+      const T* dly = sm.db + WX + c + 2;        // depths of rows j0-1 .. j0+m
       T* rhs = sm.x.s.v + c;
-      chunk_solve_db<T, TY>(dly, WX, m, dy, Bc, j0 == 0, j0 + m == ny, rhs, sm.x.s.pv + c, TX);
+      chunk_solve_db<T, TY>(dly, WX, m, D.tcy, j0 == 0, j0 + m == ny, rhs, TXP);
       const int cgl = j0 / TY;
-      D.chy[(size_t)cgl * nx + i] = rhs[0];
-      D.chy[((size_t)D.cy + cgl) * nx + i] = rhs[(m - 1) * TX];
+      const gp<T> chy = gbl(D.chy);
+      chy[(size_t)cgl * nx + i] = rhs[0];
+      chy[((size_t)D.cy + cgl) * nx + i] = rhs[(m - 1) * TXP];
     }
   }
   __syncthreads();
@@ -759,9 +824,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const int r = e / TX, c = e - r * TX;
     const int i = i0 + c, j = j0 + r;
     if (i < nx && j < ny) {
-      const size_t ii = (size_t)j * D.ipitch + i;
-      D.xhP[ii] = sm.x.s.u[e];
-      D.xhQ[ii] = sm.x.s.v[e];
+      const size_t ii = (size_t)j * ipitch + i;
+      const int C0 = (r + 2) * WX + c + 2;
+      gbl(D.xhP)[ii] = sm.p[C0] + sm.x.s.u[r * TXP + c];
+      gbl(D.xhQ)[ii] = sm.q[C0] + sm.x.s.v[r * TXP + c];
     }
   }
 }
@@ -780,8 +846,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 // static and precomputed.
 
 template <typename T>
-__device__ __forceinline__ void reduce_line(int C, int L, int line, const T* __restrict__ ch, const T* __restrict__ rs,
-                                            T* __restrict__ itf) {
+__device__ __forceinline__ void reduce_line(int C, int L, int line, const gp<const T> ch, const gp<const T> rs,
+                                            const gp<T> itf) {
   const size_t CL = (size_t)C * L;
   T al = T(0);
   for (int c = 0; c < C; ++c) {
@@ -815,8 +881,8 @@ __global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ d
   const DomDev<T>& D = doms[dom];
   if (D.st->halt) return;
   const int l = gid - line_prefix[dom];
-  if (l < D.ny) reduce_line(D.cx, D.ny, l, D.chx, D.rsx, D.ifx);
-  else reduce_line(D.cy, D.nx, l - D.ny, D.chy, D.rsy, D.ify);
+  if (l < D.ny) reduce_line<T>(D.cx, D.ny, l, gbl((const T*)D.chx), gbl((const T*)D.rsx), gbl(D.ifx));
+  else reduce_line<T>(D.cy, D.nx, l - D.ny, gbl((const T*)D.chy), gbl((const T*)D.rsy), gbl(D.ify));
 }
 
 // ---------------------------------------------------------------------------
@@ -826,9 +892,44 @@ __global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ d
 template <typename T>
 __device__ __forceinline__ void put3(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T vw, T vp, T vq) {
   const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
-  w[g] = vw;
-  P[g] = vp;
-  Q[g] = vq;
+  gbl(w)[g] = vw;
+  gbl(P)[g] = vp;
+  gbl(Q)[g] = vq;
+}
+
+// ghost cells written by interior cell (i, j) of the new state: x sides for
+// interior rows (wall mirror or wavemaker values), then y sides for all
+// columns (the corners mirror the x ghosts)
+template <typename T>
+__device__ void ghost_cell(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T wv, T p, T qv, const double* gw,
+                           const double* gP) {
+  const int nx = D.nx, ny = D.ny;
+  const bool yg = j < 2 || j >= ny - 2;
+  T gwv = wv, gpv = p, gqv = qv;
+  int gi = 0;
+  bool have_x = false;
+  if (i < 2) {
+    gi = -1 - i;
+    have_x = true;
+    if (D.bc[0] == SINE || D.bc[0] == IRREGULAR) {
+      gwv = (T)gw[i];
+      gpv = (T)gP[i];
+      gqv = T(0);
+    } else {
+      gpv = -p;
+    }
+    put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
+  } else if (i >= nx - 2) {
+    gi = 2 * nx - 1 - i;
+    have_x = true;
+    gpv = -p;
+    put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
+  }
+  if (yg) {
+    const int gj = j < 2 ? -1 - j : 2 * ny - 1 - j;
+    put3(D, w, P, Q, i, gj, wv, p, -qv);
+    if (have_x) put3(D, w, P, Q, gi, gj, gwv, gpv, -gqv);
+  }
 }
 
 template <typename T, int TY, int MX>
@@ -842,28 +943,49 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int ns = st->slot == 2 ? 0 : st->slot + 1;    // slot of level n + 1
-  T* __restrict__ w = D.w[(st->n + 1) & 1];
-  T* __restrict__ P = D.P[ns];
-  T* __restrict__ Q = D.Q[ns];
-  const T dx = D.dx, dy = D.dy, g = D.g, eps = D.eps;
+  T* w = D.w[(st->n + 1) & 1];
+  T* P = D.P[ns];
+  T* Q = D.Q[ns];
+  const gp<T> gw = gbl(w);
+  const gp<T> gP = gbl(P);
+  const gp<T> gQ = gbl(Q);
+  const gp<const T> xhP = gbl((const T*)D.xhP);
+  const gp<const T> xhQ = gbl((const T*)D.xhQ);
+  const gp<const T> spxv = gbl((const T*)D.spxv);
+  const gp<const T> spxw = gbl((const T*)D.spxw);
+  const gp<const T> spyv = gbl((const T*)D.spyv);
+  const gp<const T> spyw = gbl((const T*)D.spyw);
+  const gp<const T> ifx = gbl((const T*)D.ifx);
+  const gp<const T> ify = gbl((const T*)D.ify);
+  const gp<const T> Dbar = gbl((const T*)D.Dbar);
+  const T dx = D.dx, dy = D.dy, g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
   const double dt = st->dt;
-  double smax = 0.0;
+  const size_t CLx = (size_t)D.cx * ny, CLy = (size_t)D.cy * nx;
   constexpr int CPT = (TX * TY) / NT;
+  // all loads first
+  T lp[CPT], lq[CPT], lw[CPT], ld[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int e = tid + q * NT;
+    const int r = e / TX, c = e - r * TX;
+    const int i = min(i0 + c, nx - 1), j = min(j0 + r, ny - 1);
+    const size_t ii = (size_t)j * D.ipitch + i;
+    const size_t ox = (size_t)(i / MX) * ny + j, oy = (size_t)(j / TY) * nx + i;
+    lp[q] = xhP[ii] + spxv[ii] * ifx[ox] + spxw[ii] * ifx[CLx + ox];
+    lq[q] = xhQ[ii] + spyv[ii] * ify[oy] + spyw[ii] * ify[CLy + oy];
+    lw[q] = gw[(size_t)(j + 2) * D.pitch + D.xoff + i];
+    ld[q] = Dbar[ii];
+  }
+  double smax = 0.0;
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int e = tid + q * NT;
     const int r = e / TX, c = e - r * TX;
     const int i = i0 + c, j = j0 + r;
     if (i >= nx || j >= ny) continue;
-    const size_t ii = (size_t)j * D.ipitch + i;
-    const int qx = i / MX, qy = j / TY;
-    const size_t ox = (size_t)qx * ny + j, oy = (size_t)qy * nx + i;
-    const size_t CLx = (size_t)D.cx * ny, CLy = (size_t)D.cy * nx;
-    T p = D.xhP[ii] + D.spxv[ii] * D.ifx[ox] + D.spxw[ii] * D.ifx[CLx + ox];
-    T qv = D.xhQ[ii] + D.spyv[ii] * D.ify[oy] + D.spyw[ii] * D.ify[CLy + oy];
+    T p = lp[q], qv = lq[q], wv = lw[q];
+    const T Db = ld[q];
     const size_t gidx = (size_t)(j + 2) * D.pitch + D.xoff + i;
-    T wv = w[gidx];
-    const T Db = D.Dbar[ii];
     if (D.any_sponge && Db > T(0)) {
       const T dist[4] = {(T(i) + T(0.5)) * dx, (T(nx - i) - T(0.5)) * dx, (T(j) + T(0.5)) * dy,
                          (T(ny - j) - T(0.5)) * dy};
@@ -881,53 +1003,22 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
         wv *= fac;
         p *= fac;
         qv *= fac;
-        w[gidx] = wv;
+        gw[gidx] = wv;
       }
     }
-    P[gidx] = p;
-    Q[gidx] = qv;
+    gP[gidx] = p;
+    gQ[gidx] = qv;
     // Eq. (22) speeds of the new state
     const T h = fmax(wv + Db, T(0));
-    const T u = desing(p, h, eps), v = desing(qv, h, eps);
-    const T cel = sqrt(g * h);
-    T s = fmax((fabs(u) + cel) / dx, (fabs(v) + cel) / dy);
-    double sd = (double)s;
-    if (sd != sd) sd = __longlong_as_double(0x7ff0000000000000ll);
+    const T vf = vfac(h, eps);
+    const T u = p * vf, v = qv * vf;
+    const T cel = fsqrt(g * h);
+    const T sx = (fabs(u) + cel) * idx, sy = (fabs(v) + cel) * idy;
+    // a NaN in either direction must reach the maximum as +inf
+    double sd = (sx != sx || sy != sy) ? __longlong_as_double(0x7ff0000000000000ll) : (double)fmax(sx, sy);
     smax = fmax(smax, sd);
-    // ghost cells of the new state: x sides for interior rows, then y sides
-    // for all columns (corners mirror the x-ghosts)
-    const bool xg = i < 2 || i >= nx - 2, yg = j < 2 || j >= ny - 2;
-    if (xg || yg) {
-      T gwv = wv, gpv = p, gqv = qv;
-      int gi = i;
-      bool have_x = false;
-      if (i < 2) {
-        gi = -1 - i;
-        have_x = true;
-        if (D.bc[0] == SINE || D.bc[0] == IRREGULAR) {
-          gwv = (T)st->gw[i];
-          gpv = (T)st->gP[i];
-          gqv = T(0);
-        } else {
-          gpv = -p;
-        }
-        put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
-      }
-      if (i >= nx - 2) {
-        const int gie = 2 * nx - 1 - i;
-        put3(D, w, P, Q, gie, j, wv, -p, qv);
-        if (!have_x) {
-          gi = gie;
-          gwv = wv; gpv = -p; gqv = qv;
-          have_x = true;
-        }
-      }
-      if (yg) {
-        const int gj = j < 2 ? -1 - j : 2 * ny - 1 - j;
-        put3(D, w, P, Q, i, gj, wv, p, -qv);
-        if (have_x) put3(D, w, P, Q, gi, gj, gwv, gpv, -gqv);
-      }
-    }
+    // ghost cells of the new state
+    if (i < 2 || i >= nx - 2 || j < 2 || j >= ny - 2) ghost_cell(D, w, P, Q, i, j, wv, p, qv, st->gw, st->gP);
   }
   // block max -> one atomic per block
   __shared__ double red[NT / 64];

@@ -97,8 +97,8 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   if (e >= L * C) return;
   const int line = e % L, c = e / L;
   const int s = c * M, m = min(M, n - s);
-  const T h = dir == 0 ? D.dx : D.dy;
-  T Dl[M + 2], r[M], piv[M];
+  const T* tc = dir == 0 ? D.tcx : D.tcy;
+  T Dl[M + 2], r[M];
   for (int k = 0; k < m + 2; ++k) {
     const int q = s - 1 + k;
     Dl[k] = dir == 0 ? cellD(D, q, line) : cellD(D, line, q);
@@ -106,8 +106,8 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   const bool wave_w = dir == 0 && (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
   const bool fold_lo = s == 0 && !wave_w, fold_hi = s + m == n;
   T a0, b0, c0, am, bm, cm;
-  tri_coef(dpos(Dl[0]), dpos(Dl[1]), dpos(Dl[2]), h, D.Bc, a0, b0, c0);
-  tri_coef(dpos(Dl[m - 1]), dpos(Dl[m]), dpos(Dl[m + 1]), h, D.Bc, am, bm, cm);
+  tri_coef(dpos(Dl[0]), dpos(Dl[1]), dpos(Dl[2]), tc, a0, b0, c0);
+  tri_coef(dpos(Dl[m - 1]), dpos(Dl[m]), dpos(Dl[m + 1]), tc, am, bm, cm);
   T* sv = dir == 0 ? D.spxv : D.spyv;
   T* sw = dir == 0 ? D.spxw : D.spyw;
   T* rs = dir == 0 ? D.rsx : D.rsy;
@@ -116,7 +116,7 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   for (int k = 0; k < m; ++k) r[k] = T(0);
   if (c > 0) {
     r[0] = -a0;
-    chunk_solve_db<T, M>(Dl, 1, m, h, D.Bc, fold_lo, fold_hi, r, piv, 1);
+    chunk_solve_db<T, M>(Dl, 1, m, tc, fold_lo, fold_hi, r, 1);
   }
   for (int k = 0; k < m; ++k) {
     const int q = s + k;
@@ -128,7 +128,7 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   for (int k = 0; k < m; ++k) r[k] = T(0);
   if (c < C - 1) {
     r[m - 1] = -cm;
-    chunk_solve_db<T, M>(Dl, 1, m, h, D.Bc, fold_lo, fold_hi, r, piv, 1);
+    chunk_solve_db<T, M>(Dl, 1, m, tc, fold_lo, fold_hi, r, 1);
   }
   for (int k = 0; k < m; ++k) {
     const int q = s + k;
@@ -195,38 +195,6 @@ __global__ void k_setup_waves(const DomDev<T>* Dp, double B) {
 // state transfer, ghosts and diagnostics
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__device__ void ghost_cell(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T wv, T p, T qv, const double* gw,
-                           const double* gP) {
-  const int nx = D.nx, ny = D.ny;
-  const bool yg = j < 2 || j >= ny - 2;
-  T gwv = wv, gpv = p, gqv = qv;
-  int gi = 0;
-  bool have_x = false;
-  if (i < 2) {
-    gi = -1 - i;
-    have_x = true;
-    if (D.bc[0] == SINE || D.bc[0] == IRREGULAR) {
-      gwv = (T)gw[i];
-      gpv = (T)gP[i];
-      gqv = T(0);
-    } else {
-      gpv = -p;
-    }
-    put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
-  } else if (i >= nx - 2) {
-    gi = 2 * nx - 1 - i;
-    have_x = true;
-    gpv = -p;
-    put3(D, w, P, Q, gi, j, gwv, gpv, gqv);
-  }
-  if (yg) {
-    const int gj = j < 2 ? -1 - j : 2 * ny - 1 - j;
-    put3(D, w, P, Q, i, gj, wv, p, -qv);
-    if (have_x) put3(D, w, P, Q, gi, gj, gwv, gpv, -gqv);
-  }
-}
-
 // scatter io (FP64 interior) into level 0: which 0 = eta -> w, 1 = P, 2 = Q
 template <typename T>
 __global__ void k_scatter(const DomDev<T>* Dp, int which, int* bad) {
@@ -263,9 +231,8 @@ __global__ void __launch_bounds__(256) k_init_ghosts(const DomDev<T>* Dp) {
     const T h = fmax(wv + D.Dbar[(size_t)j * D.ipitch + i], T(0));
     const T u = desing(p, h, D.eps), v = desing(qv, h, D.eps);
     const T c = sqrt(D.g * h);
-    double s = (double)fmax((fabs(u) + c) / D.dx, (fabs(v) + c) / D.dy);
-    if (s != s) s = __longlong_as_double(0x7ff0000000000000ll);
-    sm = s;
+    const T sx = (fabs(u) + c) / D.dx, sy = (fabs(v) + c) / D.dy;
+    sm = (sx != sx || sy != sy) ? __longlong_as_double(0x7ff0000000000000ll) : (double)fmax(sx, sy);
   }
   for (int o = 32; o > 0; o >>= 1) sm = fmax(sm, __shfl_xor(sm, o, 64));
   __shared__ double red[4];
@@ -515,6 +482,26 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.B = (T)p->B;
   D.Bc = (T)(p->B + 1.0 / 3.0);
   D.gn2 = (T)(p->g * p->manning_n * p->manning_n);
+  {
+    const double dx = p->dx, dy = p->dy, bc = p->B + 1.0 / 3.0;
+    D.idx = (T)(1.0 / dx);
+    D.idy = (T)(1.0 / dy);
+    D.i2dx = (T)(1.0 / (2.0 * dx));
+    D.i2dy = (T)(1.0 / (2.0 * dy));
+    D.idx2 = (T)(1.0 / (dx * dx));
+    D.idy2 = (T)(1.0 / (dy * dy));
+    D.i4dxdy = (T)(1.0 / (4.0 * dx * dy));
+    D.i2dx3 = (T)(1.0 / (2.0 * dx * dx * dx));
+    D.i2dy3 = (T)(1.0 / (2.0 * dy * dy * dy));
+    D.i2dxdy2 = (T)(1.0 / (2.0 * dx * dy * dy));
+    D.i2dx2dy = (T)(1.0 / (2.0 * dx * dx * dy));
+    D.tcx[0] = (T)(1.0 / (2.0 * dx));
+    D.tcx[1] = (T)(bc / (dx * dx));
+    D.tcx[2] = (T)(1.0 / (6.0 * dx));
+    D.tcy[0] = (T)(1.0 / (2.0 * dy));
+    D.tcy[1] = (T)(bc / (dy * dy));
+    D.tcy[2] = (T)(1.0 / (6.0 * dy));
+  }
   D.theta = (T)p->theta;
   const double eps = p->eps_desing > 0 ? p->eps_desing : fmax(pow(p->dx, 4), pow(p->dy, 4));
   D.eps = (T)eps;

@@ -22,12 +22,13 @@ def mods():
 
 
 def _specs():
-    out = [S.sloping_beach(nx=192, ny=64, dx=0.1, x_toe=2.0, t_end=0.6),
-           S.solitary_flat(nx=160, ny=48, x0=2.0, t_end=0.3),
-           S.rip_beach_scaled(96, 64, cfl=0.125, fstar_order=1, t_end=30.0),
-           S.solitary_flat(nx=300, ny=32, x0=3.0, t_end=0.45)]
-    for s in out:
-        s["params"]["t_end"] = s["t_end"]
+    ends = [0.6, 0.3, 30.0, 0.45]
+    out = [S.sloping_beach(nx=192, ny=64, dx=0.1, x_toe=2.0),
+           S.solitary_flat(nx=160, ny=48, x0=2.0),
+           S.rip_beach_scaled(96, 64, cfl=0.125, fstar_order=1),
+           S.solitary_flat(nx=300, ny=32, x0=3.0)]
+    for s, t in zip(out, ends):
+        s["params"]["t_end"] = t
     return out
 
 
