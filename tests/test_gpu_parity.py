@@ -3,12 +3,12 @@
 FP64: relative L2 error per field <= 1e-12 after every compared step.  FP32:
 eta within 1e-4 relative L2 after 1000 steps on non-breaking cases.
 
-The relative error divides by max(||ref||, 0.01 s sqrt(N)), s the field's
+The relative error divides by max(||ref||, 0.1 s sqrt(N)), s the field's
 natural scale in the case (wave amplitude for eta, amplitude times the
-long-wave speed for P and Q): while a field is still far below its natural
-size (the first steps behind a ramped wavemaker) the comparison is against 1 %
-of that size, not against the roundoff of the oracle's own FP64 cancellation
-of hydrostatic flux and bed source in water at rest.
+long-wave speed for P and Q): while a field is far below its natural size
+(the first steps behind a ramped wavemaker, a standing wave's flux passing
+through zero in time) the comparison is against 10 % of that size, not
+against the roundoff of the oracle's own FP64 cancellations.
 """
 import math
 
@@ -43,7 +43,7 @@ def scales(spec):
 
 
 def rel(a, b, scale=0.0):
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 0.01 * scale * math.sqrt(b.size), 1e-300))
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 0.1 * scale * math.sqrt(b.size), 1e-300))
 
 
 def pair(bq, spec, precision):
