@@ -160,10 +160,25 @@ int bq_batch_step(bq_batch* b, int32_t n_steps);
 int bq_batch_sync(bq_batch* b);
 int bq_batch_free(bq_batch* b);
 
+/* Launch lanes of a batch (1 or 2; default 2).  With 2 lanes the members are
+ * split into two groups of about equal cell count and each group is advanced
+ * on its own stream: the batch's stream and one the batch owns, joined to
+ * the batch's stream by events at the end of every bq_batch_step, so the
+ * caller sees one stream.  One group's stencil/update kernel (arithmetic
+ * bound) then runs beside the other group's line-coupling and finalize
+ * kernels (latency and bandwidth bound).  Each domain's arithmetic is the
+ * same for any lane count, so results are bitwise identical.  Changing the
+ * lane count waits for the batch's queued work.  bq_batch_lanes returns the
+ * lanes in use (1 when the batch has one member). */
+int bq_batch_set_lanes(bq_batch* b, int32_t lanes);
+int bq_batch_lanes(const bq_batch* b);
+
 /* Timing of the step's four kernels (Delta t, stencil + AB3 + local solves,
  * line coupling, finalize): runs n_steps plain launches with hipEvents around
- * every kernel on the launch stream and returns the mean duration of each in
- * ms_out[4].  The steps advance the state like bq_step / bq_batch_step. */
+ * every kernel on the launch stream and returns the mean duration of one
+ * launch of each in ms_out[4].  A two-lane batch runs both lanes at once, as
+ * bq_batch_step does, each launch covering one group.  The steps advance the
+ * state like bq_step / bq_batch_step. */
 int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out);
 int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
 

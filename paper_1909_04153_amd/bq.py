@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
 EXPORTS = ["bq_abi_version", "bq_last_error", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
            "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
            "bq_batch_create", "bq_batch_set", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
-           "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps"]
+           "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps",
+           "bq_batch_set_lanes", "bq_batch_lanes"]
 KERNELS = ("k_dt", "k_rhs", "k_reduced", "k_final")
 
 _lib = None
@@ -93,6 +94,8 @@ def load(path: str | None = None):
     L.bq_batch_set_graph_steps.argtypes = [vp, ip]
     L.bq_profile_steps.argtypes = [vp, ip, dp]
     L.bq_batch_profile_steps.argtypes = [vp, ip, dp]
+    L.bq_batch_set_lanes.argtypes = [vp, ip]
+    L.bq_batch_lanes.argtypes = [vp]
     if L.bq_abi_version() != 1:
         raise RuntimeError("libbq ABI version mismatch")
     if path is None:
@@ -251,7 +254,7 @@ class Domain:
 class Batch:
     """Domains of one precision advanced together by one launch per phase."""
 
-    def __init__(self, domains, stream=None):
+    def __init__(self, domains, stream=None, lanes: int = 2):
         torch = _torch()
         self.domains = list(domains)
         self.stream = stream if stream is not None else torch.cuda.Stream()
@@ -260,6 +263,15 @@ class Batch:
         _check(load().bq_batch_create(arr, len(self.domains), ctypes.c_void_p(self.stream.cuda_stream),
                                       ctypes.byref(h)))
         self._h = h
+        if lanes != 2:
+            self.set_lanes(lanes)
+
+    def set_lanes(self, lanes: int):
+        _check(load().bq_batch_set_lanes(self._h, int(lanes)))
+
+    @property
+    def lanes(self) -> int:
+        return int(load().bq_batch_lanes(self._h))
 
     def set(self, domains):
         self.domains = list(domains)
@@ -282,7 +294,7 @@ class Batch:
 
     def close(self):
         if getattr(self, "_h", None):
-            self.stream.synchronize()
+            load().bq_batch_sync(self._h)
             load().bq_batch_free(self._h)
             self._h = None
 

@@ -6,7 +6,7 @@
 //     multiple of 256 B and interior column 0 256-B aligned:
 //       w[2] (double-buffered), P[3], Q[3] (rings: slot n % 3 = level n);
 //   * interior-only fields: E, F, G rings (slot n % 3), local solutions
-//     xhP, xhQ, spikes of the chunked line solves, cell still-water depth;
+//     xhP, xhQ of the chunked line solves, cell still-water depth;
 //   * corner still-water depth Dc with two mirrored ghost corner layers;
 //   * per-chunk boundary/interface values of the line solves, [chunk][line];
 //   * one FP64 DevState: time, Delta t history, weights, status.
@@ -21,8 +21,9 @@
 //             tridiagonal solves of Eq. (19)-(20) for the P, Q increments;
 //   k_reduced per line: the chunk-interface recurrence that couples the
 //             chunk-local solutions into the exact line solution;
-//   k_final   pointwise: P, Q = local solution + spike corrections, sponge,
-//             ghost cells of the new state, CFL maximum of the new state.
+//   k_final   P, Q = local solution + the chunk systems' response to the
+//             neighbour-chunk values, sponge, ghost cells of the new state,
+//             CFL maximum of the new state.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -85,10 +86,6 @@ struct DomDev {
   T* Dbar;
   T* xhP;
   T* xhQ;
-  T* spxv;
-  T* spxw;
-  T* spyv;
-  T* spyw;
   T* chx;                   // [2][cx][ny]: local solution at chunk first / last
   T* chy;                   // [2][cy][nx]
   T* rsx;                   // [6][cx][ny]: static interface-recurrence coefficients
@@ -130,18 +127,29 @@ template <> __device__ __forceinline__ float frcbrt<float>(float x) {
   return __builtin_amdgcn_exp2f(-0.33333333f * __builtin_amdgcn_logf(x));
 }
 
+// generalised minmod of three values: the one nearest zero when all three
+// share a sign, else zero
 template <typename T>
 __device__ __forceinline__ T gmm(T a, T b, T c) {
   const T lo = fmin(a, fmin(b, c));
   const T hi = fmax(a, fmax(b, c));
   return lo > T(0) ? lo : (hi < T(0) ? hi : T(0));
 }
+// FP32: med3(a, c, 0) is minmod(a, c), and minmod(minmod(a, c), b) is the
+// same value as above, in two median-of-three instructions
+template <>
+__device__ __forceinline__ float gmm<float>(float a, float b, float c) {
+  return __builtin_amdgcn_fmed3f(__builtin_amdgcn_fmed3f(a, c, 0.0f), b, 0.0f);
+}
 
-// limited slope (times the cell size) of q at a cell from its two neighbours
+// half the limited slope (times the cell size) of q at a cell from its two
+// neighbours, ht = theta / 2: minmod(ht (q0 - qm), (qp - qm) / 4, ht (qp - q0));
+// theta = 0 selects the unlimited central slope.  Halving is exact, so the
+// face values q0 -/+ hslope equal q0 -/+ slope / 2.
 template <typename T>
-__device__ __forceinline__ T slope(T qm, T q0, T qp, T theta) {
-  const T c = T(0.5) * (qp - qm);
-  return theta > T(0) ? gmm(theta * (q0 - qm), c, theta * (qp - q0)) : c;
+__device__ __forceinline__ T hslope(T qm, T q0, T qp, T ht) {
+  const T c = T(0.25) * (qp - qm);
+  return ht > T(0) ? gmm(ht * (q0 - qm), c, ht * (qp - q0)) : c;
 }
 
 // Velocity factor of the KP07 desingularisation, u = q * vfac(h):
@@ -174,10 +182,10 @@ __device__ __forceinline__ T dpos(T D) {
 // Piecewise-linear w at a cell's low/high faces with the KP07 positivity
 // correction; Dlo/Dhi are the still-water depths at the faces (bed = -D).
 template <typename T>
-__device__ __forceinline__ void recon_w(T wm, T w0, T wp, T theta, T Dlo, T Dhi, T& wlo, T& whi) {
-  const T s = slope(wm, w0, wp, theta);
-  wlo = w0 - T(0.5) * s;
-  whi = w0 + T(0.5) * s;
+__device__ __forceinline__ void recon_w(T wm, T w0, T wp, T ht, T Dlo, T Dhi, T& wlo, T& whi) {
+  const T s = hslope(wm, w0, wp, ht);
+  wlo = w0 - s;
+  whi = w0 + s;
   if (whi + Dhi < T(0)) {
     whi = -Dhi;
     wlo = T(2) * w0 + Dhi;
@@ -197,7 +205,7 @@ __device__ __forceinline__ void recon_w(T wm, T w0, T wp, T theta, T Dlo, T Dhi,
 // difference of large numbers in deep water.
 template <typename T>
 struct Side {
-  T w, h, un, ut, qn, qt, pp;
+  T w, h, un, ut, qn, qt, dev, pp;
 };
 
 template <typename T>
@@ -205,14 +213,25 @@ __device__ __forceinline__ Side<T> make_side(T w, T qn, T qt, T Dface, T eps, T 
   Side<T> s;
   s.w = w;
   s.h = fmax(w + Dface, T(0));
-  const T vf = vfac(s.h, eps);
-  s.un = qn * vf;
-  s.ut = qt * vf;
-  s.qn = s.h * s.un;
-  s.qt = s.h * s.ut;
+  const T h2 = s.h * s.h;
+  const T h4 = h2 * h2;
+  if (h4 >= eps) {
+    // u = q / h, and the recomputed discharge h u is q itself
+    const T vf = frcp(s.h);
+    s.un = qn * vf;
+    s.ut = qt * vf;
+    s.qn = qn;
+    s.qt = qt;
+  } else {
+    const T vf = T(1.4142135623730951) * s.h * frcp(fsqrt(h4 + eps));
+    s.un = qn * vf;
+    s.ut = qt * vf;
+    s.qn = s.h * s.un;
+    s.qt = s.h * s.ut;
+  }
   const T Dp = fmax(Dface, T(0));
-  const T dev = Dface > T(0) ? (s.h > T(0) ? w : -Dface) : s.h;
-  s.pp = T(0.5) * g * dev * (s.h + Dp);
+  s.dev = Dface > T(0) ? (s.h > T(0) ? w : -Dface) : s.h;
+  s.pp = T(0.5) * g * s.dev * (s.h + Dp);
   return s;
 }
 
@@ -275,11 +294,12 @@ __device__ __forceinline__ void tri_coef(T dm, T d0, T dp, const T* tc, T& a, T&
 // each side (d = max(D, 0)); tc are the Eq. (21) constants of the direction.
 // fold_lo / fold_hi fold the odd mirror of a wall into the first / last
 // diagonal.  rhs (stride rs) is overwritten with the solution; the reciprocal
-// pivots stay in registers (the loops are unrolled over M).
+// pivots and the upper diagonal stay in registers (the loops are unrolled
+// over M).
 template <typename T, int M>
 __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
                                                T* rhs, int rs) {
-  T piv[M];
+  T piv[M], up[M];
   T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -300,6 +320,7 @@ __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const
       }
       const T iu = frcp(u);
       piv[k] = iu;
+      up[k] = c;
       rhs[k * rs] = y;
       y_prev = y;
       iu_prev = iu;
@@ -310,13 +331,62 @@ __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const
 #pragma unroll
   for (int k = M - 1; k >= 0; --k) {
     if (k < m) {
-      T a, b, c;
-      tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
       const T y = rhs[k * rs];
-      const T x = (k == m - 1) ? y * piv[k] : (y - c * x_next) * piv[k];
+      const T x = (k == m - 1) ? y * piv[k] : (y - up[k] * x_next) * piv[k];
       rhs[k * rs] = x;
       x_next = x;
     }
+  }
+}
+
+// Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
+// own L2): block b runs on XCD b % 8.  Renumber so that every XCD walks a
+// contiguous run of tiles; a tile's halo rows and columns are then mostly
+// the neighbour tiles' interiors, fetched from HBM once into the same L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int xcd = b % NXCD, local = b / NXCD;
+  const int per = nb / NXCD, rem = nb % NXCD;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// The same solve for kernels that must stay light on registers: the
+// reciprocal pivots go to LDS (pv, stride rs) and the upper diagonal is
+// recomputed in the backward sweep.
+template <typename T>
+__device__ __forceinline__ void chunk_solve_lds(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                                T* rhs, T* pv, int rs) {
+  T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
+  for (int k = 0; k < m; ++k) {
+    T a, b, c;
+    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+    if (k == 0 && fold_lo) b -= a;
+    if (k == m - 1 && fold_hi) b -= c;
+    const T r = rhs[k * rs];
+    T u, y;
+    if (k == 0) {
+      u = b;
+      y = r;
+    } else {
+      const T l = a * iu_prev;
+      u = b - l * c_prev;
+      y = r - l * y_prev;
+    }
+    const T iu = frcp(u);
+    pv[k * rs] = iu;
+    rhs[k * rs] = y;
+    y_prev = y;
+    iu_prev = iu;
+    c_prev = c;
+  }
+  T x_next = rhs[(m - 1) * rs] * pv[(m - 1) * rs];
+  rhs[(m - 1) * rs] = x_next;
+  for (int k = m - 2; k >= 0; --k) {
+    T a, b, c;
+    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+    const T x = (rhs[k * rs] - c * x_next) * pv[k * rs];
+    rhs[k * rs] = x;
+    x_next = x;
   }
 }
 
@@ -470,7 +540,7 @@ __global__ void k_commit(const DomDev<T>* __restrict__ doms, int nd) {
 // ---------------------------------------------------------------------------
 
 template <typename T, int TY, int MX>
-struct RhsSmem {
+struct alignas(16) RhsSmem {
   static constexpr int WX = TX + 4, WY = TY + 4;      // radius-2 tiles
   static constexpr int BX = TX + 2, BY = TY + 2;      // radius-1 tiles
   static constexpr int CXN = TX + 5, CYN = TY + 5;    // corners
@@ -481,16 +551,14 @@ struct RhsSmem {
   T db[WY * WX];                                      // cell still-water depth
   T pt[BY * BX];                                      // sum_k beta_k P^{n-k}
   T qt[BY * BX];
-  T dc[CYN * CXN];
-  static constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
-  static constexpr int NF = NFX > NFY ? NFX : NFY;
   union {
-    T f[3][NF];                                       // x-face, then y-face fluxes
+    T ax[3][TY * TX];                                 // x-direction parts of E, F, G per cell
     struct {
       T u[TY * TXP];
       T v[TY * TXP];
     } s;
   } x;
+  T dc[CYN * CXN];
 };
 
 template <typename T, int TY, int MX>
@@ -504,11 +572,12 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   constexpr int CPT = (TX * TY) / NT;                 // cells per thread
   static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
   __shared__ S sm;
-  const int dom = find_domain(tile_prefix, nd, blockIdx.x);
+  const int bt = xcd_tile(blockIdx.x, gridDim.x);
+  const int dom = find_domain(tile_prefix, nd, bt);
   const DomDev<T>& D = doms[dom];
   const DevState* st = D.st;
   if (st->halt) return;
-  const int tile = blockIdx.x - tile_prefix[dom];
+  const int tile = bt - tile_prefix[dom];
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int slot = st->slot;
@@ -524,6 +593,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   const T beta0 = (T)st->beta[0], beta1 = (T)st->beta[1], beta2 = (T)st->beta[2];
   const bool hist = st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
   const int pitch = D.pitch, xoff = D.xoff, ipitch = D.ipitch;
+  // Cells of a thread in the per-cell phases: column cY, rows rY0 .. rY0+CPT-1
+  // (consecutive rows, so the vertical stencils of a thread's cells overlap).
+  const int cY = tid % TX, rY0 = (tid / TX) * CPT;
+  static_assert((NT / TX) * CPT == TY, "per-cell mapping covers the tile");
 
   // ---- phase 0: issue every load of the tile before the first LDS store ----
   // E, F, G history of this thread's cells (consumed in phase 2)
@@ -537,9 +610,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const gp<const T> G2 = gbl((const T*)D.G[s2]);
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-      const int e = tid + q * NT;
-      const int r = e / TX, c = e - r * TX;
-      const int i = min(i0 + c, nx - 1), j = min(j0 + r, ny - 1);
+      const int i = min(i0 + cY, nx - 1), j = min(j0 + rY0 + q, ny - 1);
       const size_t ii = (size_t)j * ipitch + i;
       he1[q] = E1[ii]; he2[q] = E2[ii];
       hf1[q] = F1[ii]; hf2[q] = F2[ii];
@@ -608,77 +679,109 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
                      sm.dc[(r + 1) * CXN + c + 1]);
   }
 
-  const T g = D.g, eps = D.eps, theta = D.theta;
-  // ---- phase 1: face fluxes ----------------------------------------------
-  for (int e = tid; e < TY * (TX + 1); e += NT) {
-    const int r = e / (TX + 1), f = e - r * (TX + 1);
-    const int row = (r + 2) * WX;
-    // cells L = column f + 1, R = column f + 2 of the radius-2 tile
-    const T* cw = sm.dc + (r + 2) * CXN;          // corners of the face row
-    const T* cn = sm.dc + (r + 3) * CXN;
-    const T Dl = T(0.5) * (cw[f + 1] + cn[f + 1]);  // face between L-1 and L
-    const T Df = T(0.5) * (cw[f + 2] + cn[f + 2]);  // the face
-    const T Dr = T(0.5) * (cw[f + 3] + cn[f + 3]);  // face between R and R+1
-    T wLl, wLh, wRl, wRh;
-    recon_w(sm.w[row + f], sm.w[row + f + 1], sm.w[row + f + 2], theta, Dl, Df, wLl, wLh);
-    recon_w(sm.w[row + f + 1], sm.w[row + f + 2], sm.w[row + f + 3], theta, Df, Dr, wRl, wRh);
-    const T sPL = slope(sm.p[row + f], sm.p[row + f + 1], sm.p[row + f + 2], theta);
-    const T sPR = slope(sm.p[row + f + 1], sm.p[row + f + 2], sm.p[row + f + 3], theta);
-    const T sQL = slope(sm.q[row + f], sm.q[row + f + 1], sm.q[row + f + 2], theta);
-    const T sQR = slope(sm.q[row + f + 1], sm.q[row + f + 2], sm.q[row + f + 3], theta);
-    const Side<T> L = make_side(wLh, sm.p[row + f + 1] + T(0.5) * sPL, sm.q[row + f + 1] + T(0.5) * sQL, Df, eps, g);
-    const Side<T> R = make_side(wRl, sm.p[row + f + 2] - T(0.5) * sPR, sm.q[row + f + 2] - T(0.5) * sQR, Df, eps, g);
-    T f0, fn, ft;
-    cu_flux(L, R, g, Df, f0, fn, ft);
-    sm.x.f[0][e] = f0;
-    sm.x.f[1][e] = fn;
-    sm.x.f[2][e] = ft;
-  }
-  __syncthreads();
-  // x-flux differences of this thread's cells, then the buffer takes the
-  // y-face fluxes
-  T acc_e[CPT], acc_f[CPT], acc_g[CPT];
+  const T g = D.g, eps = D.eps, ht = T(0.5) * D.theta;
+  const T idx = D.idx, idy = D.idy;
+  // ---- phase 1x: x-faces by row segments ----------------------------------
+  // Thread (row rx, cells cx0 .. cx0+CPT-1) reconstructs cells cx0-1 ..
+  // cx0+CPT once, takes the CPT+1 faces between them (the last one is also
+  // its right neighbour's first) and writes the x-parts of its cells' E, F, G
+  // (flux differences plus the x bed-slope source) to LDS.
+  constexpr int SPR = TX / CPT;
+  static_assert(SPR * TY == NT, "one x-segment per thread");
   {
-    const T idx = D.idx;
+    const int rx = tid / SPR, cx0 = (tid - rx * SPR) * CPT;
+    const T* wr = sm.w + (rx + 2) * WX + cx0;         // tile column cx0 = cell cx0 - 2
+    const T* pr = sm.p + (rx + 2) * WX + cx0;
+    const T* qr = sm.q + (rx + 2) * WX + cx0;
+    const T* c0 = sm.dc + (rx + 2) * CXN + cx0 + 1;   // corners of face cx0 - 1
+    T Dfx[CPT + 3];                                   // still-water depth of face cx0 - 1 + k
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int e = tid + q * NT;
-      const int r = e / TX, c = e - r * TX;
-      const int fxw = r * (TX + 1) + c;
-      acc_e[q] = -(sm.x.f[0][fxw + 1] - sm.x.f[0][fxw]) * idx;
-      acc_f[q] = -(sm.x.f[1][fxw + 1] - sm.x.f[1][fxw]) * idx;
-      acc_g[q] = -(sm.x.f[2][fxw + 1] - sm.x.f[2][fxw]) * idx;
+    for (int k = 0; k < CPT + 3; ++k) Dfx[k] = T(0.5) * (c0[k] + c0[k + CXN]);
+    // cell cx0 - 1 + k at its low (l) and high (h) faces
+    T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
+#pragma unroll
+    for (int k = 0; k < CPT + 2; ++k) {
+      recon_w(wr[k], wr[k + 1], wr[k + 2], ht, Dfx[k], Dfx[k + 1], wl[k], wh[k]);
+      const T sp = hslope(pr[k], pr[k + 1], pr[k + 2], ht);
+      const T sq = hslope(qr[k], qr[k + 1], qr[k + 2], ht);
+      pl[k] = pr[k + 1] - sp;
+      ph[k] = pr[k + 1] + sp;
+      ql[k] = qr[k + 1] - sq;
+      qh[k] = qr[k + 1] + sq;
+    }
+    T f0w = T(0), fnw = T(0), ftw = T(0), dvw = T(0);  // west face of the cell being closed
+#pragma unroll
+    for (int m = 0; m <= CPT; ++m) {
+      // face cx0 + m between cells cx0 + m - 1 (k = m) and cx0 + m (k = m + 1)
+      const T Df = Dfx[m + 1];
+      const Side<T> L = make_side(wh[m], ph[m], qh[m], Df, eps, g);
+      const Side<T> R = make_side(wl[m + 1], pl[m + 1], ql[m + 1], Df, eps, g);
+      T f0, fn, ft;
+      cu_flux(L, R, g, Df, f0, fn, ft);
+      if (m > 0) {
+        // cell cx0 + m - 1: well-balanced bed source -g h b_x with h the mean
+        // of its own face depths; with the still-water parts of the pressure
+        // fluxes taken out only the face-depth departures remain
+        const T Dw = Dfx[m], De = Dfx[m + 1];
+        const T bed = g * (De - Dw) * (T(0.5) * (L.dev + dvw)) + shore_term(Dw, De, g);
+        const int o = rx * TX + cx0 + m - 1;
+        sm.x.ax[0][o] = -(f0 - f0w) * idx;
+        sm.x.ax[1][o] = (bed - (fn - fnw)) * idx;
+        sm.x.ax[2][o] = -(ft - ftw) * idx;
+      }
+      f0w = f0;
+      fnw = fn;
+      ftw = ft;
+      dvw = R.dev;
     }
   }
-  __syncthreads();
-  for (int e = tid; e < (TY + 1) * TX; e += NT) {
-    const int gy = e / TX, c = e - gy * TX;
-    const int col = c + 2;
-    // cells S = row gy + 1, N = row gy + 2 of the radius-2 tile
-    const T Ds = T(0.5) * (sm.dc[(gy + 1) * CXN + col] + sm.dc[(gy + 1) * CXN + col + 1]);
-    const T Df = T(0.5) * (sm.dc[(gy + 2) * CXN + col] + sm.dc[(gy + 2) * CXN + col + 1]);
-    const T Dn = T(0.5) * (sm.dc[(gy + 3) * CXN + col] + sm.dc[(gy + 3) * CXN + col + 1]);
-    const int r0 = gy * WX + col, r1 = r0 + WX, r2 = r1 + WX, r3 = r2 + WX;
-    T wSl, wSh, wNl, wNh;
-    recon_w(sm.w[r0], sm.w[r1], sm.w[r2], theta, Ds, Df, wSl, wSh);
-    recon_w(sm.w[r1], sm.w[r2], sm.w[r3], theta, Df, Dn, wNl, wNh);
-    const T sQS = slope(sm.q[r0], sm.q[r1], sm.q[r2], theta);
-    const T sQN = slope(sm.q[r1], sm.q[r2], sm.q[r3], theta);
-    const T sPS = slope(sm.p[r0], sm.p[r1], sm.p[r2], theta);
-    const T sPN = slope(sm.p[r1], sm.p[r2], sm.p[r3], theta);
-    // normal = Q, tangential = P
-    const Side<T> Sd = make_side(wSh, sm.q[r1] + T(0.5) * sQS, sm.p[r1] + T(0.5) * sPS, Df, eps, g);
-    const Side<T> Nd = make_side(wNl, sm.q[r2] - T(0.5) * sQN, sm.p[r2] - T(0.5) * sPN, Df, eps, g);
-    T f0, fn, ft;
-    cu_flux(Sd, Nd, g, Df, f0, fn, ft);
-    sm.x.f[0][e] = f0;
-    sm.x.f[1][e] = ft;   // x-momentum flux through a y-face
-    sm.x.f[2][e] = fn;   // y-momentum flux through a y-face
+  // ---- phase 1y: y-faces by column segments, kept in registers ---------------
+  // normal = Q, tangential = P; thread cells (rY0 + q, cY)
+  T acc_e[CPT], acc_f[CPT], acc_g[CPT];
+  {
+    const T* wc = sm.w + rY0 * WX + cY + 2;           // tile row rY0 = row rY0 - 2
+    const T* pc = sm.p + rY0 * WX + cY + 2;
+    const T* qc = sm.q + rY0 * WX + cY + 2;
+    const T* c0 = sm.dc + (rY0 + 1) * CXN + cY + 2;   // corners of face rY0 - 1
+    T Dfy[CPT + 3];
+#pragma unroll
+    for (int k = 0; k < CPT + 3; ++k) Dfy[k] = T(0.5) * (c0[k * CXN] + c0[k * CXN + 1]);
+    T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
+#pragma unroll
+    for (int k = 0; k < CPT + 2; ++k) {
+      recon_w(wc[k * WX], wc[(k + 1) * WX], wc[(k + 2) * WX], ht, Dfy[k], Dfy[k + 1], wl[k], wh[k]);
+      const T sp = hslope(pc[k * WX], pc[(k + 1) * WX], pc[(k + 2) * WX], ht);
+      const T sq = hslope(qc[k * WX], qc[(k + 1) * WX], qc[(k + 2) * WX], ht);
+      pl[k] = pc[(k + 1) * WX] - sp;
+      ph[k] = pc[(k + 1) * WX] + sp;
+      ql[k] = qc[(k + 1) * WX] - sq;
+      qh[k] = qc[(k + 1) * WX] + sq;
+    }
+    T f0s = T(0), fns = T(0), fts = T(0), dvs = T(0);
+#pragma unroll
+    for (int m = 0; m <= CPT; ++m) {
+      const T Df = Dfy[m + 1];
+      const Side<T> Sd = make_side(wh[m], qh[m], ph[m], Df, eps, g);
+      const Side<T> Nd = make_side(wl[m + 1], ql[m + 1], pl[m + 1], Df, eps, g);
+      T f0, fn, ft;
+      cu_flux(Sd, Nd, g, Df, f0, fn, ft);
+      if (m > 0) {
+        const T Ds = Dfy[m], Dn = Dfy[m + 1];
+        const T bed = g * (Dn - Ds) * (T(0.5) * (Sd.dev + dvs)) + shore_term(Ds, Dn, g);
+        acc_e[m - 1] = -(f0 - f0s) * idy;
+        acc_f[m - 1] = -(ft - fts) * idy;              // x-momentum through y-faces
+        acc_g[m - 1] = (bed - (fn - fns)) * idy;       // y-momentum
+      }
+      f0s = f0;
+      fns = fn;
+      fts = ft;
+      dvs = Nd.dev;
+    }
   }
   __syncthreads();
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
-  const T idx = D.idx, idy = D.idy, B = D.B, Bc = D.Bc, gn2 = D.gn2;
+  const T B = D.B, Bc = D.Bc, gn2 = D.gn2;
   const T a0 = (T)st->alpha[0], a1 = (T)st->alpha[1], a2 = (T)st->alpha[2];
   const gp<T> wn = gbl(D.w[(st->n + 1) & 1]);
   const gp<T> E0 = gbl(D.E[slot]);
@@ -687,31 +790,16 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   T ures[CPT], vres[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
-    const int e = tid + q * NT;
-    const int r = e / TX, c = e - r * TX;
+    const int r = rY0 + q, c = cY;
     const int i = i0 + c, j = j0 + r;
     ures[q] = T(0);
     vres[q] = T(0);
     if (i >= nx || j >= ny) continue;
     const int C0 = (r + 2) * WX + c + 2;   // radius-2 tile index of the cell
-    const int fyS = r * TX + c;
-    T e_ = acc_e[q] - (sm.x.f[0][fyS + TX] - sm.x.f[0][fyS]) * idy;
-    T f_ = acc_f[q] - (sm.x.f[1][fyS + TX] - sm.x.f[1][fyS]) * idy;
-    T g_ = acc_g[q] - (sm.x.f[2][fyS + TX] - sm.x.f[2][fyS]) * idy;
-    // well-balanced bed slope source -g h b_x with h the mean of the cell's
-    // own face depths; only the departure of those depths from the face
-    // still-water depths remains once the still-water parts cancel against
-    // the pressure fluxes
-    {
-      const T* cr = sm.dc + (r + 2) * CXN + c + 2;   // corner (i, j)
-      const T Dw = T(0.5) * (cr[0] + cr[CXN]), De = T(0.5) * (cr[1] + cr[CXN + 1]);
-      const T Ds = T(0.5) * (cr[0] + cr[1]), Dn = T(0.5) * (cr[CXN] + cr[CXN + 1]);
-      T wl, wh;
-      recon_w(sm.w[C0 - 1], sm.w[C0], sm.w[C0 + 1], theta, Dw, De, wl, wh);
-      f_ += (g * (De - Dw) * (T(0.5) * (face_dev(wh, De) + face_dev(wl, Dw))) + shore_term(Dw, De, g)) * idx;
-      recon_w(sm.w[C0 - WX], sm.w[C0], sm.w[C0 + WX], theta, Ds, Dn, wl, wh);
-      g_ += (g * (Dn - Ds) * (T(0.5) * (face_dev(wh, Dn) + face_dev(wl, Ds))) + shore_term(Ds, Dn, g)) * idy;
-    }
+    const int o = r * TX + c;
+    T e_ = sm.x.ax[0][o] + acc_e[q];
+    T f_ = sm.x.ax[1][o] + acc_f[q];
+    T g_ = sm.x.ax[2][o] + acc_g[q];
     const T Db = sm.db[C0];
     const T d0 = dpos(Db);
     const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
@@ -768,13 +856,11 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     ures[q] = (a0 * f_ + a1 * hf1[q] + a2 * hf2[q]) + fs;
     vres[q] = (a0 * g_ + a1 * hg1[q] + a2 * hg2[q]) + gs;
   }
-  __syncthreads();  // fluxes consumed; the union now holds U*, V*
+  __syncthreads();  // x-parts consumed; the union now holds U*, V*
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
-    const int e = tid + q * NT;
-    const int r = e / TX, c = e - r * TX;
-    sm.x.s.u[r * TXP + c] = ures[q];
-    sm.x.s.v[r * TXP + c] = vres[q];
+    sm.x.s.u[(rY0 + q) * TXP + cY] = ures[q];
+    sm.x.s.v[(rY0 + q) * TXP + cY] = vres[q];
   }
   __syncthreads();
 
@@ -933,8 +1019,25 @@ __device__ void ghost_cell(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T
 }
 
 template <typename T, int TY, int MX>
+struct alignas(16) FinSmem {
+  static constexpr int CXN = TX + 3, CYN = TY + 3;    // corners of cells i0-1 .. i0+TX, j0-1 .. j0+TY
+  static constexpr int BX = TX + 2, BY = TY + 2;      // cells with one neighbour on each side
+  static constexpr int TXP = TX + 1;
+  T dc[CYN * CXN];
+  T db[BY * BX];                                      // cell still-water depth
+  T cx[TY * TXP];                                     // x-line correction of P
+  T cy[TY * TXP];                                     // y-line correction of Q
+  T px[TY * TXP];                                     // reciprocal pivots of the x solves
+  T py[TY * TXP];                                     // and of the y solves
+};
+
+template <typename T, int TY, int MX>
 __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_prefix,
                                              int nd) {
+  using S = FinSmem<T, TY, MX>;
+  constexpr int CXN = S::CXN, BX = S::BX, TXP = S::TXP;
+  constexpr int NWC = (S::CYN * CXN + NT - 1) / NT;
+  __shared__ S sm;
   const int dom = find_domain(tile_prefix, nd, blockIdx.x);
   const DomDev<T>& D = doms[dom];
   DevState* st = D.st;
@@ -951,30 +1054,98 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   const gp<T> gQ = gbl(Q);
   const gp<const T> xhP = gbl((const T*)D.xhP);
   const gp<const T> xhQ = gbl((const T*)D.xhQ);
-  const gp<const T> spxv = gbl((const T*)D.spxv);
-  const gp<const T> spxw = gbl((const T*)D.spxw);
-  const gp<const T> spyv = gbl((const T*)D.spyv);
-  const gp<const T> spyw = gbl((const T*)D.spyw);
   const gp<const T> ifx = gbl((const T*)D.ifx);
   const gp<const T> ify = gbl((const T*)D.ify);
-  const gp<const T> Dbar = gbl((const T*)D.Dbar);
+  const gp<const T> Dc = gbl((const T*)D.Dc);
   const T dx = D.dx, dy = D.dy, g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
   const double dt = st->dt;
-  const size_t CLx = (size_t)D.cx * ny, CLy = (size_t)D.cy * nx;
   constexpr int CPT = (TX * TY) / NT;
-  // all loads first
-  T lp[CPT], lq[CPT], lw[CPT], ld[CPT];
+  // all loads first: corners of the tile's cells and their neighbours, the
+  // local solutions and the new surface
+  T rc[NWC];
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) {
+    const int e = min(tid + k * NT, S::CYN * CXN - 1);
+    const int r = e / CXN, c = e - r * CXN;
+    const int ic = min(i0 + c - 1, nx + 2), jc = min(j0 + r - 1, ny + 2);
+    rc[k] = Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
+  }
+  T lp[CPT], lq[CPT], lw[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int e = tid + q * NT;
     const int r = e / TX, c = e - r * TX;
     const int i = min(i0 + c, nx - 1), j = min(j0 + r, ny - 1);
     const size_t ii = (size_t)j * D.ipitch + i;
-    const size_t ox = (size_t)(i / MX) * ny + j, oy = (size_t)(j / TY) * nx + i;
-    lp[q] = xhP[ii] + spxv[ii] * ifx[ox] + spxw[ii] * ifx[CLx + ox];
-    lq[q] = xhQ[ii] + spyv[ii] * ify[oy] + spyw[ii] * ify[CLy + oy];
+    lp[q] = xhP[ii];
+    lq[q] = xhQ[ii];
     lw[q] = gw[(size_t)(j + 2) * D.pitch + D.xoff + i];
-    ld[q] = Dbar[ii];
+  }
+#pragma unroll
+  for (int k = 0; k < NWC; ++k) {
+    const int e = tid + k * NT;
+    if (e < S::CYN * CXN) sm.dc[e] = rc[k];
+  }
+  __syncthreads();
+  for (int e = tid; e < S::BY * BX; e += NT) {
+    const int r = e / BX, c = e - r * BX;
+    sm.db[e] = dbar4(sm.dc[r * CXN + c], sm.dc[r * CXN + c + 1], sm.dc[(r + 1) * CXN + c],
+                     sm.dc[(r + 1) * CXN + c + 1]);
+  }
+  __syncthreads();
+  // Exact line solution = local solution + the response of the chunk system
+  // to its coupling with the neighbour chunks' end values (from the
+  // line-coupling kernel): a right-hand side that is zero except -a x_left
+  // in the first row and -c x_right in the last.  The response is solved
+  // here from the static matrix instead of read as stored spikes.
+  constexpr int NCX = TX / MX;
+  const bool wave_w = (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
+  if (tid < TY * NCX) {
+    const int r = tid / NCX, qc = tid - r * NCX;
+    const int j = j0 + r, is = i0 + qc * MX;
+    if (j < ny && is < nx) {
+      const int m = min(MX, nx - is);
+      const T* dlx = sm.db + (r + 1) * BX + qc * MX;   // cells is-1 .. is+m
+      T* rhs = sm.cx + r * TXP + qc * MX;
+      const size_t o = (size_t)(is / MX) * ny + j;
+      const T xl = ifx[o], xr = ifx[(size_t)D.cx * ny + o];
+      T a, b, c0, cm;
+      tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c0);
+      const T r0 = -a * xl;
+      tri_coef(dpos(dlx[m - 1]), dpos(dlx[m]), dpos(dlx[m + 1]), D.tcx, a, b, cm);
+      for (int k = 0; k < m; ++k) rhs[k] = T(0);
+      rhs[0] = r0;
+      rhs[m - 1] -= cm * xr;
+      chunk_solve_lds<T>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs, sm.px + r * TXP + qc * MX, 1);
+    }
+  } else if (tid >= 64 && tid < 64 + TX) {
+    const int c = tid - 64;
+    const int i = i0 + c;
+    if (i < nx && j0 < ny) {
+      const int m = min(TY, ny - j0);
+      const T* dly = sm.db + c + 1;                    // rows j0-1 .. j0+m
+      T* rhs = sm.cy + c;
+      const size_t o = (size_t)(j0 / TY) * nx + i;
+      const T xl = ify[o], xr = ify[(size_t)D.cy * nx + o];
+      T a, b, c0, cm;
+      tri_coef(dpos(dly[0]), dpos(dly[BX]), dpos(dly[2 * BX]), D.tcy, a, b, c0);
+      const T r0 = -a * xl;
+      tri_coef(dpos(dly[(m - 1) * BX]), dpos(dly[m * BX]), dpos(dly[(m + 1) * BX]), D.tcy, a, b, cm);
+      for (int k = 0; k < m; ++k) rhs[k * TXP] = T(0);
+      rhs[0] = r0;
+      rhs[(m - 1) * TXP] -= cm * xr;
+      chunk_solve_lds<T>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, rhs, sm.py + c, TXP);
+    }
+  }
+  __syncthreads();
+  T ld[CPT];
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int e = tid + q * NT;
+    const int r = e / TX, c = e - r * TX;
+    lp[q] += sm.cx[r * TXP + c];
+    lq[q] += sm.cy[r * TXP + c];
+    ld[q] = sm.db[(r + 1) * BX + c + 1];
   }
   double smax = 0.0;
 #pragma unroll

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <vector>
 
 #include "bq.h"
@@ -85,8 +86,8 @@ __global__ void k_setup_cells(const DomDev<T>* Dp) {
 }
 
 // spikes of the chunk-local systems: responses to a unit value of the
-// neighbour just left (v) and right (w) of the chunk; boundary values of the
-// spikes go to rs[0..3] (v_first, v_last, w_first, w_last)
+// neighbour just left (v) and right (w) of the chunk; only their end values
+// are kept, in rs[0..3] (v_first, v_last, w_first, w_last)
 template <typename T, int M>
 __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   const DomDev<T>& D = *Dp;
@@ -108,8 +109,6 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   T a0, b0, c0, am, bm, cm;
   tri_coef(dpos(Dl[0]), dpos(Dl[1]), dpos(Dl[2]), tc, a0, b0, c0);
   tri_coef(dpos(Dl[m - 1]), dpos(Dl[m]), dpos(Dl[m + 1]), tc, am, bm, cm);
-  T* sv = dir == 0 ? D.spxv : D.spyv;
-  T* sw = dir == 0 ? D.spxw : D.spyw;
   T* rs = dir == 0 ? D.rsx : D.rsy;
   const size_t CL = (size_t)C * L, o = (size_t)c * L + line;
   // left spike
@@ -118,10 +117,6 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
     r[0] = -a0;
     chunk_solve_db<T, M>(Dl, 1, m, tc, fold_lo, fold_hi, r, 1);
   }
-  for (int k = 0; k < m; ++k) {
-    const int q = s + k;
-    sv[dir == 0 ? (size_t)line * D.ipitch + q : (size_t)q * D.ipitch + line] = r[k];
-  }
   rs[o] = r[0];
   rs[CL + o] = r[m - 1];
   // right spike
@@ -129,10 +124,6 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
   if (c < C - 1) {
     r[m - 1] = -cm;
     chunk_solve_db<T, M>(Dl, 1, m, tc, fold_lo, fold_hi, r, 1);
-  }
-  for (int k = 0; k < m; ++k) {
-    const int q = s + k;
-    sw[dir == 0 ? (size_t)line * D.ipitch + q : (size_t)q * D.ipitch + line] = r[k];
   }
   rs[2 * CL + o] = r[0];
   rs[3 * CL + o] = r[m - 1];
@@ -347,9 +338,18 @@ struct bq_batch {
   std::vector<bq_domain*> doms;
   int precision = BQ_FP64;
   hipStream_t stream = nullptr;
-  void* mem = nullptr;          // table + prefixes
+  void* mem = nullptr;          // tables + prefixes of L, G[0], G[1]
   size_t mem_bytes = 0;
-  Launch L;
+  Launch L;                     // all members, one lane
+  // Two lanes: the members split into two groups of about equal cell count,
+  // each advanced on its own stream (the batch's stream and `aux`), so one
+  // group's stencil kernel (arithmetic-bound) runs beside the other group's
+  // line-coupling and finalize kernels (bandwidth- and latency-bound).
+  Launch G[2];
+  int lanes_req = 2;            // requested lanes (1 or 2)
+  int lanes = 1;                // lanes in use (1 if there is one member)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int graph_steps = 16;
 };
 
@@ -357,7 +357,7 @@ struct bq_batch {
 struct Layout {
   size_t off_state, off_desc, off_tp, off_lp;
   size_t off_w, off_P, off_Q, off_E, off_F, off_G;
-  size_t off_Dc, off_Dbar, off_xhP, off_xhQ, off_spxv, off_spxw, off_spyv, off_spyw;
+  size_t off_Dc, off_Dbar, off_xhP, off_xhQ;
   size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
   size_t ghosted, interior, total;
   int pitch, xoff, ipitch, cpitch, cx, cy, tiles_x, tiles_y, TY, MX;
@@ -400,10 +400,6 @@ static Layout layout_for(const bq_params* p) {
   L.off_Dbar = take(L.interior);
   L.off_xhP = take(L.interior);
   L.off_xhQ = take(L.interior);
-  L.off_spxv = take(L.interior);
-  L.off_spxw = take(L.interior);
-  L.off_spyv = take(L.interior);
-  L.off_spyw = take(L.interior);
   L.off_chx = take(2 * (size_t)L.cx * ny * sizeof(T));
   L.off_chy = take(2 * (size_t)L.cy * nx * sizeof(T));
   L.off_rsx = take(6 * (size_t)L.cx * ny * sizeof(T));
@@ -528,10 +524,6 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.Dbar = (T*)(b + Ly.off_Dbar);
   D.xhP = (T*)(b + Ly.off_xhP);
   D.xhQ = (T*)(b + Ly.off_xhQ);
-  D.spxv = (T*)(b + Ly.off_spxv);
-  D.spxw = (T*)(b + Ly.off_spxw);
-  D.spyv = (T*)(b + Ly.off_spyv);
-  D.spyw = (T*)(b + Ly.off_spyw);
   D.chx = (T*)(b + Ly.off_chx);
   D.chy = (T*)(b + Ly.off_chy);
   D.rsx = (T*)(b + Ly.off_rsx);
@@ -800,18 +792,46 @@ static int load_t(bq_domain* d, const void* host, size_t bytes) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-static int batch_build_t(bq_batch* b) {
-  const int nd = (int)b->doms.size();
+static void drop_graph(Launch& L) {
+  if (L.graph) (void)hipGraphExecDestroy(L.graph);
+  L.graph = nullptr;
+  L.graph_built = 0;
+}
+
+// device tables (DomDev<T>[nd], tile and line prefixes) of one member list
+template <typename T>
+static int fill_launch(Launch& L, char* m, size_t tb, size_t pb, const std::vector<bq_domain*>& doms, hipStream_t s) {
+  const int nd = (int)doms.size();
   std::vector<DomDev<T>> tab(nd);
   std::vector<int> tp(nd + 1), lp(nd + 1);
   tp[0] = lp[0] = 0;
   for (int k = 0; k < nd; ++k) {
-    tab[k] = desc<T>(b->doms[k]);
+    tab[k] = desc<T>(doms[k]);
     tp[k + 1] = tp[k] + tab[k].tiles_x * tab[k].tiles_y;
     lp[k + 1] = lp[k] + tab[k].nx + tab[k].ny;
   }
+  HIPCHK(hipMemcpyAsync(m, tab.data(), sizeof(DomDev<T>) * nd, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m + tb, tp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m + tb + pb, lp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, s));
+  drop_graph<T>(L);
+  L.table = m;
+  L.tile_prefix = (int*)(m + tb);
+  L.line_prefix = (int*)(m + tb + pb);
+  L.nd = nd;
+  L.tiles = tp[nd];
+  L.lines = lp[nd];
+  return BQ_OK;
+}
+
+template <typename T>
+static int batch_build_t(bq_batch* b) {
+  const int nd = (int)b->doms.size();
   const size_t tb = rup(sizeof(DomDev<T>) * (size_t)nd, 256), pb = rup(sizeof(int) * (size_t)(nd + 1), 256);
-  const size_t need = tb + 2 * pb;
+  const size_t one = tb + 2 * pb;
+  const size_t need = 3 * one;
+  // the previous tables may still be read by queued work
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (b->aux) HIPCHK(hipStreamSynchronize(b->aux));
   if (need > b->mem_bytes) {
     if (b->mem) HIPCHK(hipFree(b->mem));
     b->mem = nullptr;
@@ -819,21 +839,119 @@ static int batch_build_t(bq_batch* b) {
     b->mem_bytes = need;
   }
   char* m = (char*)b->mem;
-  HIPCHK(hipMemcpyAsync(m, tab.data(), sizeof(DomDev<T>) * nd, hipMemcpyHostToDevice, b->stream));
-  HIPCHK(hipMemcpyAsync(m + tb, tp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, b->stream));
-  HIPCHK(hipMemcpyAsync(m + tb + pb, lp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, b->stream));
-  HIPCHK(hipStreamSynchronize(b->stream));
-  if (b->L.graph) {
-    HIPCHK(hipGraphExecDestroy(b->L.graph));
-    b->L.graph = nullptr;
-    b->L.graph_built = 0;
+  int rc = fill_launch<T>(b->L, m, tb, pb, b->doms, b->stream);
+  if (rc) return rc;
+  b->lanes = (b->lanes_req == 2 && nd >= 2) ? 2 : 1;
+  if (b->lanes == 2) {
+    // greedy split by cell count, largest first; members keep their order
+    std::vector<int> ord(nd);
+    for (int k = 0; k < nd; ++k) ord[k] = k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      return (long long)b->doms[x]->nx * b->doms[x]->ny > (long long)b->doms[y]->nx * b->doms[y]->ny;
+    });
+    std::vector<int> grp(nd, 0);
+    long long cells[2] = {0, 0};
+    for (int k : ord) {
+      const int gsel = cells[1] < cells[0] ? 1 : 0;
+      grp[k] = gsel;
+      cells[gsel] += (long long)b->doms[k]->nx * b->doms[k]->ny;
+    }
+    for (int gsel = 0; gsel < 2; ++gsel) {
+      std::vector<bq_domain*> part;
+      for (int k = 0; k < nd; ++k)
+        if (grp[k] == gsel) part.push_back(b->doms[k]);
+      rc = fill_launch<T>(b->G[gsel], m + (1 + gsel) * one, tb, pb, part, b->stream);
+      if (rc) return rc;
+    }
+    if (!b->aux) HIPCHK(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking));
+    if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+    if (!b->ev_join) HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+  } else {
+    drop_graph<T>(b->G[0]);
+    drop_graph<T>(b->G[1]);
   }
-  b->L.table = m;
-  b->L.tile_prefix = (int*)(m + tb);
-  b->L.line_prefix = (int*)(m + tb + pb);
-  b->L.nd = nd;
-  b->L.tiles = tp[nd];
-  b->L.lines = lp[nd];
+  HIPCHK(hipStreamSynchronize(b->stream));
+  return BQ_OK;
+}
+
+// the aux lane starts after the work queued so far on the batch's stream, and
+// the batch's stream continues only after the aux lane's work
+static int fork_aux(bq_batch* b) {
+  HIPCHK(hipEventRecord(b->ev_fork, b->stream));
+  HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+  return BQ_OK;
+}
+
+static int join_aux(bq_batch* b) {
+  HIPCHK(hipEventRecord(b->ev_join, b->aux));
+  HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join, 0));
+  return BQ_OK;
+}
+
+template <typename T>
+static int batch_run_t(bq_batch* b, int n_steps) {
+  if (b->lanes == 1) return run_steps<T>(b->L, b->stream, n_steps, b->graph_steps);
+  if (n_steps <= 0) return BQ_OK;
+  int rc = fork_aux(b);
+  if (!rc) rc = run_steps<T>(b->G[0], b->stream, n_steps, b->graph_steps);
+  if (!rc) rc = run_steps<T>(b->G[1], b->aux, n_steps, b->graph_steps);
+  const int rj = join_aux(b);
+  return rc ? rc : rj;
+}
+
+// Kernel timing with both lanes running: hipEvents around every kernel on
+// its own lane's stream; ms_out[k] is the mean duration of one launch of
+// kernel k (a launch covers one group).
+template <typename T>
+static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
+  if (b->lanes == 1) return profile_t<T>(b->L, b->stream, n_steps, ms_out);
+  constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
+  hipStream_t ss[2] = {b->stream, b->aux};
+  hipEvent_t ev[2][5];
+  for (int l = 0; l < 2; ++l)
+    for (int k = 0; k < 5; ++k) HIPCHK(hipEventCreate(&ev[l][k]));
+  double acc[4] = {0, 0, 0, 0};
+  int rc = fork_aux(b);
+  for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
+    for (int l = 0; l < 2; ++l) (void)hipEventRecord(ev[l][0], ss[l]);
+    for (int l = 0; l < 2; ++l) {
+      const Launch& L = b->G[l];
+      k_dt<T><<<L.nd, 64, 0, ss[l]>>>((const DomDev<T>*)L.table, 0.0);
+      (void)hipEventRecord(ev[l][1], ss[l]);
+    }
+    for (int l = 0; l < 2; ++l) {
+      const Launch& L = b->G[l];
+      k_rhs<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_prefix, L.nd);
+      (void)hipEventRecord(ev[l][2], ss[l]);
+    }
+    for (int l = 0; l < 2; ++l) {
+      const Launch& L = b->G[l];
+      k_reduced<T><<<cdiv(L.lines, 256), 256, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_prefix, L.nd);
+      (void)hipEventRecord(ev[l][3], ss[l]);
+    }
+    for (int l = 0; l < 2; ++l) {
+      const Launch& L = b->G[l];
+      k_final<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_prefix, L.nd);
+      (void)hipEventRecord(ev[l][4], ss[l]);
+    }
+    for (int l = 0; l < 2 && rc == BQ_OK; ++l)
+      if (hipEventSynchronize(ev[l][4]) != hipSuccess) rc = fail(BQ_EDEVICE, "hipEventSynchronize");
+    for (int l = 0; l < 2 && rc == BQ_OK; ++l)
+      for (int k = 0; k < 4; ++k) {
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, ev[l][k], ev[l][k + 1]);
+        acc[k] += 0.5 * ms;
+      }
+  }
+  for (int l = 0; l < 2; ++l) enqueue_commit<T>(b->G[l], ss[l]);
+  const int rj = join_aux(b);
+  for (int l = 0; l < 2; ++l)
+    for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[l][k]);
+  if (rc) return rc;
+  if (rj) return rj;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (int k = 0; k < 4; ++k) ms_out[k] = n_steps > 0 ? acc[k] / n_steps : 0.0;
   return BQ_OK;
 }
 
@@ -962,7 +1080,7 @@ int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out) {
 
 int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out) {
   if (!b || !ms_out || n_steps < 0) return fail(BQ_EINVAL, "bad argument");
-  return DISPATCH(b->precision, profile_t, b->L, b->stream, n_steps, ms_out);
+  return DISPATCH(b->precision, batch_profile_t, b, n_steps, ms_out);
 }
 
 int bq_set_graph_steps(bq_domain* d, int32_t steps) {
@@ -1000,14 +1118,24 @@ int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n) {
 int bq_batch_step(bq_batch* b, int32_t n_steps) {
   if (!b) return fail(BQ_EINVAL, "NULL batch");
   if (n_steps < 0) return fail(BQ_EINVAL, "n_steps < 0");
-  return DISPATCH(b->precision, run_steps, b->L, b->stream, n_steps, b->graph_steps);
+  return DISPATCH(b->precision, batch_run_t, b, n_steps);
 }
 
 int bq_batch_sync(bq_batch* b) {
   if (!b) return fail(BQ_EINVAL, "NULL batch");
   HIPCHK(hipStreamSynchronize(b->stream));
+  if (b->aux) HIPCHK(hipStreamSynchronize(b->aux));
   return BQ_OK;
 }
+
+int bq_batch_set_lanes(bq_batch* b, int32_t lanes) {
+  if (!b || (lanes != 1 && lanes != 2)) return fail(BQ_EINVAL, "lanes must be 1 or 2");
+  if (lanes == b->lanes_req) return BQ_OK;
+  b->lanes_req = lanes;
+  return DISPATCH(b->precision, batch_build_t, b);
+}
+
+int bq_batch_lanes(const bq_batch* b) { return b ? b->lanes : fail(BQ_EINVAL, "NULL batch"); }
 
 int bq_batch_set_graph_steps(bq_batch* b, int32_t steps) {
   if (!b || steps < 0) return fail(BQ_EINVAL, "bad argument");
@@ -1017,7 +1145,14 @@ int bq_batch_set_graph_steps(bq_batch* b, int32_t steps) {
 
 int bq_batch_free(bq_batch* b) {
   if (!b) return fail(BQ_EINVAL, "NULL batch");
+  (void)hipStreamSynchronize(b->stream);
+  if (b->aux) (void)hipStreamSynchronize(b->aux);
   if (b->L.graph) (void)hipGraphExecDestroy(b->L.graph);
+  for (int l = 0; l < 2; ++l)
+    if (b->G[l].graph) (void)hipGraphExecDestroy(b->G[l].graph);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->aux) (void)hipStreamDestroy(b->aux);
   if (b->mem) (void)hipFree(b->mem);
   delete b;
   return BQ_OK;

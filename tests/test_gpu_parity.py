@@ -251,11 +251,38 @@ def test_batch_members_equal_solo_runs(bq):
         g.step(30)
         g.sync()
         solo.append([g.read(f) for f in FIELDS])
-    doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
-    b = bq.Batch(doms)
-    b.step(30)
-    b.sync()
-    for d, ref in zip(doms, solo):
-        assert d.sync().n == 30
-        for f, r in zip(FIELDS, ref):
-            assert np.array_equal(d.read(f), r), f
+    for lanes in (1, 2):
+        doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
+        b = bq.Batch(doms, lanes=lanes)
+        assert b.lanes == lanes
+        b.step(30)
+        b.sync()
+        for d, ref in zip(doms, solo):
+            assert d.sync().n == 30
+            for f, r in zip(FIELDS, ref):
+                assert np.array_equal(d.read(f), r), (lanes, f)
+        b.close()
+
+
+def test_two_lane_batch_profile_and_graphs_match_one_lane(bq):
+    # kernel timing (plain launches on both lanes) then graph replays, against
+    # a one-lane batch doing the same steps
+    specs = [S.sloping_beach(nx=200, ny=40, dx=0.1, x_toe=2.0, t_end=0.0),
+             S.solitary_flat(nx=130, ny=70, x0=2.0),
+             S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0),
+             S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.125, fstar_order=1)]
+    out = {}
+    for lanes in (1, 2):
+        doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
+        b = bq.Batch(doms, lanes=lanes)
+        ms = b.profile(3)
+        assert all(v >= 0.0 for v in ms.values())
+        b.set_graph_steps(4)
+        b.step(9)
+        b.sync()
+        out[lanes] = [[d.read(f) for f in FIELDS] for d in doms]
+        assert all(d.sync().n == 12 for d in doms)
+        b.close()
+    for x, y in zip(out[1], out[2]):
+        for a, c in zip(x, y):
+            assert np.array_equal(a, c)
