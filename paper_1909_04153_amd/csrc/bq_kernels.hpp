@@ -111,6 +111,31 @@ __device__ __forceinline__ gp<T> gbl(T* p) {
   return (gp<T>)p;
 }
 
+// A pointer read from device memory that is the same in every lane: pin it
+// to scalar registers, so that loads through it take the scalar-base form.
+template <typename P>
+__device__ __forceinline__ P* uni(P* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return (P*)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Element `off` of a field whose base address is the same for the whole
+// block: a scalar base plus a 32-bit per-lane byte offset (the workspace
+// keeps every field below 4 GiB).
+template <typename T>
+__device__ __forceinline__ T ldu(const T* base, unsigned off) {
+  const gp<const char> b = (gp<const char>)(const char*)base;
+  return *(gp<const T>)(b + (unsigned)(off * (unsigned)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stu(T* base, unsigned off, T v) {
+  const gp<char> b = (gp<char>)(char*)base;
+  *(gp<T>)(b + (unsigned)(off * (unsigned)sizeof(T))) = v;
+}
+
 // Square root, reciprocal and cube root.  FP64 uses the correctly rounded
 // operations (parity with the FP64 oracle at 1e-12); FP32 uses the hardware
 // transcendental instructions (about 1 ulp), whose error is far below the
@@ -566,9 +591,6 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
                                            int nd) {
   using S = RhsSmem<T, TY, MX>;
   constexpr int WX = S::WX, BX = S::BX, CXN = S::CXN, TXP = S::TXP;
-  constexpr int NWW = (S::WY * WX + NT - 1) / NT;     // staging rounds per array
-  constexpr int NWC = (S::CYN * CXN + NT - 1) / NT;
-  constexpr int NWB = (S::BY * BX + NT - 1) / NT;
   constexpr int CPT = (TX * TY) / NT;                 // cells per thread
   static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
   __shared__ S sm;
@@ -580,103 +602,110 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   const int tile = bt - tile_prefix[dom];
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
-  const int slot = st->slot;
+  const int slot = uni(st->slot), par = uni((int)(st->n & 1));
   const int s1 = slot == 0 ? 2 : slot - 1, s2 = slot == 2 ? 0 : slot + 1;
-  const gp<const T> w = gbl((const T*)D.w[st->n & 1]);
-  const gp<const T> Pn = gbl((const T*)D.P[slot]);
-  const gp<const T> Qn = gbl((const T*)D.Q[slot]);
-  const gp<const T> P1 = gbl((const T*)D.P[s1]);
-  const gp<const T> P2 = gbl((const T*)D.P[s2]);
-  const gp<const T> Q1 = gbl((const T*)D.Q[s1]);
-  const gp<const T> Q2 = gbl((const T*)D.Q[s2]);
-  const gp<const T> Dc = gbl((const T*)D.Dc);
   const T beta0 = (T)st->beta[0], beta1 = (T)st->beta[1], beta2 = (T)st->beta[2];
   const bool hist = st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
-  const int pitch = D.pitch, xoff = D.xoff, ipitch = D.ipitch;
+  const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
   // Cells of a thread in the per-cell phases: column cY, rows rY0 .. rY0+CPT-1
   // (consecutive rows, so the vertical stencils of a thread's cells overlap).
   const int cY = tid % TX, rY0 = (tid / TX) * CPT;
   static_assert((NT / TX) * CPT == TY, "per-cell mapping covers the tile");
+  const unsigned oI = (unsigned)((j0 + rY0) * ipitch + i0 + cY);          // interior fields
+  const unsigned oG = (unsigned)((j0 + rY0 + 2) * pitch + xoff + i0 + cY);  // ghosted fields
 
   // ---- phase 0: issue every load of the tile before the first LDS store ----
+  // Each LDS tile of width Wd is read RG = NT / Wd rows per round: thread
+  // (r0, c) = (tid / Wd, tid % Wd) loads rows r0 + RG k, so the LDS index is
+  // a per-thread base plus a constant.  The threads beyond RG whole rows and
+  // the rows past the tile in the last round repeat a row of the tile (same
+  // values to the same LDS words), so every round is branch-free.  The
+  // workspace pads every field to whole tiles plus the halo, so no index is
+  // clamped to the domain: values outside it only reach cells outside it.
+  constexpr int RGW = NT / WX, KW = (S::WY + RGW - 1) / RGW;
+  constexpr int RGC = NT / CXN, KC = (S::CYN + RGC - 1) / RGC;
+  constexpr int RGB = NT / BX, KB = (S::BY + RGB - 1) / RGB;
+  const int rW = min(tid / WX, RGW - 1), cW = tid - (tid / WX) * WX;
+  const int rC = min(tid / CXN, RGC - 1), cC = tid - (tid / CXN) * CXN;
+  const int rB = min(tid / BX, RGB - 1), cB = tid - (tid / BX) * BX;
+  auto rowW = [&](int k) { return k < KW - 1 ? rW + RGW * k : min(rW + RGW * k, S::WY - 1); };
+  auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
+  auto rowB = [&](int k) { return k < KB - 1 ? rB + RGB * k : min(rB + RGB * k, S::BY - 1); };
   // E, F, G history of this thread's cells (consumed in phase 2)
   T he1[CPT], he2[CPT], hf1[CPT], hf2[CPT], hg1[CPT], hg2[CPT];
   {
-    const gp<const T> E1 = gbl((const T*)D.E[s1]);
-    const gp<const T> E2 = gbl((const T*)D.E[s2]);
-    const gp<const T> F1 = gbl((const T*)D.F[s1]);
-    const gp<const T> F2 = gbl((const T*)D.F[s2]);
-    const gp<const T> G1 = gbl((const T*)D.G[s1]);
-    const gp<const T> G2 = gbl((const T*)D.G[s2]);
+    const T* E1 = uni((const T*)D.E[s1]);
+    const T* E2 = uni((const T*)D.E[s2]);
+    const T* F1 = uni((const T*)D.F[s1]);
+    const T* F2 = uni((const T*)D.F[s2]);
+    const T* G1 = uni((const T*)D.G[s1]);
+    const T* G2 = uni((const T*)D.G[s2]);
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
-      const int i = min(i0 + cY, nx - 1), j = min(j0 + rY0 + q, ny - 1);
-      const size_t ii = (size_t)j * ipitch + i;
-      he1[q] = E1[ii]; he2[q] = E2[ii];
-      hf1[q] = F1[ii]; hf2[q] = F2[ii];
-      hg1[q] = G1[ii]; hg2[q] = G2[ii];
+      const unsigned o = oI + (unsigned)(q * ipitch);
+      he1[q] = ldu(E1, o); he2[q] = ldu(E2, o);
+      hf1[q] = ldu(F1, o); hf2[q] = ldu(F2, o);
+      hg1[q] = ldu(G1, o); hg2[q] = ldu(G2, o);
     }
   }
-  T rw[NWW], rp[NWW], rq[NWW], rc[NWC], h1p[NWB], h2p[NWB], h1q[NWB], h2q[NWB];
+  T rw[KW], rp[KW], rq[KW], rc[KC], h1p[KB], h2p[KB], h1q[KB], h2q[KB];
+  {
+    const T* w = uni((const T*)D.w[par]);
+    const T* Pn = uni((const T*)D.P[slot]);
+    const T* Qn = uni((const T*)D.Q[slot]);
+    const unsigned oW = (unsigned)(j0 * pitch + xoff + i0 - 2 + cW);       // radius-2 tile
 #pragma unroll
-  for (int k = 0; k < NWW; ++k) {
-    const int e = min(tid + k * NT, S::WY * WX - 1);
-    const int r = e / WX, c = e - r * WX;
-    const int i = min(max(i0 + c - 2, -2), nx + 1), j = min(max(j0 + r - 2, -2), ny + 1);
-    const size_t g = (size_t)(j + 2) * pitch + xoff + i;
-    rw[k] = w[g];
-    rp[k] = Pn[g];
-    rq[k] = Qn[g];
-  }
+    for (int k = 0; k < KW; ++k) {
+      const unsigned o = oW + (unsigned)(rowW(k) * pitch);
+      rw[k] = ldu(w, o);
+      rp[k] = ldu(Pn, o);
+      rq[k] = ldu(Qn, o);
+    }
+    const T* Dc = uni((const T*)D.Dc);
+    const unsigned oC = (unsigned)(j0 * cpitch + i0 + cC);                 // corners
 #pragma unroll
-  for (int k = 0; k < NWC; ++k) {
-    const int e = min(tid + k * NT, S::CYN * CXN - 1);
-    const int r = e / CXN, c = e - r * CXN;
-    const int ic = min(i0 + c - 2, nx + 2), jc = min(j0 + r - 2, ny + 2);
-    rc[k] = Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
-  }
-#pragma unroll
-  for (int k = 0; k < NWB; ++k) {
-    h1p[k] = h2p[k] = h1q[k] = h2q[k] = T(0);
+    for (int k = 0; k < KC; ++k) rc[k] = ldu(Dc, oC + (unsigned)(rowC(k) * cpitch));
+    const unsigned oB = (unsigned)((j0 + 1) * pitch + xoff + i0 - 1 + cB);   // radius-1 tile
     if (hist) {
-      const int e = min(tid + k * NT, S::BY * BX - 1);
-      const int r = e / BX, c = e - r * BX;
-      const int i = min(max(i0 + c - 1, -2), nx + 1), j = min(max(j0 + r - 1, -2), ny + 1);
-      const size_t g = (size_t)(j + 2) * pitch + xoff + i;
-      h1p[k] = P1[g]; h2p[k] = P2[g];
-      h1q[k] = Q1[g]; h2q[k] = Q2[g];
+      const T* P1 = uni((const T*)D.P[s1]);
+      const T* P2 = uni((const T*)D.P[s2]);
+      const T* Q1 = uni((const T*)D.Q[s1]);
+      const T* Q2 = uni((const T*)D.Q[s2]);
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const unsigned o = oB + (unsigned)(rowB(k) * pitch);
+        h1p[k] = ldu(P1, o);
+        h2p[k] = ldu(P2, o);
+        h1q[k] = ldu(Q1, o);
+        h2q[k] = ldu(Q2, o);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KB; ++k) h1p[k] = h2p[k] = h1q[k] = h2q[k] = T(0);
     }
   }
 #pragma unroll
-  for (int k = 0; k < NWW; ++k) {
-    const int e = tid + k * NT;
-    if (e < S::WY * WX) {
-      sm.w[e] = rw[k];
-      sm.p[e] = rp[k];
-      sm.q[e] = rq[k];
-    }
+  for (int k = 0; k < KW; ++k) {
+    const int e = rowW(k) * WX + cW;
+    sm.w[e] = rw[k];
+    sm.p[e] = rp[k];
+    sm.q[e] = rq[k];
   }
 #pragma unroll
-  for (int k = 0; k < NWC; ++k) {
-    const int e = tid + k * NT;
-    if (e < S::CYN * CXN) sm.dc[e] = rc[k];
-  }
+  for (int k = 0; k < KC; ++k) sm.dc[rowC(k) * CXN + cC] = rc[k];
   __syncthreads();
   // weighted P/Q history (level n from the staged tile) and cell depths
 #pragma unroll
-  for (int k = 0; k < NWB; ++k) {
-    const int e = tid + k * NT;
-    if (e < S::BY * BX) {
-      const int r = e / BX, c = e - r * BX;
-      const int t2 = (r + 1) * WX + c + 1;    // same cell in the radius-2 tile
-      sm.pt[e] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
-      sm.qt[e] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
-    }
+  for (int k = 0; k < KB; ++k) {
+    const int r = rowB(k);
+    const int t2 = (r + 1) * WX + cB + 1;             // same cell in the radius-2 tile
+    sm.pt[r * BX + cB] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
+    sm.qt[r * BX + cB] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
   }
-  for (int e = tid; e < S::WY * WX; e += NT) {
-    const int r = e / WX, c = e - r * WX;
-    sm.db[e] = dbar4(sm.dc[r * CXN + c], sm.dc[r * CXN + c + 1], sm.dc[(r + 1) * CXN + c],
-                     sm.dc[(r + 1) * CXN + c + 1]);
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+    const int c0 = rowW(k) * CXN + cW;
+    sm.db[rowW(k) * WX + cW] = dbar4(sm.dc[c0], sm.dc[c0 + 1], sm.dc[c0 + CXN], sm.dc[c0 + CXN + 1]);
   }
 
   const T g = D.g, eps = D.eps, ht = T(0.5) * D.theta;
@@ -783,10 +812,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
   const T B = D.B, Bc = D.Bc, gn2 = D.gn2;
   const T a0 = (T)st->alpha[0], a1 = (T)st->alpha[1], a2 = (T)st->alpha[2];
-  const gp<T> wn = gbl(D.w[(st->n + 1) & 1]);
-  const gp<T> E0 = gbl(D.E[slot]);
-  const gp<T> F0 = gbl(D.F[slot]);
-  const gp<T> G0 = gbl(D.G[slot]);
+  T* const wn = uni(D.w[par ^ 1]);
+  T* const E0 = uni(D.E[slot]);
+  T* const F0 = uni(D.F[slot]);
+  T* const G0 = uni(D.G[slot]);
   T ures[CPT], vres[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
@@ -845,11 +874,11 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const T fs = d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
     const T gs = d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
     // Eq. (42)-(43)
-    const size_t ii = (size_t)j * ipitch + i;
-    E0[ii] = e_;
-    F0[ii] = f_;
-    G0[ii] = g_;
-    wn[(size_t)(j + 2) * pitch + xoff + i] = sm.w[C0] + (a0 * e_ + a1 * he1[q] + a2 * he2[q]);
+    const unsigned ii = oI + (unsigned)(q * ipitch);
+    stu(E0, ii, e_);
+    stu(F0, ii, f_);
+    stu(G0, ii, g_);
+    stu(wn, oG + (unsigned)(q * pitch), sm.w[C0] + (a0 * e_ + a1 * he1[q] + a2 * he2[q]));
     // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
     // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
     // U*^n = T P^n with the same matrix
@@ -904,17 +933,16 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     }
   }
   __syncthreads();
+  // local solutions (cells outside the domain land in the fields' padding)
+  T* const xhP = uni(D.xhP);
+  T* const xhQ = uni(D.xhQ);
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
-    const int e = tid + q * NT;
-    const int r = e / TX, c = e - r * TX;
-    const int i = i0 + c, j = j0 + r;
-    if (i < nx && j < ny) {
-      const size_t ii = (size_t)j * ipitch + i;
-      const int C0 = (r + 2) * WX + c + 2;
-      gbl(D.xhP)[ii] = sm.p[C0] + sm.x.s.u[r * TXP + c];
-      gbl(D.xhQ)[ii] = sm.q[C0] + sm.x.s.v[r * TXP + c];
-    }
+    const int r = rY0 + q;
+    const int C0 = (r + 2) * WX + cY + 2;
+    const unsigned ii = oI + (unsigned)(q * ipitch);
+    stu(xhP, ii, sm.p[C0] + sm.x.s.u[r * TXP + cY]);
+    stu(xhQ, ii, sm.q[C0] + sm.x.s.v[r * TXP + cY]);
   }
 }
 

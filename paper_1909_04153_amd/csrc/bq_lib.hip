@@ -370,16 +370,19 @@ static Layout layout_for(const bq_params* p) {
   const int A = 256 / (int)sizeof(T);
   L.TY = Cfg<T>::TY;
   L.MX = Cfg<T>::MX;
-  L.xoff = A;
-  L.pitch = (int)rup((size_t)A + nx + 2, (size_t)A);
-  L.ipitch = (int)rup((size_t)nx, (size_t)A);
-  L.cpitch = (int)rup((size_t)nx + 5, 64);
   L.cx = cdiv(nx, L.MX);
   L.cy = cdiv(ny, L.TY);
   L.tiles_x = cdiv(nx, TX);
   L.tiles_y = cdiv(ny, L.TY);
-  L.ghosted = (size_t)(ny + 4) * L.pitch * sizeof(T);
-  L.interior = (size_t)ny * L.ipitch * sizeof(T);
+  // fields are padded to whole tiles plus the stencil halo, so the stencil
+  // kernel reads every tile without clamping its indices
+  const int NX = L.tiles_x * TX, NY = L.tiles_y * L.TY;
+  L.xoff = A;
+  L.pitch = (int)rup((size_t)A + NX + 2, (size_t)A);
+  L.ipitch = NX;
+  L.cpitch = (int)rup((size_t)NX + 5, 64);
+  L.ghosted = (size_t)(NY + 4) * L.pitch * sizeof(T);
+  L.interior = (size_t)NY * L.ipitch * sizeof(T);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -396,7 +399,7 @@ static Layout layout_for(const bq_params* p) {
   L.off_E = take(3 * L.interior);
   L.off_F = take(3 * L.interior);
   L.off_G = take(3 * L.interior);
-  L.off_Dc = take((size_t)(ny + 5) * L.cpitch * sizeof(T));
+  L.off_Dc = take((size_t)(NY + 5) * L.cpitch * sizeof(T));
   L.off_Dbar = take(L.interior);
   L.off_xhP = take(L.interior);
   L.off_xhQ = take(L.interior);
