@@ -321,14 +321,15 @@ __device__ __forceinline__ void tri_coef(T dm, T d0, T dp, const T* tc, T& a, T&
 // diagonal.  rhs (stride rs) is overwritten with the solution; the reciprocal
 // pivots and the upper diagonal stay in registers (the loops are unrolled
 // over M).
-template <typename T, int M>
-__device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
-                                               T* rhs, int rs) {
+template <typename T, int M, bool FULL>
+__device__ __forceinline__ void chunk_solve_db_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                                T* rhs, int rs) {
+  if (FULL) m = M;
   T piv[M], up[M];
   T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
-    if (k < m) {
+    if (FULL || k < m) {
       T a, b, c;
       tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
       if (k == 0 && fold_lo) b -= a;
@@ -355,13 +356,21 @@ __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const
   T x_next = T(0);
 #pragma unroll
   for (int k = M - 1; k >= 0; --k) {
-    if (k < m) {
+    if (FULL || k < m) {
       const T y = rhs[k * rs];
       const T x = (k == m - 1) ? y * piv[k] : (y - up[k] * x_next) * piv[k];
       rhs[k * rs] = x;
       x_next = x;
     }
   }
+}
+// full chunks (the common case) take a branch-free unrolled path, so the
+// LDS reads can be issued ahead of the dependent arithmetic
+template <typename T, int M>
+__device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                               T* rhs, int rs) {
+  if (m == M) chunk_solve_db_<T, M, true>(Dl, ds, m, tc, fold_lo, fold_hi, rhs, rs);
+  else chunk_solve_db_<T, M, false>(Dl, ds, m, tc, fold_lo, fold_hi, rhs, rs);
 }
 
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
@@ -377,17 +386,25 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 // The same solve for kernels that must stay light on registers: the
 // reciprocal pivots go to LDS (pv, stride rs) and the upper diagonal is
-// recomputed in the backward sweep.
-template <typename T>
+// recomputed in the backward sweep.  The sweeps stay rolled; each iteration
+// issues the next row's LDS reads before its own dependent arithmetic, so
+// the read latency overlaps the pivot recurrence.
+// EDGE: the right-hand side is zero except r0 in the first row and r1 in the
+// last (rhs is then only written), as for the response to the neighbour
+// chunks' end values.
+template <typename T, bool EDGE>
 __device__ __forceinline__ void chunk_solve_lds(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
-                                                T* rhs, T* pv, int rs) {
+                                                T* rhs, T* pv, int rs, T r0 = T(0), T r1 = T(0)) {
+  T d0 = dpos(Dl[0]), d1 = dpos(Dl[ds]), d2 = dpos(Dl[2 * ds]);
+  T r = EDGE ? (m == 1 ? r0 + r1 : r0) : rhs[0];
   T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
   for (int k = 0; k < m; ++k) {
+    const T d3 = dpos(Dl[(k + 3 <= m + 1 ? k + 3 : m + 1) * ds]);
+    const T rn = EDGE ? (k + 2 == m ? r1 : T(0)) : rhs[(k + 1 < m ? k + 1 : k) * rs];
     T a, b, c;
-    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+    tri_coef(d0, d1, d2, tc, a, b, c);
     if (k == 0 && fold_lo) b -= a;
     if (k == m - 1 && fold_hi) b -= c;
-    const T r = rhs[k * rs];
     T u, y;
     if (k == 0) {
       u = b;
@@ -403,26 +420,47 @@ __device__ __forceinline__ void chunk_solve_lds(const T* Dl, int ds, int m, cons
     y_prev = y;
     iu_prev = iu;
     c_prev = c;
+    d0 = d1;
+    d1 = d2;
+    d2 = d3;
+    r = rn;
   }
-  T x_next = rhs[(m - 1) * rs] * pv[(m - 1) * rs];
+  // backward: row k needs the depths of rows k-1, k, k+1 (Dl[k .. k+2])
+  T x_next = y_prev * iu_prev;
   rhs[(m - 1) * rs] = x_next;
+  if (m < 2) return;
+  T e0 = dpos(Dl[(m - 2) * ds]), e1 = dpos(Dl[(m - 1) * ds]), e2 = dpos(Dl[m * ds]);
+  T yk = rhs[(m - 2) * rs], pk = pv[(m - 2) * rs];
   for (int k = m - 2; k >= 0; --k) {
+    const int kn = k > 0 ? k - 1 : 0;
+    const T en = dpos(Dl[kn * ds]);
+    const T yn = rhs[kn * rs], pn = pv[kn * rs];
     T a, b, c;
-    tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
-    const T x = (rhs[k * rs] - c * x_next) * pv[k * rs];
+    tri_coef(e0, e1, e2, tc, a, b, c);
+    const T x = (yk - c * x_next) * pk;
     rhs[k * rs] = x;
     x_next = x;
+    e2 = e1;
+    e1 = e0;
+    e0 = en;
+    yk = yn;
+    pk = pn;
   }
 }
 
-// locate the domain of a flattened index with a prefix table (nd + 1 entries)
-__device__ __forceinline__ int find_domain(const int* prefix, int nd, int idx) {
-  int lo = 0, hi = nd;  // prefix[lo] <= idx < prefix[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (prefix[mid] <= idx) lo = mid; else hi = mid;
+// Work item (tile or line) of a launch -> (domain, index within it).  A
+// batch carries a packed map, one word per item: domain << MAP_SHIFT | index
+// (a single dependent load, no search); a single domain is the identity.
+constexpr int MAP_SHIFT = 18;
+__device__ __forceinline__ void locate(const int* map, int nd, int idx, int& dom, int& loc) {
+  if (nd == 1) {
+    dom = 0;
+    loc = idx;
+    return;
   }
-  return lo;
+  const int v = map[idx];
+  dom = v >> MAP_SHIFT;
+  loc = v & ((1 << MAP_SHIFT) - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,14 +608,18 @@ struct alignas(16) RhsSmem {
   static constexpr int BX = TX + 2, BY = TY + 2;      // radius-1 tiles
   static constexpr int CXN = TX + 5, CYN = TY + 5;    // corners
   static constexpr int TXP = TX + 1;                  // padded row of the solve buffers
-  T w[WY * WX];
-  T p[WY * WX];
-  T q[WY * WX];
-  T db[WY * WX];                                      // cell still-water depth
+  // LDS row pitch of the radius-2 tiles: 5 mod 64 words, so the x-segment
+  // threads (stride 4 within a row, 4 rows per wave) hit 64 distinct banks
+  static constexpr int LW = WX + 1;
+  static constexpr int AXP = TX + 1;                  // row pitch of ax (same reason)
+  T w[WY * LW];
+  T p[WY * LW];
+  T q[WY * LW];
+  T db[WY * LW];                                      // cell still-water depth
   T pt[BY * BX];                                      // sum_k beta_k P^{n-k}
   T qt[BY * BX];
   union {
-    T ax[3][TY * TX];                                 // x-direction parts of E, F, G per cell
+    T ax[3][TY * AXP];                                // x-direction parts of E, F, G per cell
     struct {
       T u[TY * TXP];
       T v[TY * TXP];
@@ -587,19 +629,18 @@ struct alignas(16) RhsSmem {
 };
 
 template <typename T, int TY, int MX>
-__global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_prefix,
+__global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                            int nd) {
   using S = RhsSmem<T, TY, MX>;
-  constexpr int WX = S::WX, BX = S::BX, CXN = S::CXN, TXP = S::TXP;
+  constexpr int WX = S::WX, LW = S::LW, AXP = S::AXP, BX = S::BX, CXN = S::CXN, TXP = S::TXP;
   constexpr int CPT = (TX * TY) / NT;                 // cells per thread
   static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
   __shared__ S sm;
-  const int bt = xcd_tile(blockIdx.x, gridDim.x);
-  const int dom = find_domain(tile_prefix, nd, bt);
+  int dom, tile;
+  locate(tile_map, nd, xcd_tile(blockIdx.x, gridDim.x), dom, tile);
   const DomDev<T>& D = doms[dom];
   const DevState* st = D.st;
   if (st->halt) return;
-  const int tile = bt - tile_prefix[dom];
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int slot = uni(st->slot), par = uni((int)(st->n & 1));
@@ -686,7 +727,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   }
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
-    const int e = rowW(k) * WX + cW;
+    const int e = rowW(k) * LW + cW;
     sm.w[e] = rw[k];
     sm.p[e] = rp[k];
     sm.q[e] = rq[k];
@@ -698,14 +739,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     const int r = rowB(k);
-    const int t2 = (r + 1) * WX + cB + 1;             // same cell in the radius-2 tile
+    const int t2 = (r + 1) * LW + cB + 1;             // same cell in the radius-2 tile
     sm.pt[r * BX + cB] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
     sm.qt[r * BX + cB] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
   }
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
     const int c0 = rowW(k) * CXN + cW;
-    sm.db[rowW(k) * WX + cW] = dbar4(sm.dc[c0], sm.dc[c0 + 1], sm.dc[c0 + CXN], sm.dc[c0 + CXN + 1]);
+    sm.db[rowW(k) * LW + cW] = dbar4(sm.dc[c0], sm.dc[c0 + 1], sm.dc[c0 + CXN], sm.dc[c0 + CXN + 1]);
   }
 
   const T g = D.g, eps = D.eps, ht = T(0.5) * D.theta;
@@ -719,9 +760,9 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   static_assert(SPR * TY == NT, "one x-segment per thread");
   {
     const int rx = tid / SPR, cx0 = (tid - rx * SPR) * CPT;
-    const T* wr = sm.w + (rx + 2) * WX + cx0;         // tile column cx0 = cell cx0 - 2
-    const T* pr = sm.p + (rx + 2) * WX + cx0;
-    const T* qr = sm.q + (rx + 2) * WX + cx0;
+    const T* wr = sm.w + (rx + 2) * LW + cx0;         // tile column cx0 = cell cx0 - 2
+    const T* pr = sm.p + (rx + 2) * LW + cx0;
+    const T* qr = sm.q + (rx + 2) * LW + cx0;
     const T* c0 = sm.dc + (rx + 2) * CXN + cx0 + 1;   // corners of face cx0 - 1
     T Dfx[CPT + 3];                                   // still-water depth of face cx0 - 1 + k
 #pragma unroll
@@ -753,7 +794,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
         // fluxes taken out only the face-depth departures remain
         const T Dw = Dfx[m], De = Dfx[m + 1];
         const T bed = g * (De - Dw) * (T(0.5) * (L.dev + dvw)) + shore_term(Dw, De, g);
-        const int o = rx * TX + cx0 + m - 1;
+        const int o = rx * AXP + cx0 + m - 1;
         sm.x.ax[0][o] = -(f0 - f0w) * idx;
         sm.x.ax[1][o] = (bed - (fn - fnw)) * idx;
         sm.x.ax[2][o] = -(ft - ftw) * idx;
@@ -768,9 +809,9 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   // normal = Q, tangential = P; thread cells (rY0 + q, cY)
   T acc_e[CPT], acc_f[CPT], acc_g[CPT];
   {
-    const T* wc = sm.w + rY0 * WX + cY + 2;           // tile row rY0 = row rY0 - 2
-    const T* pc = sm.p + rY0 * WX + cY + 2;
-    const T* qc = sm.q + rY0 * WX + cY + 2;
+    const T* wc = sm.w + rY0 * LW + cY + 2;           // tile row rY0 = row rY0 - 2
+    const T* pc = sm.p + rY0 * LW + cY + 2;
+    const T* qc = sm.q + rY0 * LW + cY + 2;
     const T* c0 = sm.dc + (rY0 + 1) * CXN + cY + 2;   // corners of face rY0 - 1
     T Dfy[CPT + 3];
 #pragma unroll
@@ -778,13 +819,13 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
 #pragma unroll
     for (int k = 0; k < CPT + 2; ++k) {
-      recon_w(wc[k * WX], wc[(k + 1) * WX], wc[(k + 2) * WX], ht, Dfy[k], Dfy[k + 1], wl[k], wh[k]);
-      const T sp = hslope(pc[k * WX], pc[(k + 1) * WX], pc[(k + 2) * WX], ht);
-      const T sq = hslope(qc[k * WX], qc[(k + 1) * WX], qc[(k + 2) * WX], ht);
-      pl[k] = pc[(k + 1) * WX] - sp;
-      ph[k] = pc[(k + 1) * WX] + sp;
-      ql[k] = qc[(k + 1) * WX] - sq;
-      qh[k] = qc[(k + 1) * WX] + sq;
+      recon_w(wc[k * LW], wc[(k + 1) * LW], wc[(k + 2) * LW], ht, Dfy[k], Dfy[k + 1], wl[k], wh[k]);
+      const T sp = hslope(pc[k * LW], pc[(k + 1) * LW], pc[(k + 2) * LW], ht);
+      const T sq = hslope(qc[k * LW], qc[(k + 1) * LW], qc[(k + 2) * LW], ht);
+      pl[k] = pc[(k + 1) * LW] - sp;
+      ph[k] = pc[(k + 1) * LW] + sp;
+      ql[k] = qc[(k + 1) * LW] - sq;
+      qh[k] = qc[(k + 1) * LW] + sq;
     }
     T f0s = T(0), fns = T(0), fts = T(0), dvs = T(0);
 #pragma unroll
@@ -824,23 +865,23 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     ures[q] = T(0);
     vres[q] = T(0);
     if (i >= nx || j >= ny) continue;
-    const int C0 = (r + 2) * WX + c + 2;   // radius-2 tile index of the cell
-    const int o = r * TX + c;
+    const int C0 = (r + 2) * LW + c + 2;   // radius-2 tile index of the cell
+    const int o = r * AXP + c;
     T e_ = sm.x.ax[0][o] + acc_e[q];
     T f_ = sm.x.ax[1][o] + acc_f[q];
     T g_ = sm.x.ax[2][o] + acc_g[q];
     const T Db = sm.db[C0];
     const T d0 = dpos(Db);
     const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
-    const T dym = dpos(sm.db[C0 - WX]), dyp = dpos(sm.db[C0 + WX]);
+    const T dym = dpos(sm.db[C0 - LW]), dyp = dpos(sm.db[C0 + LW]);
     const T ddx = (dxp - dxm) * D.i2dx, ddy = (dyp - dym) * D.i2dy;
     // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0)
     if (d0 > T(0)) {
 #define ETA(o) (sm.w[C0 + (o)] + fmin(sm.db[C0 + (o)], T(0)))
       const T e00 = ETA(0);
-      const T exm = ETA(-1), exp_ = ETA(1), eym = ETA(-WX), eyp = ETA(WX);
-      const T emm = ETA(-WX - 1), epm = ETA(-WX + 1), emp = ETA(WX - 1), epp = ETA(WX + 1);
-      const T exm2 = ETA(-2), exp2 = ETA(2), eym2 = ETA(-2 * WX), eyp2 = ETA(2 * WX);
+      const T exm = ETA(-1), exp_ = ETA(1), eym = ETA(-LW), eyp = ETA(LW);
+      const T emm = ETA(-LW - 1), epm = ETA(-LW + 1), emp = ETA(LW - 1), epp = ETA(LW + 1);
+      const T exm2 = ETA(-2), exp2 = ETA(2), eym2 = ETA(-2 * LW), eyp2 = ETA(2 * LW);
 #undef ETA
       const T exx = (exp_ - T(2) * e00 + exm) * D.idx2;
       const T eyy = (eyp - T(2) * e00 + eym) * D.idy2;
@@ -904,13 +945,13 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
       // depths of cells is-1 .. is+m (tile columns qc*MX+1 ..)
-      const T* dlx = sm.db + (r + 2) * WX + qc * MX + 1;
+      const T* dlx = sm.db + (r + 2) * LW + qc * MX + 1;
       T* rhs = sm.x.s.u + r * TXP + qc * MX;
       if (is == 0 && wave_w) {
         // Dirichlet ghost: the increment of P_{-1} from t_n to t_{n+1}
         T a, b, c;
         tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c);
-        rhs[0] -= a * ((T)st->gP[0] - sm.p[(r + 2) * WX + 1]);
+        rhs[0] -= a * ((T)st->gP[0] - sm.p[(r + 2) * LW + 1]);
       }
       chunk_solve_db<T, MX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs, 1);
       const int cgl = is / MX;
@@ -923,9 +964,9 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
-      const T* dly = sm.db + WX + c + 2;        // depths of rows j0-1 .. j0+m
+      const T* dly = sm.db + LW + c + 2;        // depths of rows j0-1 .. j0+m
       T* rhs = sm.x.s.v + c;
-      chunk_solve_db<T, TY>(dly, WX, m, D.tcy, j0 == 0, j0 + m == ny, rhs, TXP);
+      chunk_solve_db<T, TY>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, rhs, TXP);
       const int cgl = j0 / TY;
       const gp<T> chy = gbl(D.chy);
       chy[(size_t)cgl * nx + i] = rhs[0];
@@ -939,7 +980,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int r = rY0 + q;
-    const int C0 = (r + 2) * WX + cY + 2;
+    const int C0 = (r + 2) * LW + cY + 2;
     const unsigned ii = oI + (unsigned)(q * ipitch);
     stu(xhP, ii, sm.p[C0] + sm.x.s.u[r * TXP + cY]);
     stu(xhQ, ii, sm.q[C0] + sm.x.s.v[r * TXP + cY]);
@@ -987,14 +1028,14 @@ __device__ __forceinline__ void reduce_line(int C, int L, int line, const gp<con
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ doms, const int* __restrict__ line_prefix,
-                                                int nd) {
+__global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ doms, const int* __restrict__ line_map,
+                                                int nd, int lines) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= line_prefix[nd]) return;
-  const int dom = find_domain(line_prefix, nd, gid);
+  if (gid >= lines) return;
+  int dom, l;
+  locate(line_map, nd, gid, dom, l);
   const DomDev<T>& D = doms[dom];
   if (D.st->halt) return;
-  const int l = gid - line_prefix[dom];
   if (l < D.ny) reduce_line<T>(D.cx, D.ny, l, gbl((const T*)D.chx), gbl((const T*)D.rsx), gbl(D.ifx));
   else reduce_line<T>(D.cy, D.nx, l - D.ny, gbl((const T*)D.chy), gbl((const T*)D.rsy), gbl(D.ify));
 }
@@ -1051,26 +1092,30 @@ struct alignas(16) FinSmem {
   static constexpr int CXN = TX + 3, CYN = TY + 3;    // corners of cells i0-1 .. i0+TX, j0-1 .. j0+TY
   static constexpr int BX = TX + 2, BY = TY + 2;      // cells with one neighbour on each side
   static constexpr int TXP = TX + 1;
-  T dc[CYN * CXN];
   T db[BY * BX];                                      // cell still-water depth
-  T cx[TY * TXP];                                     // x-line correction of P
-  T cy[TY * TXP];                                     // y-line correction of Q
-  T px[TY * TXP];                                     // reciprocal pivots of the x solves
-  T py[TY * TXP];                                     // and of the y solves
+  union {
+    T dc[CYN * CXN];                                  // corners (until db is formed)
+    struct {
+      T cx[TY * TXP];                                 // x-line correction of P
+      T cy[TY * TXP];                                 // y-line correction of Q
+      T px[TY * TXP];                                 // reciprocal pivots of the x solves
+      T py[TY * TXP];                                 // and of the y solves
+    } s;
+  } u;
 };
 
 template <typename T, int TY, int MX>
-__global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_prefix,
+__global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                              int nd) {
   using S = FinSmem<T, TY, MX>;
   constexpr int CXN = S::CXN, BX = S::BX, TXP = S::TXP;
   constexpr int NWC = (S::CYN * CXN + NT - 1) / NT;
   __shared__ S sm;
-  const int dom = find_domain(tile_prefix, nd, blockIdx.x);
+  int dom, tile;
+  locate(tile_map, nd, blockIdx.x, dom, tile);
   const DomDev<T>& D = doms[dom];
   DevState* st = D.st;
   if (st->halt) return;
-  const int tile = blockIdx.x - tile_prefix[dom];
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int ns = st->slot == 2 ? 0 : st->slot + 1;    // slot of level n + 1
@@ -1088,8 +1133,23 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   const T dx = D.dx, dy = D.dy, g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
   const double dt = st->dt;
   constexpr int CPT = (TX * TY) / NT;
-  // all loads first: corners of the tile's cells and their neighbours, the
-  // local solutions and the new surface
+  // all loads first: the neighbour-chunk end values of this thread's line
+  // solve (if it has one), corners of the tile's cells and their
+  // neighbours, the local solutions and the new surface
+  constexpr int NCX = TX / MX;
+  T xl = T(0), xr = T(0);
+  if (tid < TY * NCX) {
+    const int r = tid / NCX, qc = tid - r * NCX;
+    const int j = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
+    const size_t o = (size_t)(is / MX) * ny + j;
+    xl = ifx[o];
+    xr = ifx[(size_t)D.cx * ny + o];
+  } else if (tid >= 64 && tid < 64 + TX) {
+    const int i = min(i0 + tid - 64, nx - 1);
+    const size_t o = (size_t)(j0 / TY) * nx + i;
+    xl = ify[o];
+    xr = ify[(size_t)D.cy * nx + o];
+  }
   T rc[NWC];
 #pragma unroll
   for (int k = 0; k < NWC; ++k) {
@@ -1112,13 +1172,13 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
 #pragma unroll
   for (int k = 0; k < NWC; ++k) {
     const int e = tid + k * NT;
-    if (e < S::CYN * CXN) sm.dc[e] = rc[k];
+    if (e < S::CYN * CXN) sm.u.dc[e] = rc[k];
   }
   __syncthreads();
   for (int e = tid; e < S::BY * BX; e += NT) {
     const int r = e / BX, c = e - r * BX;
-    sm.db[e] = dbar4(sm.dc[r * CXN + c], sm.dc[r * CXN + c + 1], sm.dc[(r + 1) * CXN + c],
-                     sm.dc[(r + 1) * CXN + c + 1]);
+    sm.db[e] = dbar4(sm.u.dc[r * CXN + c], sm.u.dc[r * CXN + c + 1], sm.u.dc[(r + 1) * CXN + c],
+                     sm.u.dc[(r + 1) * CXN + c + 1]);
   }
   __syncthreads();
   // Exact line solution = local solution + the response of the chunk system
@@ -1126,7 +1186,6 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   // line-coupling kernel): a right-hand side that is zero except -a x_left
   // in the first row and -c x_right in the last.  The response is solved
   // here from the static matrix instead of read as stored spikes.
-  constexpr int NCX = TX / MX;
   const bool wave_w = (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
   if (tid < TY * NCX) {
     const int r = tid / NCX, qc = tid - r * NCX;
@@ -1134,17 +1193,13 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
       const T* dlx = sm.db + (r + 1) * BX + qc * MX;   // cells is-1 .. is+m
-      T* rhs = sm.cx + r * TXP + qc * MX;
-      const size_t o = (size_t)(is / MX) * ny + j;
-      const T xl = ifx[o], xr = ifx[(size_t)D.cx * ny + o];
+      T* rhs = sm.u.s.cx + r * TXP + qc * MX;
       T a, b, c0, cm;
       tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c0);
       const T r0 = -a * xl;
       tri_coef(dpos(dlx[m - 1]), dpos(dlx[m]), dpos(dlx[m + 1]), D.tcx, a, b, cm);
-      for (int k = 0; k < m; ++k) rhs[k] = T(0);
-      rhs[0] = r0;
-      rhs[m - 1] -= cm * xr;
-      chunk_solve_lds<T>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs, sm.px + r * TXP + qc * MX, 1);
+      chunk_solve_lds<T, true>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs,
+                               sm.u.s.px + r * TXP + qc * MX, 1, r0, -cm * xr);
     }
   } else if (tid >= 64 && tid < 64 + TX) {
     const int c = tid - 64;
@@ -1152,17 +1207,12 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
       const T* dly = sm.db + c + 1;                    // rows j0-1 .. j0+m
-      T* rhs = sm.cy + c;
-      const size_t o = (size_t)(j0 / TY) * nx + i;
-      const T xl = ify[o], xr = ify[(size_t)D.cy * nx + o];
+      T* rhs = sm.u.s.cy + c;
       T a, b, c0, cm;
       tri_coef(dpos(dly[0]), dpos(dly[BX]), dpos(dly[2 * BX]), D.tcy, a, b, c0);
       const T r0 = -a * xl;
       tri_coef(dpos(dly[(m - 1) * BX]), dpos(dly[m * BX]), dpos(dly[(m + 1) * BX]), D.tcy, a, b, cm);
-      for (int k = 0; k < m; ++k) rhs[k * TXP] = T(0);
-      rhs[0] = r0;
-      rhs[(m - 1) * TXP] -= cm * xr;
-      chunk_solve_lds<T>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, rhs, sm.py + c, TXP);
+      chunk_solve_lds<T, true>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, rhs, sm.u.s.py + c, TXP, r0, -cm * xr);
     }
   }
   __syncthreads();
@@ -1171,8 +1221,8 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   for (int q = 0; q < CPT; ++q) {
     const int e = tid + q * NT;
     const int r = e / TX, c = e - r * TX;
-    lp[q] += sm.cx[r * TXP + c];
-    lq[q] += sm.cy[r * TXP + c];
+    lp[q] += sm.u.s.cx[r * TXP + c];
+    lq[q] += sm.u.s.cy[r * TXP + c];
     ld[q] = sm.db[(r + 1) * BX + c + 1];
   }
   double smax = 0.0;

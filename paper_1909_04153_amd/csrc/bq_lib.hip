@@ -310,8 +310,8 @@ __global__ void __launch_bounds__(256) k_diag(const DomDev<T>* Dp, int wslot, in
 struct Launch {
   // device tables of one launch group (a domain or a batch)
   void* table = nullptr;        // DomDev<T>[nd]
-  int* tile_prefix = nullptr;   // nd + 1
-  int* line_prefix = nullptr;   // nd + 1
+  int* tile_map = nullptr;      // per tile: domain << MAP_SHIFT | tile (batches; NULL for one domain)
+  int* line_map = nullptr;      // per line: domain << MAP_SHIFT | line
   int nd = 0, tiles = 0, lines = 0;
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;          // steps per replay (0 = none)
@@ -355,7 +355,7 @@ struct bq_batch {
 
 // layout of a domain in its workspace
 struct Layout {
-  size_t off_state, off_desc, off_tp, off_lp;
+  size_t off_state, off_desc;
   size_t off_w, off_P, off_Q, off_E, off_F, off_G;
   size_t off_Dc, off_Dbar, off_xhP, off_xhQ;
   size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
@@ -391,8 +391,6 @@ static Layout layout_for(const bq_params* p) {
   };
   L.off_state = take(sizeof(DevState));
   L.off_desc = take(sizeof(DomDev<T>));
-  L.off_tp = take(2 * sizeof(int));
-  L.off_lp = take(2 * sizeof(int));
   L.off_w = take(2 * L.ghosted);
   L.off_P = take(3 * L.ghosted);
   L.off_Q = take(3 * L.ghosted);
@@ -543,14 +541,10 @@ static int create_t(bq_domain* d, const double* depth_c) {
   HIPCHK(hipMemcpyAsync(d->ddev, &D, sizeof(D), hipMemcpyHostToDevice, s));
   // tables of the single-domain launch group
   d->L.table = d->ddev;
-  d->L.tile_prefix = (int*)(b + Ly.off_tp);
-  d->L.line_prefix = (int*)(b + Ly.off_lp);
+  d->L.tile_map = d->L.line_map = nullptr;
   d->L.nd = 1;
   d->L.tiles = Ly.tiles_x * Ly.tiles_y;
   d->L.lines = p->nx + p->ny;
-  const int tp[2] = {0, d->L.tiles}, lp[2] = {0, d->L.lines};
-  HIPCHK(hipMemcpyAsync(d->L.tile_prefix, tp, sizeof(tp), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(d->L.line_prefix, lp, sizeof(lp), hipMemcpyHostToDevice, s));
   if (D.n_waves > 0) {
     std::vector<double> wv(4 * (size_t)D.n_waves, 0.0);
     for (int m = 0; m < D.n_waves; ++m) {
@@ -619,9 +613,9 @@ static void enqueue_step(const Launch& L, hipStream_t s, double dt_prescribed) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
   k_dt<T><<<L.nd, 64, 0, s>>>(tab, dt_prescribed);
-  k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
-  k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_prefix, L.nd);
-  k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+  k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+  k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines);
+  k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
 }
 
 template <typename T>
@@ -671,11 +665,11 @@ static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
     if (hipEventRecord(ev[0], s) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventRecord"); break; }
     k_dt<T><<<L.nd, 64, 0, s>>>(tab, 0.0);
     (void)hipEventRecord(ev[1], s);
-    k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+    k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     (void)hipEventRecord(ev[2], s);
-    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_prefix, L.nd);
+    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines);
     (void)hipEventRecord(ev[3], s);
-    k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_prefix, L.nd);
+    k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     (void)hipEventRecord(ev[4], s);
     if (hipEventSynchronize(ev[4]) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventSynchronize"); break; }
     for (int k = 0; k < 4; ++k) {
@@ -801,50 +795,58 @@ static void drop_graph(Launch& L) {
   L.graph_built = 0;
 }
 
-// device tables (DomDev<T>[nd], tile and line prefixes) of one member list
+// bytes of the device tables of one member list: DomDev<T>[nd], tile map,
+// line map
 template <typename T>
-static int fill_launch(Launch& L, char* m, size_t tb, size_t pb, const std::vector<bq_domain*>& doms, hipStream_t s) {
+static size_t launch_bytes(const std::vector<bq_domain*>& doms) {
+  size_t tiles = 0, lines = 0;
+  for (const bq_domain* d : doms) {
+    const DomDev<T>& D = desc<T>(const_cast<bq_domain*>(d));
+    tiles += (size_t)D.tiles_x * D.tiles_y;
+    lines += (size_t)D.nx + D.ny;
+  }
+  return rup(sizeof(DomDev<T>) * doms.size(), 256) + rup(sizeof(int) * tiles, 256) + rup(sizeof(int) * lines, 256);
+}
+
+template <typename T>
+static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, hipStream_t s) {
   const int nd = (int)doms.size();
   std::vector<DomDev<T>> tab(nd);
-  std::vector<int> tp(nd + 1), lp(nd + 1);
-  tp[0] = lp[0] = 0;
+  std::vector<int> tmap, lmap;
   for (int k = 0; k < nd; ++k) {
     tab[k] = desc<T>(doms[k]);
-    tp[k + 1] = tp[k] + tab[k].tiles_x * tab[k].tiles_y;
-    lp[k + 1] = lp[k] + tab[k].nx + tab[k].ny;
+    const int nt = tab[k].tiles_x * tab[k].tiles_y, nl = tab[k].nx + tab[k].ny;
+    for (int t = 0; t < nt; ++t) tmap.push_back((k << MAP_SHIFT) | t);
+    for (int l = 0; l < nl; ++l) lmap.push_back((k << MAP_SHIFT) | l);
   }
+  const size_t tb = rup(sizeof(DomDev<T>) * nd, 256), mb = rup(sizeof(int) * tmap.size(), 256);
   HIPCHK(hipMemcpyAsync(m, tab.data(), sizeof(DomDev<T>) * nd, hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(m + tb, tp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemcpyAsync(m + tb + pb, lp.data(), sizeof(int) * (nd + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m + tb, tmap.data(), sizeof(int) * tmap.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m + tb + mb, lmap.data(), sizeof(int) * lmap.size(), hipMemcpyHostToDevice, s));
   drop_graph<T>(L);
   L.table = m;
-  L.tile_prefix = (int*)(m + tb);
-  L.line_prefix = (int*)(m + tb + pb);
+  L.tile_map = (int*)(m + tb);
+  L.line_map = (int*)(m + tb + mb);
   L.nd = nd;
-  L.tiles = tp[nd];
-  L.lines = lp[nd];
+  L.tiles = (int)tmap.size();
+  L.lines = (int)lmap.size();
   return BQ_OK;
 }
 
 template <typename T>
 static int batch_build_t(bq_batch* b) {
   const int nd = (int)b->doms.size();
-  const size_t tb = rup(sizeof(DomDev<T>) * (size_t)nd, 256), pb = rup(sizeof(int) * (size_t)(nd + 1), 256);
-  const size_t one = tb + 2 * pb;
-  const size_t need = 3 * one;
+  if (nd >= (1 << (31 - MAP_SHIFT))) return fail(BQ_EINVAL, "too many domains in one batch");
+  for (bq_domain* d : b->doms) {
+    const DomDev<T>& D = desc<T>(d);
+    if ((long long)D.tiles_x * D.tiles_y >= (1 << MAP_SHIFT) || D.nx + D.ny >= (1 << MAP_SHIFT))
+      return fail(BQ_EINVAL, "a batch member is too large for the work map");
+  }
   // the previous tables may still be read by queued work
   HIPCHK(hipStreamSynchronize(b->stream));
   if (b->aux) HIPCHK(hipStreamSynchronize(b->aux));
-  if (need > b->mem_bytes) {
-    if (b->mem) HIPCHK(hipFree(b->mem));
-    b->mem = nullptr;
-    HIPCHK(hipMalloc(&b->mem, need));
-    b->mem_bytes = need;
-  }
-  char* m = (char*)b->mem;
-  int rc = fill_launch<T>(b->L, m, tb, pb, b->doms, b->stream);
-  if (rc) return rc;
   b->lanes = (b->lanes_req == 2 && nd >= 2) ? 2 : 1;
+  std::vector<bq_domain*> part[2];
   if (b->lanes == 2) {
     // greedy split by cell count, largest first; members keep their order
     std::vector<int> ord(nd);
@@ -859,13 +861,25 @@ static int batch_build_t(bq_batch* b) {
       grp[k] = gsel;
       cells[gsel] += (long long)b->doms[k]->nx * b->doms[k]->ny;
     }
-    for (int gsel = 0; gsel < 2; ++gsel) {
-      std::vector<bq_domain*> part;
-      for (int k = 0; k < nd; ++k)
-        if (grp[k] == gsel) part.push_back(b->doms[k]);
-      rc = fill_launch<T>(b->G[gsel], m + (1 + gsel) * one, tb, pb, part, b->stream);
-      if (rc) return rc;
-    }
+    for (int k = 0; k < nd; ++k) part[grp[k]].push_back(b->doms[k]);
+  }
+  const size_t s0 = launch_bytes<T>(b->doms);
+  const size_t s1 = b->lanes == 2 ? launch_bytes<T>(part[0]) : 0;
+  const size_t s2 = b->lanes == 2 ? launch_bytes<T>(part[1]) : 0;
+  const size_t need = s0 + s1 + s2;
+  if (need > b->mem_bytes) {
+    if (b->mem) HIPCHK(hipFree(b->mem));
+    b->mem = nullptr;
+    HIPCHK(hipMalloc(&b->mem, need));
+    b->mem_bytes = need;
+  }
+  char* m = (char*)b->mem;
+  int rc = fill_launch<T>(b->L, m, b->doms, b->stream);
+  if (rc) return rc;
+  if (b->lanes == 2) {
+    rc = fill_launch<T>(b->G[0], m + s0, part[0], b->stream);
+    if (!rc) rc = fill_launch<T>(b->G[1], m + s0 + s1, part[1], b->stream);
+    if (rc) return rc;
     if (!b->aux) HIPCHK(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking));
     if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     if (!b->ev_join) HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
@@ -924,17 +938,18 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
     }
     for (int l = 0; l < 2; ++l) {
       const Launch& L = b->G[l];
-      k_rhs<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_prefix, L.nd);
+      k_rhs<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
       (void)hipEventRecord(ev[l][2], ss[l]);
     }
     for (int l = 0; l < 2; ++l) {
       const Launch& L = b->G[l];
-      k_reduced<T><<<cdiv(L.lines, 256), 256, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_prefix, L.nd);
+      k_reduced<T><<<cdiv(L.lines, 256), 256, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_map, L.nd,
+                                                          L.lines);
       (void)hipEventRecord(ev[l][3], ss[l]);
     }
     for (int l = 0; l < 2; ++l) {
       const Launch& L = b->G[l];
-      k_final<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_prefix, L.nd);
+      k_final<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
       (void)hipEventRecord(ev[l][4], ss[l]);
     }
     for (int l = 0; l < 2 && rc == BQ_OK; ++l)
