@@ -857,14 +857,18 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   T* const E0 = uni(D.E[slot]);
   T* const F0 = uni(D.F[slot]);
   T* const G0 = uni(D.G[slot]);
+  // The thread's cells are consecutive rows of one column, and the body is
+  // branch-free, so the stencil reads and the eta / depth values they share
+  // are formed once for all of them (cells outside the domain compute
+  // harmless values and store nothing).
+  const T i2dx = D.i2dx, i2dy = D.i2dy, idx2 = D.idx2, idy2 = D.idy2, i4dxdy = D.i4dxdy;
+  const T i2dx3 = D.i2dx3, i2dy3 = D.i2dy3, i2dxdy2 = D.i2dxdy2, i2dx2dy = D.i2dx2dy;
+  const T Bg = B * g;
   T ures[CPT], vres[CPT];
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int r = rY0 + q, c = cY;
-    const int i = i0 + c, j = j0 + r;
-    ures[q] = T(0);
-    vres[q] = T(0);
-    if (i >= nx || j >= ny) continue;
+    const bool in = (i0 + c < nx) & (j0 + r < ny);
     const int C0 = (r + 2) * LW + c + 2;   // radius-2 tile index of the cell
     const int o = r * AXP + c;
     T e_ = sm.x.ax[0][o] + acc_e[q];
@@ -874,57 +878,60 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const T d0 = dpos(Db);
     const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
     const T dym = dpos(sm.db[C0 - LW]), dyp = dpos(sm.db[C0 + LW]);
-    const T ddx = (dxp - dxm) * D.i2dx, ddy = (dyp - dym) * D.i2dy;
-    // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0)
-    if (d0 > T(0)) {
+    const T ddx = (dxp - dxm) * i2dx, ddy = (dyp - dym) * i2dy;
+    // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0); they
+    // vanish with d0 on land
+    {
 #define ETA(o) (sm.w[C0 + (o)] + fmin(sm.db[C0 + (o)], T(0)))
       const T e00 = ETA(0);
       const T exm = ETA(-1), exp_ = ETA(1), eym = ETA(-LW), eyp = ETA(LW);
       const T emm = ETA(-LW - 1), epm = ETA(-LW + 1), emp = ETA(LW - 1), epp = ETA(LW + 1);
       const T exm2 = ETA(-2), exp2 = ETA(2), eym2 = ETA(-2 * LW), eyp2 = ETA(2 * LW);
 #undef ETA
-      const T exx = (exp_ - T(2) * e00 + exm) * D.idx2;
-      const T eyy = (eyp - T(2) * e00 + eym) * D.idy2;
-      const T exy = ((epp - epm) - (emp - emm)) * D.i4dxdy;
-      const T exxx = ((exp2 - exm2) - T(2) * (exp_ - exm)) * D.i2dx3;
-      const T eyyy = ((eyp2 - eym2) - T(2) * (eyp - eym)) * D.i2dy3;
-      const T exyy = ((epp - T(2) * exp_ + epm) - (emp - T(2) * exm + emm)) * D.i2dxdy2;
-      const T exxy = ((epp - T(2) * eyp + emp) - (epm - T(2) * eym + emm)) * D.i2dx2dy;
-      const T bg = B * g * d0 * d0;
+      const T exx = (exp_ - T(2) * e00 + exm) * idx2;
+      const T eyy = (eyp - T(2) * e00 + eym) * idy2;
+      const T exy = ((epp - epm) - (emp - emm)) * i4dxdy;
+      const T exxx = ((exp2 - exm2) - T(2) * (exp_ - exm)) * i2dx3;
+      const T eyyy = ((eyp2 - eym2) - T(2) * (eyp - eym)) * i2dy3;
+      const T exyy = ((epp - T(2) * exp_ + epm) - (emp - T(2) * exm + emm)) * i2dxdy2;
+      const T exxy = ((epp - T(2) * eyp + emp) - (epm - T(2) * eym + emm)) * i2dx2dy;
+      const T bg = Bg * d0 * d0;
       f_ += bg * d0 * (exxx + exyy) + bg * (ddx * (T(2) * exx + eyy) + ddy * exy);
       g_ += bg * d0 * (eyyy + exxy) + bg * (ddy * (T(2) * eyy + exx) + ddx * exy);
     }
     // Manning friction f1, f2 at the cell centre
-    const T h = fmax(sm.w[C0] + Db, T(0));
     const T Pc = sm.p[C0], Qc = sm.q[C0];
-    if (h > T(0) && gn2 > T(0)) {
+    if (gn2 > T(0)) {
+      const T h = fmax(sm.w[C0] + Db, T(0));
       const T vf = vfac(h, eps);
       const T u = Pc * vf, v = Qc * vf;
-      const T k = gn2 * fsqrt(u * u + v * v) * frcbrt(h);
+      const T k = h > T(0) ? gn2 * fsqrt(u * u + v * v) * frcbrt(h) : T(0);
       f_ -= k * u;
       g_ -= k * v;
     }
     // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k}) (Eq. 14-15 are linear)
     const int B0 = (r + 1) * BX + c + 1;
-    const T qy = (sm.qt[B0 + BX] - sm.qt[B0 - BX]) * D.i2dy;
-    const T qx = (sm.qt[B0 + 1] - sm.qt[B0 - 1]) * D.i2dx;
-    const T qxy = ((sm.qt[B0 + BX + 1] - sm.qt[B0 - BX + 1]) - (sm.qt[B0 + BX - 1] - sm.qt[B0 - BX - 1])) * D.i4dxdy;
-    const T py = (sm.pt[B0 + BX] - sm.pt[B0 - BX]) * D.i2dy;
-    const T px = (sm.pt[B0 + 1] - sm.pt[B0 - 1]) * D.i2dx;
-    const T pxy = ((sm.pt[B0 + BX + 1] - sm.pt[B0 - BX + 1]) - (sm.pt[B0 + BX - 1] - sm.pt[B0 - BX - 1])) * D.i4dxdy;
+    const T qy = (sm.qt[B0 + BX] - sm.qt[B0 - BX]) * i2dy;
+    const T qx = (sm.qt[B0 + 1] - sm.qt[B0 - 1]) * i2dx;
+    const T qxy = ((sm.qt[B0 + BX + 1] - sm.qt[B0 - BX + 1]) - (sm.qt[B0 + BX - 1] - sm.qt[B0 - BX - 1])) * i4dxdy;
+    const T py = (sm.pt[B0 + BX] - sm.pt[B0 - BX]) * i2dy;
+    const T px = (sm.pt[B0 + 1] - sm.pt[B0 - 1]) * i2dx;
+    const T pxy = ((sm.pt[B0 + BX + 1] - sm.pt[B0 - BX + 1]) - (sm.pt[B0 + BX - 1] - sm.pt[B0 - BX - 1])) * i4dxdy;
     const T fs = d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
     const T gs = d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
     // Eq. (42)-(43)
-    const unsigned ii = oI + (unsigned)(q * ipitch);
-    stu(E0, ii, e_);
-    stu(F0, ii, f_);
-    stu(G0, ii, g_);
-    stu(wn, oG + (unsigned)(q * pitch), sm.w[C0] + (a0 * e_ + a1 * he1[q] + a2 * he2[q]));
+    if (in) {
+      const unsigned ii = oI + (unsigned)(q * ipitch);
+      stu(E0, ii, e_);
+      stu(F0, ii, f_);
+      stu(G0, ii, g_);
+      stu(wn, oG + (unsigned)(q * pitch), sm.w[C0] + (a0 * e_ + a1 * he1[q] + a2 * he2[q]));
+    }
     // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
     // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
     // U*^n = T P^n with the same matrix
-    ures[q] = (a0 * f_ + a1 * hf1[q] + a2 * hf2[q]) + fs;
-    vres[q] = (a0 * g_ + a1 * hg1[q] + a2 * hg2[q]) + gs;
+    ures[q] = in ? (a0 * f_ + a1 * hf1[q] + a2 * hf2[q]) + fs : T(0);
+    vres[q] = in ? (a0 * g_ + a1 * hg1[q] + a2 * hg2[q]) + gs : T(0);
   }
   __syncthreads();  // x-parts consumed; the union now holds U*, V*
 #pragma unroll
@@ -1003,26 +1010,57 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 template <typename T>
 __device__ __forceinline__ void reduce_line(int C, int L, int line, const gp<const T> ch, const gp<const T> rs,
                                             const gp<T> itf) {
+  // The recurrences are serial in c, their inputs are not: the inputs of
+  // RB chunks are loaded together ahead of the RB dependent steps.
+  constexpr int RB = 8;
   const size_t CL = (size_t)C * L;
   T al = T(0);
-  for (int c = 0; c < C; ++c) {
-    const size_t o = (size_t)c * L + line;
-    const T xs = ch[o], xe = ch[CL + o];
-    const T sg = rs[o] * xs + rs[CL + o] * al;
-    al = xe + rs[2 * CL + o] * al + rs[3 * CL + o] * sg;
-    itf[o] = sg;          // temporarily sigma_c, alpha_c
-    itf[CL + o] = al;
+  for (int c0 = 0; c0 < C; c0 += RB) {
+    T xs[RB], xe[RB], r0[RB], r1[RB], r2[RB], r3[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const size_t o = (size_t)min(c0 + k, C - 1) * L + line;
+      xs[k] = ch[o];
+      xe[k] = ch[CL + o];
+      r0[k] = rs[o];
+      r1[k] = rs[CL + o];
+      r2[k] = rs[2 * CL + o];
+      r3[k] = rs[3 * CL + o];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      if (c0 + k < C) {
+        const size_t o = (size_t)(c0 + k) * L + line;
+        const T sg = r0[k] * xs[k] + r1[k] * al;
+        al = xe[k] + r2[k] * al + r3[k] * sg;
+        itf[o] = sg;          // temporarily sigma_c, alpha_c
+        itf[CL + o] = al;
+      }
+    }
   }
   T xs_next = T(0);
-  for (int c = C - 1; c >= 0; --c) {
-    const size_t o = (size_t)c * L + line;
-    const T sg = itf[o], a = itf[CL + o];
-    const T Xs = sg + rs[4 * CL + o] * xs_next;
-    const T Xe = a + rs[5 * CL + o] * xs_next;
-    itf[CL + o] = xs_next;                    // right neighbour of chunk c
-    if (c + 1 < C) itf[o + L] = Xe;          // left neighbour of chunk c + 1
-    xs_next = Xs;
-    (void)Xe;
+  for (int c1 = C - 1; c1 >= 0; c1 -= RB) {
+    T sg[RB], a[RB], r4[RB], r5[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const size_t o = (size_t)max(c1 - k, 0) * L + line;
+      sg[k] = itf[o];
+      a[k] = itf[CL + o];
+      r4[k] = rs[4 * CL + o];
+      r5[k] = rs[5 * CL + o];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const int c = c1 - k;
+      if (c >= 0) {
+        const size_t o = (size_t)c * L + line;
+        const T Xs = sg[k] + r4[k] * xs_next;
+        const T Xe = a[k] + r5[k] * xs_next;
+        itf[CL + o] = xs_next;                    // right neighbour of chunk c
+        if (c + 1 < C) itf[o + L] = Xe;          // left neighbour of chunk c + 1
+        xs_next = Xs;
+      }
+    }
   }
   itf[line] = T(0);                           // chunk 0 has no left neighbour
 }

@@ -19,14 +19,23 @@ using namespace bqk;
 // ---------------------------------------------------------------------------
 // tile configuration per precision
 // ---------------------------------------------------------------------------
+// Tile height (= y-chunk length) and x-chunk length of the line solves;
+// the chunk lengths are build-time tunables (BQ_MX_F32 / BQ_MX_F64, a
+// divisor of the 64-cell tile width).
+#ifndef BQ_MX_F32
+#define BQ_MX_F32 32
+#endif
+#ifndef BQ_MX_F64
+#define BQ_MX_F64 32
+#endif
 template <typename T> struct Cfg;
 template <> struct Cfg<float> {
   static constexpr int TY = 16;
-  static constexpr int MX = 32;
+  static constexpr int MX = BQ_MX_F32;
 };
 template <> struct Cfg<double> {
   static constexpr int TY = 8;
-  static constexpr int MX = 32;
+  static constexpr int MX = BQ_MX_F64;
 };
 
 static thread_local char g_err[512] = "";
