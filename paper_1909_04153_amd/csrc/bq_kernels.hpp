@@ -384,23 +384,21 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
-// The same solve for kernels that must stay light on registers: the
-// reciprocal pivots go to LDS (pv, stride rs) and the upper diagonal is
-// recomputed in the backward sweep.  The sweeps stay rolled; each iteration
-// issues the next row's LDS reads before its own dependent arithmetic, so
-// the read latency overlaps the pivot recurrence.
-// EDGE: the right-hand side is zero except r0 in the first row and r1 in the
-// last (rhs is then only written), as for the response to the neighbour
-// chunks' end values.
-template <typename T, bool EDGE>
-__device__ __forceinline__ void chunk_solve_lds(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
-                                                T* rhs, T* pv, int rs, T r0 = T(0), T r1 = T(0)) {
+// Response of a chunk system to a right-hand side that is zero except r0 in
+// the first row and r1 in the last (the coupling to the neighbour chunks'
+// end values), for a kernel that must stay light on registers.  The forward
+// sweep keeps y_k / u_k and c_k / u_k in LDS (out, cu; stride rs), so the
+// backward sweep is one multiply-add per row: x_k = y_k/u_k - (c_k/u_k) x_{k+1}.
+// Each iteration issues the next row's LDS read before its own dependent
+// arithmetic, so the read latency overlaps the pivot recurrence.
+template <typename T>
+__device__ __forceinline__ void chunk_edge_solve(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                                 T r0, T r1, T* out, T* cu, int rs) {
   T d0 = dpos(Dl[0]), d1 = dpos(Dl[ds]), d2 = dpos(Dl[2 * ds]);
-  T r = EDGE ? (m == 1 ? r0 + r1 : r0) : rhs[0];
+  T r = m == 1 ? r0 + r1 : r0;
   T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
   for (int k = 0; k < m; ++k) {
     const T d3 = dpos(Dl[(k + 3 <= m + 1 ? k + 3 : m + 1) * ds]);
-    const T rn = EDGE ? (k + 2 == m ? r1 : T(0)) : rhs[(k + 1 < m ? k + 1 : k) * rs];
     T a, b, c;
     tri_coef(d0, d1, d2, tc, a, b, c);
     if (k == 0 && fold_lo) b -= a;
@@ -415,36 +413,27 @@ __device__ __forceinline__ void chunk_solve_lds(const T* Dl, int ds, int m, cons
       y = r - l * y_prev;
     }
     const T iu = frcp(u);
-    pv[k * rs] = iu;
-    rhs[k * rs] = y;
+    out[k * rs] = y * iu;
+    cu[k * rs] = c * iu;
     y_prev = y;
     iu_prev = iu;
     c_prev = c;
     d0 = d1;
     d1 = d2;
     d2 = d3;
-    r = rn;
+    r = k + 2 == m ? r1 : T(0);
   }
-  // backward: row k needs the depths of rows k-1, k, k+1 (Dl[k .. k+2])
-  T x_next = y_prev * iu_prev;
-  rhs[(m - 1) * rs] = x_next;
+  T x_next = out[(m - 1) * rs];
   if (m < 2) return;
-  T e0 = dpos(Dl[(m - 2) * ds]), e1 = dpos(Dl[(m - 1) * ds]), e2 = dpos(Dl[m * ds]);
-  T yk = rhs[(m - 2) * rs], pk = pv[(m - 2) * rs];
+  T yk = out[(m - 2) * rs], ck = cu[(m - 2) * rs];
   for (int k = m - 2; k >= 0; --k) {
     const int kn = k > 0 ? k - 1 : 0;
-    const T en = dpos(Dl[kn * ds]);
-    const T yn = rhs[kn * rs], pn = pv[kn * rs];
-    T a, b, c;
-    tri_coef(e0, e1, e2, tc, a, b, c);
-    const T x = (yk - c * x_next) * pk;
-    rhs[k * rs] = x;
+    const T yn = out[kn * rs], cn = cu[kn * rs];
+    const T x = yk - ck * x_next;
+    out[k * rs] = x;
     x_next = x;
-    e2 = e1;
-    e1 = e0;
-    e0 = en;
     yk = yn;
-    pk = pn;
+    ck = cn;
   }
 }
 
@@ -1136,8 +1125,8 @@ struct alignas(16) FinSmem {
     struct {
       T cx[TY * TXP];                                 // x-line correction of P
       T cy[TY * TXP];                                 // y-line correction of Q
-      T px[TY * TXP];                                 // reciprocal pivots of the x solves
-      T py[TY * TXP];                                 // and of the y solves
+      T ux[TY * TXP];                                 // c_k / u_k of the x solves
+      T uy[TY * TXP];                                 // and of the y solves
     } s;
   } u;
 };
@@ -1147,7 +1136,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
                                              int nd) {
   using S = FinSmem<T, TY, MX>;
   constexpr int CXN = S::CXN, BX = S::BX, TXP = S::TXP;
-  constexpr int NWC = (S::CYN * CXN + NT - 1) / NT;
+  constexpr int CPT = (TX * TY) / NT;
   __shared__ S sm;
   int dom, tile;
   locate(tile_map, nd, blockIdx.x, dom, tile);
@@ -1156,62 +1145,58 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   if (st->halt) return;
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
-  const int ns = st->slot == 2 ? 0 : st->slot + 1;    // slot of level n + 1
-  T* w = D.w[(st->n + 1) & 1];
-  T* P = D.P[ns];
-  T* Q = D.Q[ns];
-  const gp<T> gw = gbl(w);
-  const gp<T> gP = gbl(P);
-  const gp<T> gQ = gbl(Q);
-  const gp<const T> xhP = gbl((const T*)D.xhP);
-  const gp<const T> xhQ = gbl((const T*)D.xhQ);
-  const gp<const T> ifx = gbl((const T*)D.ifx);
-  const gp<const T> ify = gbl((const T*)D.ify);
-  const gp<const T> Dc = gbl((const T*)D.Dc);
-  const T dx = D.dx, dy = D.dy, g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
-  const double dt = st->dt;
-  constexpr int CPT = (TX * TY) / NT;
+  const int ns = uni(st->slot == 2 ? 0 : st->slot + 1);   // slot of level n + 1
+  const int par = uni((int)((st->n + 1) & 1));
+  T* const w = uni(D.w[par]);
+  T* const P = uni(D.P[ns]);
+  T* const Q = uni(D.Q[ns]);
+  const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
+  const T g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
+  // cells of a thread: column cY, rows rY0 .. rY0+CPT-1 (as in the stencil kernel)
+  const int cY = tid % TX, rY0 = (tid / TX) * CPT;
+  const unsigned oI = (unsigned)((j0 + rY0) * ipitch + i0 + cY);
+  const unsigned oG = (unsigned)((j0 + rY0 + 2) * pitch + xoff + i0 + cY);
   // all loads first: the neighbour-chunk end values of this thread's line
-  // solve (if it has one), corners of the tile's cells and their
-  // neighbours, the local solutions and the new surface
+  // solve (if it has one), the corners of the tile's cells and their
+  // neighbours (rows read in groups, no clamping: the fields are padded to
+  // whole tiles), the local solutions and the new surface
   constexpr int NCX = TX / MX;
   T xl = T(0), xr = T(0);
   if (tid < TY * NCX) {
     const int r = tid / NCX, qc = tid - r * NCX;
     const int j = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
     const size_t o = (size_t)(is / MX) * ny + j;
-    xl = ifx[o];
-    xr = ifx[(size_t)D.cx * ny + o];
+    xl = D.ifx[o];
+    xr = D.ifx[(size_t)D.cx * ny + o];
   } else if (tid >= 64 && tid < 64 + TX) {
     const int i = min(i0 + tid - 64, nx - 1);
     const size_t o = (size_t)(j0 / TY) * nx + i;
-    xl = ify[o];
-    xr = ify[(size_t)D.cy * nx + o];
+    xl = D.ify[o];
+    xr = D.ify[(size_t)D.cy * nx + o];
   }
-  T rc[NWC];
+  constexpr int RGC = NT / CXN, KC = (S::CYN + RGC - 1) / RGC;
+  const int rC = min(tid / CXN, RGC - 1), cC = tid - (tid / CXN) * CXN;
+  auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
+  T rc[KC];
+  {
+    const T* Dc = uni((const T*)D.Dc);
+    const unsigned oC = (unsigned)((j0 + 1) * cpitch + i0 + 1 + cC);   // corner (i0-1+cC, j0-1)
 #pragma unroll
-  for (int k = 0; k < NWC; ++k) {
-    const int e = min(tid + k * NT, S::CYN * CXN - 1);
-    const int r = e / CXN, c = e - r * CXN;
-    const int ic = min(i0 + c - 1, nx + 2), jc = min(j0 + r - 1, ny + 2);
-    rc[k] = Dc[(size_t)(jc + 2) * D.cpitch + ic + 2];
+    for (int k = 0; k < KC; ++k) rc[k] = ldu(Dc, oC + (unsigned)(rowC(k) * cpitch));
   }
   T lp[CPT], lq[CPT], lw[CPT];
+  {
+    const T* xhP = uni((const T*)D.xhP);
+    const T* xhQ = uni((const T*)D.xhQ);
 #pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int e = tid + q * NT;
-    const int r = e / TX, c = e - r * TX;
-    const int i = min(i0 + c, nx - 1), j = min(j0 + r, ny - 1);
-    const size_t ii = (size_t)j * D.ipitch + i;
-    lp[q] = xhP[ii];
-    lq[q] = xhQ[ii];
-    lw[q] = gw[(size_t)(j + 2) * D.pitch + D.xoff + i];
+    for (int q = 0; q < CPT; ++q) {
+      lp[q] = ldu(xhP, oI + (unsigned)(q * ipitch));
+      lq[q] = ldu(xhQ, oI + (unsigned)(q * ipitch));
+      lw[q] = ldu((const T*)w, oG + (unsigned)(q * pitch));
+    }
   }
 #pragma unroll
-  for (int k = 0; k < NWC; ++k) {
-    const int e = tid + k * NT;
-    if (e < S::CYN * CXN) sm.u.dc[e] = rc[k];
-  }
+  for (int k = 0; k < KC; ++k) sm.u.dc[rowC(k) * CXN + cC] = rc[k];
   __syncthreads();
   for (int e = tid; e < S::BY * BX; e += NT) {
     const int r = e / BX, c = e - r * BX;
@@ -1231,13 +1216,12 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
       const T* dlx = sm.db + (r + 1) * BX + qc * MX;   // cells is-1 .. is+m
-      T* rhs = sm.u.s.cx + r * TXP + qc * MX;
       T a, b, c0, cm;
       tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c0);
       const T r0 = -a * xl;
       tri_coef(dpos(dlx[m - 1]), dpos(dlx[m]), dpos(dlx[m + 1]), D.tcx, a, b, cm);
-      chunk_solve_lds<T, true>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs,
-                               sm.u.s.px + r * TXP + qc * MX, 1, r0, -cm * xr);
+      chunk_edge_solve<T>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, r0, -cm * xr,
+                          sm.u.s.cx + r * TXP + qc * MX, sm.u.s.ux + r * TXP + qc * MX, 1);
     }
   } else if (tid >= 64 && tid < 64 + TX) {
     const int c = tid - 64;
@@ -1245,37 +1229,30 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
       const T* dly = sm.db + c + 1;                    // rows j0-1 .. j0+m
-      T* rhs = sm.u.s.cy + c;
       T a, b, c0, cm;
       tri_coef(dpos(dly[0]), dpos(dly[BX]), dpos(dly[2 * BX]), D.tcy, a, b, c0);
       const T r0 = -a * xl;
       tri_coef(dpos(dly[(m - 1) * BX]), dpos(dly[m * BX]), dpos(dly[(m + 1) * BX]), D.tcy, a, b, cm);
-      chunk_solve_lds<T, true>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, rhs, sm.u.s.py + c, TXP, r0, -cm * xr);
+      chunk_edge_solve<T>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, r0, -cm * xr, sm.u.s.cy + c, sm.u.s.uy + c,
+                          TXP);
     }
   }
   __syncthreads();
-  T ld[CPT];
+  // new state, sponge, CFL speeds (Eq. 22) and ghost cells
+  const double dt = st->dt;
+  T smax = T(0);
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
-    const int e = tid + q * NT;
-    const int r = e / TX, c = e - r * TX;
-    lp[q] += sm.u.s.cx[r * TXP + c];
-    lq[q] += sm.u.s.cy[r * TXP + c];
-    ld[q] = sm.db[(r + 1) * BX + c + 1];
-  }
-  double smax = 0.0;
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int e = tid + q * NT;
-    const int r = e / TX, c = e - r * TX;
-    const int i = i0 + c, j = j0 + r;
+    const int r = rY0 + q, i = i0 + cY, j = j0 + r;
+    T p = lp[q] + sm.u.s.cx[r * TXP + cY];
+    T qv = lq[q] + sm.u.s.cy[r * TXP + cY];
+    T wv = lw[q];
+    const T Db = sm.db[(r + 1) * BX + cY + 1];
     if (i >= nx || j >= ny) continue;
-    T p = lp[q], qv = lq[q], wv = lw[q];
-    const T Db = ld[q];
-    const size_t gidx = (size_t)(j + 2) * D.pitch + D.xoff + i;
+    const unsigned og = oG + (unsigned)(q * pitch);
     if (D.any_sponge && Db > T(0)) {
-      const T dist[4] = {(T(i) + T(0.5)) * dx, (T(nx - i) - T(0.5)) * dx, (T(j) + T(0.5)) * dy,
-                         (T(ny - j) - T(0.5)) * dy};
+      const T dist[4] = {(T(i) + T(0.5)) * D.dx, (T(nx - i) - T(0.5)) * D.dx, (T(j) + T(0.5)) * D.dy,
+                         (T(ny - j) - T(0.5)) * D.dy};
       T sig = T(0);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
@@ -1290,32 +1267,31 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
         wv *= fac;
         p *= fac;
         qv *= fac;
-        gw[gidx] = wv;
+        stu(w, og, wv);
       }
     }
-    gP[gidx] = p;
-    gQ[gidx] = qv;
-    // Eq. (22) speeds of the new state
+    stu(P, og, p);
+    stu(Q, og, qv);
     const T h = fmax(wv + Db, T(0));
     const T vf = vfac(h, eps);
     const T u = p * vf, v = qv * vf;
     const T cel = fsqrt(g * h);
     const T sx = (fabs(u) + cel) * idx, sy = (fabs(v) + cel) * idy;
     // a NaN in either direction must reach the maximum as +inf
-    double sd = (sx != sx || sy != sy) ? __longlong_as_double(0x7ff0000000000000ll) : (double)fmax(sx, sy);
+    const T sd = (sx != sx || sy != sy) ? T(INFINITY) : fmax(sx, sy);
     smax = fmax(smax, sd);
-    // ghost cells of the new state
     if (i < 2 || i >= nx - 2 || j < 2 || j >= ny - 2) ghost_cell(D, w, P, Q, i, j, wv, p, qv, st->gw, st->gP);
   }
-  // block max -> one atomic per block
-  __shared__ double red[NT / 64];
+  // block max -> one atomic per block (max commutes with the widening to
+  // FP64, so the FP32 maximum converts to the same value)
+  __shared__ T red[NT / 64];
   for (int o = 32; o > 0; o >>= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
   if ((tid & 63) == 0) red[tid >> 6] = smax;
   __syncthreads();
   if (tid == 0) {
-    double m = red[0];
+    T m = red[0];
     for (int k = 1; k < NT / 64; ++k) m = fmax(m, red[k]);
-    atomicMax(&st->smax_bits, (unsigned long long)__double_as_longlong(m));
+    atomicMax(&st->smax_bits, (unsigned long long)__double_as_longlong((double)m));
   }
 }
 
