@@ -97,6 +97,9 @@ void bqo_fd_weights(double h1, double h2, double D[9]);
 void bqo_step_weights(int64_t n, int32_t fstar_order, double h0, double h1, double h2, double alpha[3], double D[9]);
 double bqo_lazy_ema(double cand, double prev, double a);
 void bqo_thomas(int32_t n, const double* a, const double* b, const double* c, const double* r, double* x);
+/* Line solve of Eq. (19)-(21) used by the step: Thomas plus one step of
+ * iterative refinement with the residual in extended precision. */
+void bqo_solve_line(int32_t n, const double* a, const double* b, const double* c, const double* r, double* x);
 double bqo_minmod(double a, double b, double c);
 double bqo_ms_wavenumber(double omega, double depth, double g, double B);
 /* single x-face KP07 flux between a left cell (wL, PL, QL) and a right cell

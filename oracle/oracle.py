@@ -82,6 +82,7 @@ def lib():
         L.bqo_lazy_ema.restype = ctypes.c_double
         L.bqo_lazy_ema.argtypes = [ctypes.c_double] * 3
         L.bqo_thomas.argtypes = [ctypes.c_int32, dp, dp, dp, dp, dp]
+        L.bqo_solve_line.argtypes = [ctypes.c_int32, dp, dp, dp, dp, dp]
         L.bqo_minmod.restype = ctypes.c_double
         L.bqo_minmod.argtypes = [ctypes.c_double] * 3
         L.bqo_ms_wavenumber.restype = ctypes.c_double
@@ -130,6 +131,14 @@ def thomas(a, b, c, r):
     a, b, c, r = (_f64(v) for v in (a, b, c, r))
     x = np.zeros_like(r)
     lib().bqo_thomas(len(r), _ptr(a), _ptr(b), _ptr(c), _ptr(r), _ptr(x))
+    return x
+
+
+def solve_line(a, b, c, r):
+    """the step's line solve: Thomas plus one extended-precision refinement"""
+    a, b, c, r = (_f64(v) for v in (a, b, c, r))
+    x = np.zeros_like(r)
+    lib().bqo_solve_line(len(r), _ptr(a), _ptr(b), _ptr(c), _ptr(r), _ptr(x))
     return x
 
 

@@ -100,9 +100,11 @@ CASES = {
     "central_slopes": lambda: S.standing_wave_1d(2.0, cells_per_wavelength=40, rel_amp=1e-2, theta=0.0),
     # smallest domain
     "tiny_4x4": lambda: S.closed_basin_hump(nx=4, ny=4, dx=0.5, cfl=0.125, fstar_order=1),
+    # x-lines of 2100 cells: more chunks than one wave of the line coupling
+    "long_lines": lambda: S.solitary_flat(nx=2100, ny=8, dx=0.05, x0=50.0),
 }
 STEPS = {"beach_ragged": 700, "rip_2d": 150, "hump_2d": 300, "dam_break": 200, "central_slopes": 300,
-         "tiny_4x4": 100}
+         "tiny_4x4": 100, "long_lines": 100}
 
 
 @pytest.mark.parametrize("case", sorted(CASES))

@@ -4,6 +4,7 @@ the generalised minmod, the KP07 central-upwind face flux (reading of Sec.
 import math
 
 import numpy as np
+import pytest
 
 from oracle import oracle as O
 
@@ -23,6 +24,47 @@ def test_thomas_matches_dense_solve():
         x = O.thomas(a, b, c, r)
         assert np.max(np.abs(M @ x - r)) <= 1e-12 * np.max(np.abs(r)) * np.max(b)
         np.testing.assert_allclose(x, x_ref, rtol=1e-12, atol=1e-14)
+
+
+def _thomas_extended(a, b, c, r):
+    # the same elimination in numpy's extended precision (80-bit on x86-64)
+    a, b, c, r = (np.asarray(v, dtype=np.longdouble) for v in (a, b, c, r))
+    n = len(r)
+    cp = np.zeros(n, dtype=np.longdouble)
+    rp = np.zeros(n, dtype=np.longdouble)
+    cp[0], rp[0] = c[0] / b[0], r[0] / b[0]
+    for i in range(1, n):
+        m = b[i] - a[i] * cp[i - 1]
+        cp[i], rp[i] = c[i] / m, (r[i] - a[i] * rp[i - 1]) / m
+    x = np.zeros(n, dtype=np.longdouble)
+    x[-1] = rp[-1]
+    for i in range(n - 2, -1, -1):
+        x[i] = rp[i] - cp[i] * x[i + 1]
+    return x
+
+
+def test_line_solve_reaches_the_exact_solution_on_long_lines():
+    # Eq. 19-21 on a 2100-cell line at d/dx = 20 ((B + 1/3) d^2/dx^2 = 160,
+    # condition number ~641), wall folds at both ends, a smooth wave plus
+    # noise on the right-hand side: the plain FP64 sweep is ~1e-14 off the
+    # extended-precision solution; the step's refined solve must be at
+    # FP64 rounding of it
+    if np.finfo(np.longdouble).eps > 1e-18:
+        pytest.skip("no extended precision long double on this host")
+    n, k = 2100, (1.0 / 15.0 + 1.0 / 3.0) * 400.0
+    a = np.full(n, -k)
+    c = np.full(n, -k)
+    b = np.full(n, 1.0 + 2.0 * k)
+    b[0] -= a[0]
+    b[-1] -= c[-1]
+    a[0] = c[-1] = 0.0
+    rng = np.random.default_rng(1)
+    x0 = np.arange(n) * 0.05
+    r = 0.1 * np.exp(-((x0 - 50.0) / 1.0) ** 2) + 1e-3 * rng.normal(size=n)
+    xe = _thomas_extended(a, b, c, r)
+    rel = lambda x: float(np.linalg.norm((x - xe).astype(np.float64)) / np.linalg.norm(xe.astype(np.float64)))
+    assert rel(O.solve_line(a, b, c, r)) <= 2e-16
+    assert rel(O.thomas(a, b, c, r)) >= 1e-15   # the refinement is what closes the gap
 
 
 def test_minmod():
