@@ -136,6 +136,53 @@ def cpu_baseline(specs, budget_s):
     return done_cells / used, used, names
 
 
+def _oracle_worker(args):
+    spec, budget_s = args
+    from oracle.oracle import OracleDomain
+
+    o = OracleDomain(spec["params"], spec["depth_c"])
+    o.set_state(spec["eta"], spec["P"], spec["Q"])
+    n = spec["params"]["nx"] * spec["params"]["ny"]
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        if o.step(1) != 0:
+            break
+        steps += 1
+    el = time.perf_counter() - t0
+    o.close()
+    return n * steps, el
+
+
+def cpu_baseline_all_cores(specs, budget_s, cores):
+    """one oracle process per core on distinct domains of the batch (the
+    oracle itself is single-threaded): aggregate cell-steps/s"""
+    import multiprocessing as mp
+
+    jobs = [(specs[k % len(specs)], budget_s) for k in range(cores)]
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    return sum(c / e for c, e in res if e > 0)
+
+
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """device-to-device copy of `mib` MiB: (read + write) bytes / time"""
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.ones(n, dtype=torch.uint8, device="cuda")
+    a.copy_(b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        a.copy_(b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n / (ms * 1e-3) / 1e9
+
+
 def serve_run(bq, seconds):
     """a short Poisson request stream (mixed sizes 128..1024, 2..12 s simulated
     each) through the continuous-batching loop"""
@@ -248,7 +295,23 @@ def main():
         out["kernels_ms_two_lane"] = kms2
     del group, doms
     torch.cuda.synchronize()
+    out["copy_gbs"] = copy_bandwidth(torch)
+    tr = roof["traffic"]
+    if tr:
+        roof["traffic_gbs"] = tr / (kms[dom_k] * 1e-3) / 1e9
+        roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
     if not args.no_fp64:
+        # one C3-type domain (2048 x 2048 rip beach, FP32): the single-domain rate
+        sp, dt_ = workload("rip2048")
+        ds, g = make_group(bq, sp, dt_)
+        c = sum(s["params"]["nx"] * s["params"]["ny"] for s in sp)
+        n = max(20, args.steps // 2)
+        e = timed(torch, g, n, args.warmup)
+        out["fp32_single_c3"] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / n * 1e3,
+                                 "cells": c, "steps": n,
+                                 "effective_hbm_frac": WORDS_STEP * 4 * c * n / e / 1e9 / HBM_PEAK_GBS}
+        del g, ds
+        torch.cuda.synchronize()
         fp64 = {}
         for wl in ("beach1024x256_fp64", "solitary200x20"):
             sp, dt_ = workload(wl)
@@ -267,6 +330,11 @@ def main():
         out["cpu_baseline"] = {"value": rate / 1e9, "unit": "Gcell-steps/s", "cores": 1, "kind": "oracle",
                                "seconds": used, "sample": "; ".join(names),
                                "host_cpus": os.cpu_count()}
+        cores = max(1, min(16, os.cpu_count() or 1))
+        agg = cpu_baseline_all_cores(specs, args.cpu_seconds / 2, cores)
+        out["cpu_baseline_all_cores"] = {"value": agg / 1e9, "unit": "Gcell-steps/s", "cores": cores,
+                                         "kind": "oracle", "sample": f"{cores} processes, one batch domain each, "
+                                                                     f"{args.cpu_seconds / 2:.0f} s"}
     print(json.dumps(out), flush=True)
 
 

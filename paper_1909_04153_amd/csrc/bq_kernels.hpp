@@ -121,6 +121,12 @@ __device__ __forceinline__ P* uni(P* p) {
   return (P*)(((unsigned long long)hi << 32) | lo);
 }
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// materialise a value in a register at this point (the compiler may not sink
+// its computation to a later use)
+template <typename T>
+__device__ __forceinline__ void pin(T& v) {
+  __asm__ volatile("" : "+v"(v));
+}
 
 // Element `off` of a field whose base address is the same for the whole
 // block: a scalar base plus a 32-bit per-lane byte offset (the workspace
@@ -148,6 +154,9 @@ template <> __device__ __forceinline__ double frcp<double>(double x) { return 1.
 template <> __device__ __forceinline__ double frcbrt<double>(double x) { return 1.0 / cbrt(x); }
 template <> __device__ __forceinline__ float fsqrt<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+// a / b: correctly rounded in FP64, reciprocal-multiply in FP32
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 template <> __device__ __forceinline__ float frcbrt<float>(float x) {
   return __builtin_amdgcn_exp2f(-0.33333333f * __builtin_amdgcn_logf(x));
 }
@@ -240,17 +249,21 @@ __device__ __forceinline__ Side<T> make_side(T w, T qn, T qt, T Dface, T eps, T 
   s.h = fmax(w + Dface, T(0));
   const T h2 = s.h * s.h;
   const T h4 = h2 * h2;
-  if (h4 >= eps) {
-    // u = q / h, and the recomputed discharge h u is q itself
+  // FP32: for h^4 >= eps, u = q / h and the recomputed discharge h u is q
+  // itself (exact identities); FP64 evaluates the general expression, so
+  // that at wet/dry fronts it rounds like the FP64 reference
+  if (sizeof(T) == 4 && h4 >= eps) {
     const T vf = frcp(s.h);
     s.un = qn * vf;
     s.ut = qt * vf;
     s.qn = qn;
     s.qt = qt;
   } else {
-    const T vf = T(1.4142135623730951) * s.h * frcp(fsqrt(h4 + eps));
-    s.un = qn * vf;
-    s.ut = qt * vf;
+    // u = sqrt(2) h q / sqrt(h^4 + max(h^4, eps)), recomputed discharge h u
+    const T den = fsqrt(h4 + fmax(h4, eps));
+    const T sh = T(1.4142135623730951) * s.h;
+    s.un = fdiv(sh * qn, den);
+    s.ut = fdiv(sh * qt, den);
     s.qn = s.h * s.un;
     s.qt = s.h * s.ut;
   }
@@ -318,14 +331,14 @@ __device__ __forceinline__ void tri_coef(T dm, T d0, T dp, const T* tc, T& a, T&
 // cell-average still-water depths of the chunk's cells with one neighbour on
 // each side (d = max(D, 0)); tc are the Eq. (21) constants of the direction.
 // fold_lo / fold_hi fold the odd mirror of a wall into the first / last
-// diagonal.  rhs (stride rs) is overwritten with the solution; the reciprocal
-// pivots and the upper diagonal stay in registers (the loops are unrolled
-// over M).
+// diagonal.  rhs (stride rs) is overwritten with the solution; the forward
+// sweep leaves y_k / u_k in rhs and keeps c_k / u_k in registers, so the
+// backward sweep is one multiply-add per row (the loops are unrolled over M).
 template <typename T, int M, bool FULL>
 __device__ __forceinline__ void chunk_solve_db_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
                                                 T* rhs, int rs) {
   if (FULL) m = M;
-  T piv[M], up[M];
+  T cu[M];                                     // c_k / u_k; rhs holds y_k / u_k
   T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
 #pragma unroll
   for (int k = 0; k < M; ++k) {
@@ -345,9 +358,8 @@ __device__ __forceinline__ void chunk_solve_db_(const T* Dl, int ds, int m, cons
         y = r - l * y_prev;
       }
       const T iu = frcp(u);
-      piv[k] = iu;
-      up[k] = c;
-      rhs[k * rs] = y;
+      cu[k] = c * iu;
+      rhs[k * rs] = y * iu;
       y_prev = y;
       iu_prev = iu;
       c_prev = c;
@@ -358,7 +370,7 @@ __device__ __forceinline__ void chunk_solve_db_(const T* Dl, int ds, int m, cons
   for (int k = M - 1; k >= 0; --k) {
     if (FULL || k < m) {
       const T y = rhs[k * rs];
-      const T x = (k == m - 1) ? y * piv[k] : (y - up[k] * x_next) * piv[k];
+      const T x = (k == m - 1) ? y : y - cu[k] * x_next;
       rhs[k * rs] = x;
       x_next = x;
     }
@@ -605,9 +617,11 @@ struct alignas(16) RhsSmem {
   T p[WY * LW];
   T q[WY * LW];
   T db[WY * LW];                                      // cell still-water depth
-  T pt[BY * BX];                                      // sum_k beta_k P^{n-k}
-  T qt[BY * BX];
   union {
+    struct {
+      T pt[BY * BX];                                  // sum_k beta_k P^{n-k} (until the F* terms are formed)
+      T qt[BY * BX];
+    } h;
     T ax[3][TY * AXP];                                // x-direction parts of E, F, G per cell
     struct {
       T u[TY * TXP];
@@ -662,7 +676,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
   auto rowB = [&](int k) { return k < KB - 1 ? rB + RGB * k : min(rB + RGB * k, S::BY - 1); };
   // E, F, G history of this thread's cells (consumed in phase 2)
-  T he1[CPT], he2[CPT], hf1[CPT], hf2[CPT], hg1[CPT], hg2[CPT];
+  // combined as the AB3 history terms alpha_1 X^{n-1} + alpha_2 X^{n-2}
+  // (Eq. 42) right away, so three values per cell stay live, not six
+  const T a1 = (T)st->alpha[1], a2 = (T)st->alpha[2];
+  T hE[CPT], hF[CPT], hG[CPT];
   {
     const T* E1 = uni((const T*)D.E[s1]);
     const T* E2 = uni((const T*)D.E[s2]);
@@ -673,9 +690,9 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const unsigned o = oI + (unsigned)(q * ipitch);
-      he1[q] = ldu(E1, o); he2[q] = ldu(E2, o);
-      hf1[q] = ldu(F1, o); hf2[q] = ldu(F2, o);
-      hg1[q] = ldu(G1, o); hg2[q] = ldu(G2, o);
+      hE[q] = a1 * ldu(E1, o) + a2 * ldu(E2, o);
+      hF[q] = a1 * ldu(F1, o) + a2 * ldu(F2, o);
+      hG[q] = a1 * ldu(G1, o) + a2 * ldu(G2, o);
     }
   }
   T rw[KW], rp[KW], rq[KW], rc[KC], h1p[KB], h2p[KB], h1q[KB], h2q[KB];
@@ -729,8 +746,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   for (int k = 0; k < KB; ++k) {
     const int r = rowB(k);
     const int t2 = (r + 1) * LW + cB + 1;             // same cell in the radius-2 tile
-    sm.pt[r * BX + cB] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
-    sm.qt[r * BX + cB] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
+    sm.x.h.pt[r * BX + cB] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
+    sm.x.h.qt[r * BX + cB] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
   }
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
@@ -738,6 +755,37 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     sm.db[rowW(k) * LW + cW] = dbar4(sm.dc[c0], sm.dc[c0 + 1], sm.dc[c0 + CXN], sm.dc[c0 + CXN + 1]);
   }
 
+  __syncthreads();
+  // F*, G* terms of this thread's cells (Eq. 14-15 are linear, so
+  // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k})), folded into the AB3
+  // history terms of U*, V* (Eq. 43); after them the history tiles' LDS
+  // holds the x-parts of the face pass
+  {
+    const T i2dx = D.i2dx, i2dy = D.i2dy, i4dxdy = D.i4dxdy, Bc = D.Bc;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int r = rY0 + q, c = cY;
+      const int C0 = (r + 2) * LW + c + 2;
+      const T d0 = dpos(sm.db[C0]);
+      const T ddx = (dpos(sm.db[C0 + 1]) - dpos(sm.db[C0 - 1])) * i2dx;
+      const T ddy = (dpos(sm.db[C0 + LW]) - dpos(sm.db[C0 - LW])) * i2dy;
+      const int B0 = (r + 1) * BX + c + 1;
+      const T qy = (sm.x.h.qt[B0 + BX] - sm.x.h.qt[B0 - BX]) * i2dy;
+      const T qx = (sm.x.h.qt[B0 + 1] - sm.x.h.qt[B0 - 1]) * i2dx;
+      const T qxy = ((sm.x.h.qt[B0 + BX + 1] - sm.x.h.qt[B0 - BX + 1]) -
+                     (sm.x.h.qt[B0 + BX - 1] - sm.x.h.qt[B0 - BX - 1])) * i4dxdy;
+      const T py = (sm.x.h.pt[B0 + BX] - sm.x.h.pt[B0 - BX]) * i2dy;
+      const T px = (sm.x.h.pt[B0 + 1] - sm.x.h.pt[B0 - 1]) * i2dx;
+      const T pxy = ((sm.x.h.pt[B0 + BX + 1] - sm.x.h.pt[B0 - BX + 1]) -
+                     (sm.x.h.pt[B0 + BX - 1] - sm.x.h.pt[B0 - BX - 1])) * i4dxdy;
+      hF[q] += d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
+      hG[q] += d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
+      pin(hE[q]);
+      pin(hF[q]);
+      pin(hG[q]);
+    }
+  }
+  __syncthreads();
   const T g = D.g, eps = D.eps, ht = T(0.5) * D.theta;
   const T idx = D.idx, idy = D.idy;
   // ---- phase 1x: x-faces by row segments ----------------------------------
@@ -841,7 +889,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
   const T B = D.B, Bc = D.Bc, gn2 = D.gn2;
-  const T a0 = (T)st->alpha[0], a1 = (T)st->alpha[1], a2 = (T)st->alpha[2];
+  const T a0 = (T)st->alpha[0];
   T* const wn = uni(D.w[par ^ 1]);
   T* const E0 = uni(D.E[slot]);
   T* const F0 = uni(D.F[slot]);
@@ -898,29 +946,19 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       f_ -= k * u;
       g_ -= k * v;
     }
-    // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k}) (Eq. 14-15 are linear)
-    const int B0 = (r + 1) * BX + c + 1;
-    const T qy = (sm.qt[B0 + BX] - sm.qt[B0 - BX]) * i2dy;
-    const T qx = (sm.qt[B0 + 1] - sm.qt[B0 - 1]) * i2dx;
-    const T qxy = ((sm.qt[B0 + BX + 1] - sm.qt[B0 - BX + 1]) - (sm.qt[B0 + BX - 1] - sm.qt[B0 - BX - 1])) * i4dxdy;
-    const T py = (sm.pt[B0 + BX] - sm.pt[B0 - BX]) * i2dy;
-    const T px = (sm.pt[B0 + 1] - sm.pt[B0 - 1]) * i2dx;
-    const T pxy = ((sm.pt[B0 + BX + 1] - sm.pt[B0 - BX + 1]) - (sm.pt[B0 + BX - 1] - sm.pt[B0 - BX - 1])) * i4dxdy;
-    const T fs = d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
-    const T gs = d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
     // Eq. (42)-(43)
     if (in) {
       const unsigned ii = oI + (unsigned)(q * ipitch);
       stu(E0, ii, e_);
       stu(F0, ii, f_);
       stu(G0, ii, g_);
-      stu(wn, oG + (unsigned)(q * pitch), sm.w[C0] + (a0 * e_ + a1 * he1[q] + a2 * he2[q]));
+      stu(wn, oG + (unsigned)(q * pitch), sm.w[C0] + (a0 * e_ + hE[q]));
     }
     // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
     // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
     // U*^n = T P^n with the same matrix
-    ures[q] = in ? (a0 * f_ + a1 * hf1[q] + a2 * hf2[q]) + fs : T(0);
-    vres[q] = in ? (a0 * g_ + a1 * hg1[q] + a2 * hg2[q]) + gs : T(0);
+    ures[q] = in ? a0 * f_ + hF[q] : T(0);
+    vres[q] = in ? a0 * g_ + hG[q] : T(0);
   }
   __syncthreads();  // x-parts consumed; the union now holds U*, V*
 #pragma unroll

@@ -107,9 +107,19 @@ STEPS = {"beach_ragged": 700, "rip_2d": 150, "hump_2d": 300, "dam_break": 200, "
          "tiny_4x4": 100, "long_lines": 100}
 
 
+# The dry-bed dam break is the one case whose per-step bar is set by the
+# problem's conditioning rather than by rounding: at the dry front the KP07
+# scheme amplifies a rounding-level difference about a thousandfold within
+# ten steps (the oracle against itself, y-uniform 1e-15 relative noise on the
+# initial surface, reaches 2e-12 at step 171; pinned in
+# test_oracle_physics.py::test_dry_front_amplifies_rounding).  Its bar is
+# five times that response.
+TOL = {"dam_break": 1e-11}
+
+
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_fp64_parity_cases(bq, case):
-    worst, _, _ = run_compare(bq, CASES[case](), STEPS[case], 10, 1e-12)
+    worst, _, _ = run_compare(bq, CASES[case](), STEPS[case], 10, TOL.get(case, 1e-12))
     print(f"{case} FP64 worst rel L2 {worst:.2e}")
 
 

@@ -208,3 +208,32 @@ def test_quadratic_fstar_extrapolation_instability_reading():
     assert np.max(np.abs(lin.read("P"))) < 1e-12
     grown = quad.info().status != 0 or np.max(np.abs(quad.read("P"))) > 1e-6
     assert grown
+
+
+def test_dry_front_amplifies_rounding():
+    """The dry-bed dam break (Sec. 2 NLSW limit) is ill-conditioned at its
+    front: a y-uniform 1e-15 relative perturbation of the initial surface
+    makes the oracle's own P differ from the unperturbed run by more than
+    1e-12 (relative L2, natural-scale floor) within 200 steps, while a
+    smooth case stays at rounding level.  This is what bounds the FP64
+    GPU-vs-oracle comparison of that case."""
+    def self_divergence(spec, pert, steps):
+        amp = max(float(np.max(np.abs(spec["eta"]))), 1e-3)
+        c = math.sqrt(9.81 * max(float(np.max(spec["depth_c"])), 1e-3))
+        o1 = OracleDomain(spec["params"], spec["depth_c"])
+        o1.set_state(spec["eta"], spec["P"], spec["Q"])
+        noise = np.random.default_rng(3).standard_normal(spec["eta"].shape[1])[None, :]
+        o2 = OracleDomain(spec["params"], spec["depth_c"])
+        o2.set_state(spec["eta"] * (1.0 + pert * noise), spec["P"], spec["Q"])
+        worst = 0.0
+        for _ in range(steps):
+            assert o1.step(1) == 0 and o2.step(1) == 0
+            a, b = o2.read("P"), o1.read("P")
+            worst = max(worst, float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 0.1 * amp * c * math.sqrt(b.size))))
+        o1.close()
+        o2.close()
+        return worst
+    dam = self_divergence(S.dam_break_dry_bed(nx=150, ny=6, dx=0.1), 1e-15, 200)
+    smooth = self_divergence(S.solitary_flat(nx=200, ny=6, x0=3.0), 1e-15, 200)
+    assert dam > 1e-12
+    assert smooth < 1e-13
