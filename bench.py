@@ -99,11 +99,11 @@ def make_group(bq, specs, dtype, lanes=2):
 
 def timed(torch, group, steps, warmup):
     group.step(warmup)
-    group.sync()
+    group.wait()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     group.step(steps)
-    group.sync()
+    group.wait()
     torch.cuda.synchronize()
     return time.perf_counter() - t0
 

@@ -220,6 +220,10 @@ class Domain:
     def set_graph_steps(self, k: int):
         _check(load().bq_set_graph_steps(self._h, int(k)))
 
+    def wait(self):
+        """wait for the queued steps (no diagnostics)"""
+        self.stream.synchronize()
+
     def sync(self) -> StepInfo:
         i = Info()
         rc = load().bq_sync(self._h, ctypes.byref(i))
@@ -283,6 +287,9 @@ class Batch:
 
     def sync(self):
         _check(load().bq_batch_sync(self._h))
+
+    def wait(self):
+        self.sync()
 
     def profile(self, n: int) -> dict:
         out = np.zeros(4)

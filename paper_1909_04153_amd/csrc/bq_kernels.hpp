@@ -35,6 +35,7 @@ enum { ST_OK = 0, ST_ENONFINITE = -4, ST_EDTMIN = -5, ST_EDONE = -7 };
 
 constexpr int TX = 64;      // tile width (cells)
 constexpr int NT = 256;     // threads per tile block
+constexpr int NDIAG = 256;  // blocks of the diagnostic sums
 
 struct alignas(64) DevState {
   // committed state
@@ -92,6 +93,8 @@ struct DomDev {
   T* rsy;                   // [6][cy][nx]
   T* ifx;                   // [2][cx][ny]: neighbour values left / right of a chunk
   T* ify;                   // [2][cy][nx]
+  double* smax_tile;        // per tile: CFL maximum of the new state (written by the finalize kernel)
+  double* diag_part;        // [2][NDIAG]: per-block mass / energy partial sums
   double* wave;             // [4][n_waves]: amplitude, omega, phase, wave number
   double* io;               // nx * ny doubles of staging for host transfers
   DevState* st;
@@ -514,6 +517,15 @@ __global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, d
   DevState* st = D.st;
   __shared__ int go;
   __shared__ double tn;
+  // CFL maximum of the current state: the finalize kernel's per-tile maxima
+  // (a NaN there is already +inf) and the initial state's value
+  double tmax = 0.0;
+  {
+    const int ntiles = D.tiles_x * D.tiles_y;
+    const gp<const double> sp = gbl((const double*)D.smax_tile);
+    for (int k = threadIdx.x; k < ntiles; k += 64) tmax = fmax(tmax, sp[k]);
+    for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+  }
   if (threadIdx.x == 0) {
     commit(st);
     go = 0;
@@ -522,7 +534,7 @@ __global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, d
       if (D.t_end > 0.0 && st->t >= D.t_end) {
         st->status = ST_EDONE;
       } else {
-        const double s = __longlong_as_double((long long)st->smax_bits);
+        const double s = fmax(__longlong_as_double((long long)st->smax_bits), tmax);
         if (!(s <= 1.79e308)) {
           st->status = ST_ENONFINITE;
         } else {
@@ -1320,8 +1332,9 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     smax = fmax(smax, sd);
     if (i < 2 || i >= nx - 2 || j < 2 || j >= ny - 2) ghost_cell(D, w, P, Q, i, j, wv, p, qv, st->gw, st->gP);
   }
-  // block max -> one atomic per block (max commutes with the widening to
-  // FP64, so the FP32 maximum converts to the same value)
+  // block max -> one word per tile (max commutes with the widening to FP64,
+  // so the FP32 maximum converts to the same value); no atomics, so a large
+  // domain's blocks do not serialise on one address
   __shared__ T red[NT / 64];
   for (int o = 32; o > 0; o >>= 1) smax = fmax(smax, __shfl_xor(smax, o, 64));
   if ((tid & 63) == 0) red[tid >> 6] = smax;
@@ -1329,7 +1342,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   if (tid == 0) {
     T m = red[0];
     for (int k = 1; k < NT / 64; ++k) m = fmax(m, red[k]);
-    atomicMax(&st->smax_bits, (unsigned long long)__double_as_longlong((double)m));
+    gbl(D.smax_tile)[tile] = (double)m;               // reduced by the next step's k_dt
   }
 }
 

@@ -274,27 +274,30 @@ __global__ void k_gather(const DomDev<T>* Dp, int which, int wslot, int pslot) {
   D.io[e] = v;
 }
 
-// FP64 mass and energy: fixed partition and fixed-order tree (one block)
+__device__ __forceinline__ int cdiv_d(int a, int b) { return (a + b - 1) / b; }
+
+// FP64 mass and energy: fixed partition (block b takes a contiguous run of
+// rows) and fixed-order trees, so the sums are reproducible
 template <typename T>
-__global__ void __launch_bounds__(256) k_diag(const DomDev<T>* Dp, int wslot, int pslot) {
+__global__ void __launch_bounds__(256) k_diag_part(const DomDev<T>* Dp, int wslot, int pslot) {
   const DomDev<T>& D = *Dp;
-  const int n = D.nx * D.ny;
+  const int R = cdiv_d(D.ny, NDIAG), j0 = blockIdx.x * R, j1 = min(D.ny, j0 + R);
   double m = 0.0, en = 0.0;
-  for (int e = threadIdx.x; e < n; e += 256) {
-    const int i = e % D.nx, j = e / D.nx;
-    const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
-    const double Db = (double)D.Dbar[(size_t)j * D.ipitch + i];
-    const double h = (double)D.w[wslot][g] + Db;
-    const double d = Db > 0.0 ? Db : 0.0;
-    m += h;
-    double ec = 0.0;
-    if (d > 0.0) ec += 0.5 * D.g_d * (h - d) * (h - d);
-    if (h > 1e-6) {
-      const double p = (double)D.P[pslot][g], q = (double)D.Q[pslot][g];
-      ec += 0.5 * (p * p + q * q) / h;
+  for (int j = j0; j < j1; ++j)
+    for (int i = threadIdx.x; i < D.nx; i += 256) {
+      const size_t g = (size_t)(j + 2) * D.pitch + D.xoff + i;
+      const double Db = (double)D.Dbar[(size_t)j * D.ipitch + i];
+      const double h = (double)D.w[wslot][g] + Db;
+      const double d = Db > 0.0 ? Db : 0.0;
+      m += h;
+      double ec = 0.0;
+      if (d > 0.0) ec += 0.5 * D.g_d * (h - d) * (h - d);
+      if (h > 1e-6) {
+        const double p = (double)D.P[pslot][g], q = (double)D.Q[pslot][g];
+        ec += 0.5 * (p * p + q * q) / h;
+      }
+      en += ec;
     }
-    en += ec;
-  }
   __shared__ double sm[256], se[256];
   sm[threadIdx.x] = m;
   se[threadIdx.x] = en;
@@ -307,8 +310,37 @@ __global__ void __launch_bounds__(256) k_diag(const DomDev<T>* Dp, int wslot, in
     __syncthreads();
   }
   if (threadIdx.x == 0) {
+    D.diag_part[blockIdx.x] = sm[0];
+    D.diag_part[NDIAG + blockIdx.x] = se[0];
+  }
+}
+
+// sum of the partials (fixed tree); the per-tile CFL maxima are folded into
+// the state's maximum for reporting (idempotent for the next Delta t)
+template <typename T>
+__global__ void __launch_bounds__(NDIAG) k_diag_final(const DomDev<T>* Dp) {
+  const DomDev<T>& D = *Dp;
+  __shared__ double sm[NDIAG], se[NDIAG], sx[NDIAG];
+  sm[threadIdx.x] = D.diag_part[threadIdx.x];
+  se[threadIdx.x] = D.diag_part[NDIAG + threadIdx.x];
+  double mx = 0.0;
+  const int ntiles = D.tiles_x * D.tiles_y;
+  for (int k = threadIdx.x; k < ntiles; k += NDIAG) mx = fmax(mx, D.smax_tile[k]);
+  sx[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = NDIAG / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      sm[threadIdx.x] += sm[threadIdx.x + s];
+      se[threadIdx.x] += se[threadIdx.x + s];
+      sx[threadIdx.x] = fmax(sx[threadIdx.x], sx[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
     D.st->mass = sm[0] * D.dx_d * D.dy_d;
     D.st->energy = se[0] * D.dx_d * D.dy_d;
+    const double s0 = __longlong_as_double((long long)D.st->smax_bits);
+    D.st->smax_bits = (unsigned long long)__double_as_longlong(fmax(s0, sx[0]));
   }
 }
 
@@ -365,7 +397,7 @@ struct bq_batch {
 // layout of a domain in its workspace
 struct Layout {
   size_t off_state, off_desc;
-  size_t off_w, off_P, off_Q, off_E, off_F, off_G;
+  size_t off_w, off_P, off_Q, off_E, off_F, off_G, off_part;
   size_t off_Dc, off_Dbar, off_xhP, off_xhQ;
   size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
   size_t ghosted, interior, total;
@@ -406,6 +438,9 @@ static Layout layout_for(const bq_params* p) {
   L.off_E = take(3 * L.interior);
   L.off_F = take(3 * L.interior);
   L.off_G = take(3 * L.interior);
+  // per-tile CFL maxima and diagnostic partial sums (zeroed by set_state,
+  // part of the checkpoint)
+  L.off_part = take(sizeof(double) * ((size_t)L.tiles_x * L.tiles_y + 2 * NDIAG));
   L.off_Dc = take((size_t)(NY + 5) * L.cpitch * sizeof(T));
   L.off_Dbar = take(L.interior);
   L.off_xhP = take(L.interior);
@@ -540,6 +575,8 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.rsy = (T*)(b + Ly.off_rsy);
   D.ifx = (T*)(b + Ly.off_ifx);
   D.ify = (T*)(b + Ly.off_ify);
+  D.smax_tile = (double*)(b + Ly.off_part);
+  D.diag_part = D.smax_tile + (size_t)Ly.tiles_x * Ly.tiles_y;
   D.wave = (double*)(b + Ly.off_wave);
   D.io = (double*)(b + Ly.off_io);
   D.st = (DevState*)(b + Ly.off_state);
@@ -710,7 +747,8 @@ static int sync_t(bq_domain* d, bq_info* out) {
   HIPCHK(hipMemcpyAsync(&h, d->st, sizeof(h), hipMemcpyDeviceToHost, d->stream));
   HIPCHK(hipStreamSynchronize(d->stream));
   if (out) {
-    k_diag<T><<<1, 256, 0, d->stream>>>((const DomDev<T>*)d->ddev, (int)(h.n & 1), (int)(h.n % 3));
+    k_diag_part<T><<<NDIAG, 256, 0, d->stream>>>((const DomDev<T>*)d->ddev, (int)(h.n & 1), (int)(h.n % 3));
+    k_diag_final<T><<<1, NDIAG, 0, d->stream>>>((const DomDev<T>*)d->ddev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&h, d->st, sizeof(h), hipMemcpyDeviceToHost, d->stream));
     HIPCHK(hipStreamSynchronize(d->stream));
