@@ -6,10 +6,11 @@
  *
  * The step (all of it runs in HIP kernels, enqueued on the caller's stream):
  *   - ghost cells, two layers per side (Sec. 3.3): solid wall, sine
- *     wavemaker, sponge layer, irregular wavemaker;
+ *     wavemaker, sponge layer, irregular wavemaker, time series;
  *   - KP07 central-upwind finite volumes for the NLSW subset with a
  *     well-balanced bed source, central differences for the dispersive terms
- *     and Manning friction: E, F, G of Eq. (11)-(13) (Sec. 3.1);
+ *     and bottom friction (Manning, and the quadratic law of the paper's
+ *     experiments, Sec. 5.3-5.4): E, F, G of Eq. (11)-(13) (Sec. 3.1);
  *   - Delta t from the CFL number of Eq. (22) on the current state, passed
  *     through the lazy moving average of Eq. (47) (Sec. 3.2.2, 3.2.2.4);
  *   - the variable-step AB3 update of w, U*, V*: Eq. (42)-(43) with the
@@ -47,10 +48,13 @@
 extern "C" {
 #endif
 
-#define BQ_ABI_VERSION 1
+#define BQ_ABI_VERSION 2
 #define BQ_MAX_WAVES 256
 
-typedef enum { BQ_WALL = 0, BQ_SINE = 1, BQ_SPONGE = 2, BQ_IRREGULAR = 3 } bq_bc;
+/* BQ_TIMESERIES: both west ghost columns take eta and P interpolated
+ * linearly in time from the samples ts_eta, ts_P (held at the first / last
+ * sample outside their span), times the start-up ramp; Q = 0 there. */
+typedef enum { BQ_WALL = 0, BQ_SINE = 1, BQ_SPONGE = 2, BQ_IRREGULAR = 3, BQ_TIMESERIES = 4 } bq_bc;
 typedef enum { BQ_SIDE_W = 0, BQ_SIDE_E = 1, BQ_SIDE_S = 2, BQ_SIDE_N = 3 } bq_side;
 typedef enum { BQ_FP64 = 0, BQ_FP32 = 1 } bq_precision;
 typedef enum {
@@ -78,7 +82,8 @@ typedef struct bq_params {
   int32_t fixed_dt;        /* 1 = every step uses dt_init (uniform AB3, Eq. 16-18) */
   double theta;            /* generalised-minmod parameter in [1, 2]; 0 = central slopes */
   double eps_desing;       /* velocity desingularisation epsilon; 0 = max(dx^4, dy^4) */
-  int32_t bc[4];           /* bq_bc per side W, E, S, N; wavemakers on W only */
+  int32_t bc[4];           /* bq_bc per side W, E, S, N; wavemakers and time
+                              series on W only */
   double sponge_width[4];  /* sponge band width per side [m] (BQ_SPONGE sides) */
   double sponge_sigma;     /* peak damping rate of the sponge [1/s] */
   int32_t n_waves;         /* wavemaker components (<= BQ_MAX_WAVES) */
@@ -93,6 +98,18 @@ typedef struct bq_params {
   int32_t precision;       /* bq_precision of the field arithmetic; Delta t,
                               the AB3/FD weights, time and mass/energy sums are
                               FP64 in both */
+  /* fields added in ABI version 2 */
+  double friction_f;       /* quadratic friction factor: f1 = f u |U|,
+                              f2 = f v |U| (Sec. 5.3-5.4: 0.0025); added to
+                              the Manning term; 0 = none */
+  int32_t ts_n;            /* BQ_TIMESERIES: samples at t = k ts_dt, k < ts_n */
+  double ts_dt;            /*   sample spacing [s] */
+  const double* ts_eta;    /*   host arrays of ts_n: surface elevation [m] */
+  const double* ts_P;      /*   and x-flux [m^2/s] at the west boundary */
+  double runup_delta;      /* > 0: keep the run-up record (bq_read which 4):
+                              per cell the highest w over the states whose
+                              depth exceeded runup_delta (Sec. 5.1: s dx / 3);
+                              0 = not kept */
 } bq_params;
 
 typedef struct bq_info {
@@ -141,7 +158,11 @@ int bq_step_dt(bq_domain* d, double dt);
  * latched status. */
 int bq_sync(bq_domain* d, bq_info* out);
 
-/* Synchronous read of the interior: which = 0 eta, 1 P, 2 Q, 3 w; FP64. */
+/* Synchronous read of the interior, FP64: which = 0 eta, 1 P, 2 Q, 3 w,
+ * 4 the run-up record (NaN where the depth never exceeded runup_delta;
+ * BQ_EINVAL unless runup_delta > 0), 5 the local CFL number of Eq. (22) of
+ * the current state with the Delta t of the last step,
+ * dt_last * max((|u|+c)/dx, (|v|+c)/dy) (Sec. 5.2). */
 int bq_read(bq_domain* d, int32_t which, double* host_out);
 
 /* Checkpoint of the full state including the AB3 history, so a resumed run

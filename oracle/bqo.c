@@ -25,8 +25,17 @@
  *       uneven bed, closed-basin mass, Madsen-Sorensen linear dispersion,
  *       solitary-wave propagation, third-order temporal convergence on a
  *       y-uniform case, Ritter dam break in the NLSW limit (d = 0).
- *   wavemaker ghost values, sponge, Manning friction (Sec. 3.3, readings) ...
- *       parity unpinned beyond the MS wave number (bisection vs. relation).
+ *   friction, Manning and quadratic (Sec. 5.3-5.4 reading) ... pinned: decay
+ *       of a uniform current against the closed form P0 / (1 + k P0 t).
+ *   time-series boundary (Sec. 3.3 reading) ....... pinned: exact linear
+ *       interpolation, hold and ramp; zero record keeps the lake at rest;
+ *       a sine record drives the linear-theory incident wave.
+ *   run-up record (Sec. 5.1 reading) .............. pinned: lake at rest;
+ *       brute-force running maximum over every step's state.
+ *   local CFL map (Eq. 22) ......................... pinned: flat lake at rest
+ *       equals the CFL number.
+ *   wavemaker ghost values, sponge (Sec. 3.3, readings) ... parity unpinned
+ *       beyond the MS wave number (bisection vs. relation).
  */
 #include "bqo.h"
 
@@ -65,6 +74,9 @@ struct bqo_domain {
   double* Us;      /* U*^{n+1} */
   double* Vs;
   double* la; double* lb; double* lc; double* lr; double* lx; double* lres; double* ldx;
+  double* ts_eta;  /* time-series boundary samples (copies) */
+  double* ts_P;
+  double* wmax;    /* run-up record, interior (NULL unless runup_delta > 0) */
   double t;
   int64_t n;
   double dt_hist[3]; /* dt_hist[0] = dt of the last step, [1], [2] older */
@@ -316,11 +328,15 @@ double bqo_ms_wavenumber(double omega, double depth, double g, double B) {
 }
 
 static int is_wave(int bc) { return bc == BQO_SINE || bc == BQO_IRREGULAR; }
+/* west sides whose ghost cells are prescribed (wavemakers, time series) */
+static int is_driven(int bc) { return is_wave(bc) || bc == BQO_TIMESERIES; }
 
 bqo_domain* bqo_create(const bqo_params* pin, const double* depth_c) {
   if (!pin || !depth_c || pin->nx < 3 || pin->ny < 3 || !(pin->dx > 0) || !(pin->dy > 0)) return NULL;
   for (int s = 1; s < 4; ++s)
-    if (is_wave(pin->bc[s])) return NULL; /* wavemaker on the west side only */
+    if (is_driven(pin->bc[s])) return NULL; /* prescribed boundary on the west side only */
+  if (pin->bc[BQO_W] == BQO_TIMESERIES && (pin->ts_n < 1 || !(pin->ts_dt > 0.0) || !pin->ts_eta || !pin->ts_P))
+    return NULL;
   if (pin->fstar_order < 0 || pin->fstar_order > 2) return NULL;
   bqo_domain* d = (bqo_domain*)calloc(1, sizeof(bqo_domain));
   d->p = *pin;
@@ -342,6 +358,15 @@ bqo_domain* bqo_create(const bqo_params* pin, const double* depth_c) {
   d->p.wave_amp = d->wave_amp;
   d->p.wave_omega = d->wave_omega;
   d->p.wave_phase = d->wave_phase;
+  const int nts = pin->bc[BQO_W] == BQO_TIMESERIES ? pin->ts_n : 0;
+  d->ts_eta = zalloc(nts + 1);
+  d->ts_P = zalloc(nts + 1);
+  for (int k = 0; k < nts; ++k) {
+    d->ts_eta[k] = pin->ts_eta[k];
+    d->ts_P[k] = pin->ts_P[k];
+  }
+  d->p.ts_eta = d->ts_eta;
+  d->p.ts_P = d->ts_P;
 
   const size_t ncell = (size_t)(nx + 4) * (size_t)(ny + 4);
   const size_t nint = (size_t)nx * (size_t)ny;
@@ -359,6 +384,7 @@ bqo_domain* bqo_create(const bqo_params* pin, const double* depth_c) {
   const int nl = nx > ny ? nx : ny;
   d->la = zalloc(nl); d->lb = zalloc(nl); d->lc = zalloc(nl); d->lr = zalloc(nl); d->lx = zalloc(nl);
   d->lres = zalloc(nl); d->ldx = zalloc(nl);
+  d->wmax = pin->runup_delta > 0.0 ? zalloc(nint) : NULL;
 
   /* corner bed, then mirror across each side (x first, then y) */
   for (int j = 0; j <= ny; ++j)
@@ -413,7 +439,7 @@ void bqo_free(bqo_domain* d) {
                     d->dep, d->ddx, d->ddy, d->Ax, d->Bx, d->Cx, d->Ay, d->By, d->Cy, d->w,
                     d->P[0], d->P[1], d->P[2], d->Q[0], d->Q[1], d->Q[2], d->E[0], d->E[1], d->E[2],
                     d->F[0], d->F[1], d->F[2], d->G[0], d->G[1], d->G[2], d->Us, d->Vs,
-                    d->la, d->lb, d->lc, d->lr, d->lx, d->lres, d->ldx};
+                    d->la, d->lb, d->lc, d->lr, d->lx, d->lres, d->ldx, d->ts_eta, d->ts_P, d->wmax};
   for (size_t k = 0; k < sizeof(ptrs) / sizeof(ptrs[0]); ++k) free(ptrs[k]);
   free(d);
 }
@@ -440,15 +466,52 @@ static void wave_at(const bqo_domain* d, double x, double t, double* eta, double
   *P = q;
 }
 
+/* time-series boundary (reading): the samples are linearly interpolated in
+ * time, held at the first / last sample outside their span, multiplied by
+ * the start-up ramp, and used for both ghost columns (no spatial phase) */
+static void series_at(const bqo_domain* d, double t, double* eta, double* P) {
+  const int n = d->p.ts_n;
+  const double s = t / d->p.ts_dt;
+  double e, q;
+  if (!(s > 0.0)) {
+    e = d->ts_eta[0];
+    q = d->ts_P[0];
+  } else if (s >= n - 1) {
+    e = d->ts_eta[n - 1];
+    q = d->ts_P[n - 1];
+  } else {
+    const int k = (int)floor(s);
+    const double f = s - k;
+    e = (1.0 - f) * d->ts_eta[k] + f * d->ts_eta[k + 1];
+    q = (1.0 - f) * d->ts_P[k] + f * d->ts_P[k + 1];
+  }
+  const double r = ramp(d, t);
+  *eta = r * e;
+  *P = r * q;
+}
+
+/* surface and x-flux prescribed at the centre of west ghost cell -k */
+static void west_value(const bqo_domain* d, int k, double t, double* eta, double* P) {
+  if (d->p.bc[BQO_W] == BQO_TIMESERIES) series_at(d, t, eta, P);
+  else wave_at(d, (0.5 - k) * d->p.dx, t, eta, P);
+}
+
+int bqo_west_ghosts(bqo_domain* d, double t, double out[4]) {
+  if (!is_driven(d->p.bc[BQO_W])) return BQO_EINVAL;
+  west_value(d, 1, t, &out[0], &out[1]);
+  west_value(d, 2, t, &out[2], &out[3]);
+  return BQO_OK;
+}
+
 static void fill_ghosts(bqo_domain* d, double* P, double* Q, double t) {
   const int nx = d->nx, ny = d->ny;
   double* w = d->w;
   /* x sides for interior rows */
   for (int j = 0; j < ny; ++j) {
     for (int k = 1; k <= 2; ++k) {
-      if (is_wave(d->p.bc[BQO_W])) {
+      if (is_driven(d->p.bc[BQO_W])) {
         double e, q;
-        wave_at(d, (0.5 - k) * d->p.dx, t, &e, &q);
+        west_value(d, k, t, &e, &q);
         w[CI(d, -k, j)] = e;
         P[CI(d, -k, j)] = q;
         Q[CI(d, -k, j)] = 0.0;
@@ -479,6 +542,21 @@ static void fill_ghosts(bqo_domain* d, double* P, double* Q, double t) {
 /* State, CFL (Eq. 22) and diagnostics                                        */
 /* ------------------------------------------------------------------------ */
 
+/* run-up record (Sec. 5.1 reading): a cell counts as inundated in a state
+ * when its depth exceeds runup_delta; the record keeps the highest surface
+ * w among its inundated states and NaN while there is none */
+static void record_runup(bqo_domain* d, int reset) {
+  if (!d->wmax) return;
+  for (int j = 0; j < d->ny; ++j)
+    for (int i = 0; i < d->nx; ++i) {
+      const double w = d->w[CI(d, i, j)];
+      const double h = w - d->bbar[CI(d, i, j)];
+      double* r = &d->wmax[II(d, i, j)];
+      if (reset) *r = NAN;
+      if (h > d->p.runup_delta && (isnan(*r) || w > *r)) *r = w;
+    }
+}
+
 int bqo_set_state(bqo_domain* d, const double* eta, const double* P, const double* Q) {
   const int nx = d->nx, ny = d->ny;
   for (int j = 0; j < ny; ++j)
@@ -506,6 +584,7 @@ int bqo_set_state(bqo_domain* d, const double* eta, const double* P, const doubl
   d->dt_hist[0] = d->dt_hist[1] = d->dt_hist[2] = 0.0;
   d->status = BQO_OK;
   fill_ghosts(d, d->P[0], d->Q[0], 0.0);
+  record_runup(d, 1);
   return BQO_OK;
 }
 
@@ -578,6 +657,7 @@ static void compute_rhs(const bqo_domain* d, const double* P, const double* Q, d
     }
   const double Bd = d->p.B;
   const double gn2 = g * d->p.manning_n * d->p.manning_n;
+  const double cf = d->p.friction_f;
   const double* w = d->w;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
@@ -614,14 +694,21 @@ static void compute_rhs(const bqo_domain* d, const double* P, const double* Q, d
         f += Bd * g * dd * dd * dd * (exxx + exyy) + Bd * g * dd * dd * (dX * (2.0 * exx + eyy) + dY * exy);
         gg += Bd * g * dd * dd * dd * (eyyy + exxy) + Bd * g * dd * dd * (dY * (2.0 * eyy + exx) + dX * exy);
       }
-      /* Manning friction f1, f2 at the cell centre */
+      /* bottom friction f1, f2 at the cell centre: Manning, g n^2 u |U| / h^(1/3),
+       * and the quadratic law f u |U| of the paper's experiments (Sec. 5.3-5.4) */
       const double h = fmax(w[CI(d, i, j)] - d->bbar[CI(d, i, j)], 0.0);
-      if (h > 0.0 && gn2 > 0.0) {
+      if (h > 0.0 && (gn2 > 0.0 || cf > 0.0)) {
         const double u = desing(P[CI(d, i, j)], h, eps);
         const double v = desing(Q[CI(d, i, j)], h, eps);
         const double sp = sqrt(u * u + v * v);
-        f -= gn2 * u * sp / cbrt(h);
-        gg -= gn2 * v * sp / cbrt(h);
+        if (gn2 > 0.0) {
+          f -= gn2 * u * sp / cbrt(h);
+          gg -= gn2 * v * sp / cbrt(h);
+        }
+        if (cf > 0.0) {
+          f -= cf * u * sp;
+          gg -= cf * v * sp;
+        }
       }
       E[II(d, i, j)] = e;
       F[II(d, i, j)] = f;
@@ -747,16 +834,16 @@ static int step_one(bqo_domain* d, double dt_prescribed) {
   double* Pnew = d->P[s2];
   double* Qnew = d->Q[s2];
   double Pg = 0.0;
-  if (is_wave(d->p.bc[BQO_W])) {
+  if (is_driven(d->p.bc[BQO_W])) {
     double e;
-    wave_at(d, -0.5 * d->p.dx, t1, &e, &Pg);
+    west_value(d, 1, t1, &e, &Pg);
   }
   for (int j = 0; j < ny; ++j) {
     for (int i = 0; i < nx; ++i) {
       const size_t q = II(d, i, j);
       d->la[i] = d->Ax[q]; d->lb[i] = d->Bx[q]; d->lc[i] = d->Cx[q]; d->lr[i] = d->Us[q];
     }
-    if (is_wave(d->p.bc[BQO_W])) d->lr[0] -= d->la[0] * Pg;  /* Dirichlet ghost */
+    if (is_driven(d->p.bc[BQO_W])) d->lr[0] -= d->la[0] * Pg;  /* Dirichlet ghost */
     else d->lb[0] -= d->la[0];                                 /* P_{-1} = -P_0 */
     d->lb[nx - 1] -= d->lc[nx - 1];                            /* P_{nx} = -P_{nx-1} */
     d->la[0] = 0.0;
@@ -806,6 +893,7 @@ static int step_one(bqo_domain* d, double dt_prescribed) {
   d->t = t1;
   d->n = n + 1;
   fill_ghosts(d, Pnew, Qnew, t1);
+  record_runup(d, 0);
   return BQO_OK;
 }
 
@@ -837,6 +925,7 @@ int bqo_info_get(bqo_domain* d, bqo_info* out) {
 int bqo_read(bqo_domain* d, int32_t which, double* out) {
   const double* P = d->P[d->n % 3];
   const double* Q = d->Q[d->n % 3];
+  if (which < 0 || which > 5 || (which == 4 && !d->wmax)) return BQO_EINVAL;
   for (int j = 0; j < d->ny; ++j)
     for (int i = 0; i < d->nx; ++i) {
       double v;
@@ -845,7 +934,15 @@ int bqo_read(bqo_domain* d, int32_t which, double* out) {
         case 1: v = P[CI(d, i, j)]; break;
         case 2: v = Q[CI(d, i, j)]; break;
         case 3: v = d->w[CI(d, i, j)]; break;
-        default: return BQO_EINVAL;
+        case 4: v = d->wmax[II(d, i, j)]; break;
+        default: {
+          /* Eq. (22) with the step that produced the state */
+          const double h = fmax(d->w[CI(d, i, j)] - d->bbar[CI(d, i, j)], 0.0);
+          const double u = desing(P[CI(d, i, j)], h, d->eps);
+          const double vv = desing(Q[CI(d, i, j)], h, d->eps);
+          const double c = sqrt(d->p.g * h);
+          v = d->dt_hist[0] * fmax((fabs(u) + c) / d->p.dx, (fabs(vv) + c) / d->p.dy);
+        }
       }
       out[II(d, i, j)] = v;
     }

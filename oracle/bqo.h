@@ -26,7 +26,7 @@
 extern "C" {
 #endif
 
-enum { BQO_WALL = 0, BQO_SINE = 1, BQO_SPONGE = 2, BQO_IRREGULAR = 3 };
+enum { BQO_WALL = 0, BQO_SINE = 1, BQO_SPONGE = 2, BQO_IRREGULAR = 3, BQO_TIMESERIES = 4 };
 enum { BQO_W = 0, BQO_E = 1, BQO_S = 2, BQO_N = 3 };
 enum {
   BQO_OK = 0,
@@ -62,6 +62,16 @@ typedef struct {
   int32_t fstar_order; /* time extrapolation of F*, G*: 2 = quadratic (Eq. 43-46),
                           1 = linear (two-point backward difference for every
                           derivative estimate); 0 selects 2 */
+  double friction_f; /* quadratic friction factor: f1 = f u |U|, f2 = f v |U|
+                        (Sec. 5.3-5.4 use 0.0025); adds to the Manning term */
+  int32_t ts_n;      /* time-series boundary (BQO_TIMESERIES, west side):
+                        samples of eta and P at t = k ts_dt, k = 0 .. ts_n-1 */
+  double ts_dt;
+  const double* ts_eta;
+  const double* ts_P;
+  double runup_delta; /* > 0: keep the run-up record, the highest w of every
+                         cell over the states whose depth exceeded it (Sec. 5.1
+                         uses s dx / 3) */
 } bqo_params;
 
 typedef struct bqo_domain bqo_domain;
@@ -84,10 +94,15 @@ int bqo_set_state(bqo_domain* d, const double* eta, const double* P, const doubl
 int bqo_step(bqo_domain* d, int32_t n_steps);
 int bqo_step_dt(bqo_domain* d, double dt);
 int bqo_info_get(bqo_domain* d, bqo_info* out);
-/* which: 0 eta, 1 P, 2 Q, 3 w; interior nx*ny, row-major */
+/* which: 0 eta, 1 P, 2 Q, 3 w, 4 run-up record (NaN where the depth never
+ * exceeded runup_delta; EINVAL unless it is kept), 5 local CFL number of
+ * Eq. (22), dt_last * max((|u|+c)/dx, (|v|+c)/dy); interior nx*ny, row-major */
 int bqo_read(bqo_domain* d, int32_t which, double* out);
 /* spatial operator at the current state: E, F, G (Eq. 11-13), interior */
 int bqo_rhs(bqo_domain* d, double* E, double* F, double* G);
+/* west ghost values at time t (wavemaker or time series): out = eta and P
+ * of ghost cell -1, then of ghost cell -2 */
+int bqo_west_ghosts(bqo_domain* d, double t, double out[4]);
 /* wave-number of the wavemaker components (Madsen-Sorensen relation) */
 int bqo_wave_numbers(bqo_domain* d, double* k_out);
 

@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bqo.c")
 _LIB = os.path.join(_HERE, "libbqo.so")
 
-WALL, SINE, SPONGE, IRREGULAR = 0, 1, 2, 3
+WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
 OK, EINVAL, ENONFINITE, EDTMIN, EDONE = 0, -1, -4, -5, -7
 
 
@@ -47,6 +47,9 @@ class _Params(ctypes.Structure):
         ("wave_amp", ctypes.POINTER(ctypes.c_double)), ("wave_omega", ctypes.POINTER(ctypes.c_double)),
         ("wave_phase", ctypes.POINTER(ctypes.c_double)), ("wave_ramp", ctypes.c_double),
         ("t_end", ctypes.c_double), ("fstar_order", ctypes.c_int32),
+        ("friction_f", ctypes.c_double), ("ts_n", ctypes.c_int32), ("ts_dt", ctypes.c_double),
+        ("ts_eta", ctypes.POINTER(ctypes.c_double)), ("ts_P", ctypes.POINTER(ctypes.c_double)),
+        ("runup_delta", ctypes.c_double),
     ]
 
 
@@ -76,6 +79,7 @@ def lib():
         L.bqo_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
         L.bqo_rhs.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.bqo_wave_numbers.argtypes = [ctypes.c_void_p, dp]
+        L.bqo_west_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
         L.bqo_ab3_alpha.argtypes = [ctypes.c_double] * 3 + [dp]
         L.bqo_fd_weights.argtypes = [ctypes.c_double] * 2 + [dp]
         L.bqo_step_weights.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_double] * 3 + [dp, dp]
@@ -179,7 +183,8 @@ class OracleDomain:
     ``params`` is a plain dict with the keys of paper_1909_04153_amd's scenario
     specs (nx, ny, dx, dy, g, B, manning_n, cfl, ema_alpha, dt_init, dt_max,
     dt_min, fixed_dt, theta, eps_desing, bc, sponge_width, sponge_sigma,
-    wave_amp, wave_omega, wave_phase, wave_ramp, t_end); ``depth_c`` is the
+    wave_amp, wave_omega, wave_phase, wave_ramp, t_end, fstar_order,
+    friction_f, ts_dt, ts_eta, ts_P, runup_delta); ``depth_c`` is the
     (ny+1, nx+1) still-water depth at cell corners.
     """
 
@@ -213,6 +218,14 @@ class OracleDomain:
         p.wave_ramp = float(params.get("wave_ramp", 0.0))
         p.t_end = float(params.get("t_end", 0.0))
         p.fstar_order = int(params.get("fstar_order", 2))
+        p.friction_f = float(params.get("friction_f", 0.0))
+        self._ts_eta = _f64(params.get("ts_eta", []))
+        self._ts_P = _f64(params.get("ts_P", np.zeros(len(self._ts_eta))))
+        p.ts_n = len(self._ts_eta)
+        p.ts_dt = float(params.get("ts_dt", 0.0))
+        p.ts_eta = _ptr(self._ts_eta) if len(self._ts_eta) else None
+        p.ts_P = _ptr(self._ts_P) if len(self._ts_P) else None
+        p.runup_delta = float(params.get("runup_delta", 0.0))
         dc = _f64(depth_c)
         assert dc.shape == (p.ny + 1, p.nx + 1), dc.shape
         self._p = p
@@ -248,9 +261,19 @@ class OracleDomain:
         return OracleInfo(i.t, i.n, i.dt_last, i.dt_prev1, i.dt_prev2, i.smax, i.mass, i.energy, i.status)
 
     def read(self, which: str) -> np.ndarray:
-        idx = {"eta": 0, "P": 1, "Q": 2, "w": 3}[which]
+        """eta, P, Q, w; runup (the run-up record, NaN where never
+        inundated); cfl (local CFL number of Eq. 22 with the last step)"""
+        idx = {"eta": 0, "P": 1, "Q": 2, "w": 3, "runup": 4, "cfl": 5}[which]
         out = np.zeros((self.ny, self.nx))
-        lib().bqo_read(self._h, idx, _ptr(out))
+        if lib().bqo_read(self._h, idx, _ptr(out)) != OK:
+            raise ValueError(f"bqo_read({which}) rejected")
+        return out
+
+    def west_ghosts(self, t: float) -> np.ndarray:
+        """(eta, P) of west ghost cell -1, then of ghost cell -2, at time t"""
+        out = np.zeros(4)
+        if lib().bqo_west_ghosts(self._h, float(t), _ptr(out)) != OK:
+            raise ValueError("the west side is not a prescribed boundary")
         return out
 
     def rhs(self):

@@ -16,7 +16,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbq.so")
 
-WALL, SINE, SPONGE, IRREGULAR = 0, 1, 2, 3
+WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
+ABI_VERSION = 2
 FP64, FP32 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDTMIN, ESTATE, EDONE = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENONFINITE: "ENONFINITE",
@@ -42,6 +43,9 @@ class Params(ctypes.Structure):
         ("wave_amp", ctypes.POINTER(ctypes.c_double)), ("wave_omega", ctypes.POINTER(ctypes.c_double)),
         ("wave_phase", ctypes.POINTER(ctypes.c_double)), ("wave_ramp", ctypes.c_double),
         ("t_end", ctypes.c_double), ("fstar_order", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("friction_f", ctypes.c_double), ("ts_n", ctypes.c_int32), ("ts_dt", ctypes.c_double),
+        ("ts_eta", ctypes.POINTER(ctypes.c_double)), ("ts_P", ctypes.POINTER(ctypes.c_double)),
+        ("runup_delta", ctypes.c_double),
     ]
 
 
@@ -96,7 +100,7 @@ def load(path: str | None = None):
     L.bq_batch_profile_steps.argtypes = [vp, ip, dp]
     L.bq_batch_set_lanes.argtypes = [vp, ip]
     L.bq_batch_lanes.argtypes = [vp]
-    if L.bq_abi_version() != 1:
+    if L.bq_abi_version() != ABI_VERSION:
         raise RuntimeError("libbq ABI version mismatch")
     if path is None:
         _lib = L
@@ -122,7 +126,7 @@ def make_params(params: dict, precision: int = FP64) -> tuple[Params, list]:
         if k in params:
             setattr(p, k, int(params[k]))
     for k in ("dx", "dy", "g", "B", "manning_n", "cfl", "ema_alpha", "dt_init", "dt_max", "dt_min", "theta",
-              "eps_desing", "sponge_sigma", "wave_ramp", "t_end"):
+              "eps_desing", "sponge_sigma", "wave_ramp", "t_end", "friction_f", "ts_dt", "runup_delta"):
         if k in params:
             setattr(p, k, float(params[k]))
     for s, v in enumerate(params.get("bc", (WALL,) * 4)):
@@ -137,6 +141,14 @@ def make_params(params: dict, precision: int = FP64) -> tuple[Params, list]:
         keep += [amp, om, ph]
         p.n_waves = len(amp)
         p.wave_amp, p.wave_omega, p.wave_phase = _dptr(amp), _dptr(om), _dptr(ph)
+    ts_eta = np.ascontiguousarray(params.get("ts_eta", []), dtype=np.float64)
+    if len(ts_eta):
+        ts_P = np.ascontiguousarray(params.get("ts_P", np.zeros(len(ts_eta))), dtype=np.float64)
+        if ts_P.shape != ts_eta.shape:
+            raise ValueError("ts_eta and ts_P must have the same length")
+        keep += [ts_eta, ts_P]
+        p.ts_n = len(ts_eta)
+        p.ts_eta, p.ts_P = _dptr(ts_eta), _dptr(ts_P)
     p.precision = int(precision)
     return p, keep
 
@@ -238,7 +250,9 @@ class Domain:
         return dict(zip(KERNELS, out.tolist()))
 
     def read(self, which: str) -> np.ndarray:
-        idx = {"eta": 0, "P": 1, "Q": 2, "w": 3}[which]
+        """eta, P, Q, w; runup (the run-up record, NaN where never
+        inundated); cfl (local CFL number of Eq. 22 with the last step)"""
+        idx = {"eta": 0, "P": 1, "Q": 2, "w": 3, "runup": 4, "cfl": 5}[which]
         out = np.zeros((self.ny, self.nx))
         _check(load().bq_read(self._h, idx, _dptr(out)))
         return out

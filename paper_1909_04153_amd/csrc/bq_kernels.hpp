@@ -30,7 +30,9 @@
 
 namespace bqk {
 
-enum { WALL = 0, SINE = 1, SPONGE = 2, IRREGULAR = 3 };
+enum { WALL = 0, SINE = 1, SPONGE = 2, IRREGULAR = 3, TIMESERIES = 4 };
+// west sides whose ghost cells are prescribed (wavemakers, time series)
+__host__ __device__ inline bool west_driven(int bc) { return bc == SINE || bc == IRREGULAR || bc == TIMESERIES; }
 enum { ST_OK = 0, ST_ENONFINITE = -4, ST_EDTMIN = -5, ST_EDONE = -7 };
 
 constexpr int TX = 64;      // tile width (cells)
@@ -69,14 +71,17 @@ struct DomDev {
   int tiles_x, tiles_y;
   int bc[4];
   int fstar_order, fixed_dt, n_waves, any_sponge;
-  T dx, dy, g, B, Bc, gn2, theta, eps;
+  int ts_n;                 // time-series samples (BC TIMESERIES on the west side)
+  int runup;                // 1 = keep the run-up record wmax
+  T dx, dy, g, B, Bc, gn2, cf, theta, eps;
+  T runup_delta;
   // reciprocals of the grid spacing combinations used by the stencils
   T idx, idy, i2dx, i2dy, idx2, idy2, i4dxdy, i2dx3, i2dy3, i2dxdy2, i2dx2dy;
   // constants of the Eq. (21) coefficients per direction: 1/(2h), (B+1/3)/h^2, 1/(6h)
   T tcx[3], tcy[3];
   T sponge_w[4];
   T sponge_sigma;
-  double dx_d, dy_d, g_d, cfl, ema_alpha, dt_init, dt_max, dt_min, wave_ramp, t_end;
+  double dx_d, dy_d, g_d, cfl, ema_alpha, dt_init, dt_max, dt_min, wave_ramp, t_end, ts_dt;
   T* w[2];
   T* P[3];
   T* Q[3];
@@ -95,7 +100,9 @@ struct DomDev {
   T* ify;                   // [2][cy][nx]
   double* smax_tile;        // per tile: CFL maximum of the new state (written by the finalize kernel)
   double* diag_part;        // [2][NDIAG]: per-block mass / energy partial sums
-  double* wave;             // [4][n_waves]: amplitude, omega, phase, wave number
+  double* wave;             // [4][n_waves]: amplitude, omega, phase, wave number;
+                            // time series: [2][ts_n]: eta, P samples
+  T* wmax;                  // run-up record (interior layout), if kept
   double* io;               // nx * ny doubles of staging for host transfers
   DevState* st;
 };
@@ -483,13 +490,40 @@ __device__ __forceinline__ void commit(DevState* st) {
 }
 
 template <typename T>
-__device__ void wave_ghosts(const DomDev<T>& D, double t, double* gw, double* gP) {
-  // surface and flux of the incident wave train at the centres of ghost
-  // cells -1 and -2 (x = -dx/2, -3dx/2); only thread 0's result is used
-  __shared__ double red[4][64];
+__device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP) {
+  // surface and flux prescribed at the centres of west ghost cells -1 and -2
+  // (x = -dx/2, -3dx/2) at time t; only thread 0's result is used
   const int tid = threadIdx.x;
-  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   const double r = D.wave_ramp > 0.0 ? 1.0 - exp(-(t / D.wave_ramp) * (t / D.wave_ramp)) : 1.0;
+  if (D.bc[0] == TIMESERIES) {
+    // samples interpolated linearly in time, held outside their span; the
+    // same values in both ghost columns
+    if (tid == 0) {
+      const int n = D.ts_n;
+      const double* se = D.wave;
+      const double* sp = D.wave + n;
+      const double s = t / D.ts_dt;
+      double e, p;
+      if (!(s > 0.0)) {
+        e = se[0];
+        p = sp[0];
+      } else if (s >= (double)(n - 1)) {
+        e = se[n - 1];
+        p = sp[n - 1];
+      } else {
+        const int k = (int)s;
+        const double f = s - (double)k;
+        e = se[k] + f * (se[k + 1] - se[k]);
+        p = sp[k] + f * (sp[k + 1] - sp[k]);
+      }
+      gw[0] = gw[1] = r * e;
+      gP[0] = gP[1] = r * p;
+    }
+    return;
+  }
+  // incident wave train: sum of the components
+  __shared__ double red[4][64];
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   const int nw = D.n_waves;
   for (int m = tid; m < nw; m += 64) {
     const double amp = D.wave[m], om = D.wave[nw + m], ph = D.wave[2 * nw + m], k = D.wave[3 * nw + m];
@@ -596,9 +630,9 @@ __global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, d
     }
   }
   __syncthreads();
-  if (go && D.n_waves > 0 && (D.bc[0] == SINE || D.bc[0] == IRREGULAR)) {
+  if (go && west_driven(D.bc[0])) {
     double gw[2], gP[2];
-    wave_ghosts(D, tn, gw, gP);
+    west_ghosts(D, tn, gw, gP);
     if (threadIdx.x == 0) {
       st->gw[0] = gw[0]; st->gw[1] = gw[1]; st->gP[0] = gP[0]; st->gP[1] = gP[1];
     }
@@ -900,7 +934,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   __syncthreads();
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
-  const T B = D.B, Bc = D.Bc, gn2 = D.gn2;
+  const T B = D.B, Bc = D.Bc, gn2 = D.gn2, cf = D.cf;
   const T a0 = (T)st->alpha[0];
   T* const wn = uni(D.w[par ^ 1]);
   T* const E0 = uni(D.E[slot]);
@@ -948,13 +982,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       f_ += bg * d0 * (exxx + exyy) + bg * (ddx * (T(2) * exx + eyy) + ddy * exy);
       g_ += bg * d0 * (eyyy + exxy) + bg * (ddy * (T(2) * eyy + exx) + ddx * exy);
     }
-    // Manning friction f1, f2 at the cell centre
+    // bottom friction f1, f2 at the cell centre: Manning g n^2 u |U| / h^(1/3)
+    // plus the quadratic law f u |U|
     const T Pc = sm.p[C0], Qc = sm.q[C0];
-    if (gn2 > T(0)) {
+    if (gn2 > T(0) || cf > T(0)) {
       const T h = fmax(sm.w[C0] + Db, T(0));
       const T vf = vfac(h, eps);
       const T u = Pc * vf, v = Qc * vf;
-      const T k = h > T(0) ? gn2 * fsqrt(u * u + v * v) * frcbrt(h) : T(0);
+      const T k = h > T(0) ? (gn2 * frcbrt(h) + cf) * fsqrt(u * u + v * v) : T(0);
       f_ -= k * u;
       g_ -= k * v;
     }
@@ -984,7 +1019,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   constexpr int NCX = TX / MX;                  // x-chunks per tile row
   static_assert(TX % MX == 0, "chunks must tile the tile width");
   static_assert(TY * NCX <= 64, "x-chunk solvers must fit one wave");
-  const bool wave_w = (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
+  const bool wave_w = west_driven(D.bc[0]);
   if (tid < TY * NCX) {
     const int r = tid / NCX, qc = tid - r * NCX;
     const int j = j0 + r, is = i0 + qc * MX;
@@ -1143,7 +1178,7 @@ __device__ void ghost_cell(const DomDev<T>& D, T* w, T* P, T* Q, int i, int j, T
   if (i < 2) {
     gi = -1 - i;
     have_x = true;
-    if (D.bc[0] == SINE || D.bc[0] == IRREGULAR) {
+    if (west_driven(D.bc[0])) {
       gwv = (T)gw[i];
       gpv = (T)gP[i];
       gqv = T(0);
@@ -1259,7 +1294,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   // line-coupling kernel): a right-hand side that is zero except -a x_left
   // in the first row and -c x_right in the last.  The response is solved
   // here from the static matrix instead of read as stored spikes.
-  const bool wave_w = (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
+  const bool wave_w = west_driven(D.bc[0]);
   if (tid < TY * NCX) {
     const int r = tid / NCX, qc = tid - r * NCX;
     const int j = j0 + r, is = i0 + qc * MX;
@@ -1323,6 +1358,13 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     stu(P, og, p);
     stu(Q, og, qv);
     const T h = fmax(wv + Db, T(0));
+    if (D.runup && h > D.runup_delta) {
+      // run-up record: highest surface over the inundated states (NaN until
+      // the first one)
+      const gp<T> wm = gbl(D.wmax);
+      const unsigned oi = oI + (unsigned)(q * ipitch);
+      if (!(wm[oi] >= wv)) wm[oi] = wv;
+    }
     const T vf = vfac(h, eps);
     const T u = p * vf, v = qv * vf;
     const T cel = fsqrt(g * h);

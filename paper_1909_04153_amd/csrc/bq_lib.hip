@@ -113,7 +113,7 @@ __global__ void k_setup_spikes(const DomDev<T>* Dp, int dir) {
     const int q = s - 1 + k;
     Dl[k] = dir == 0 ? cellD(D, q, line) : cellD(D, line, q);
   }
-  const bool wave_w = dir == 0 && (D.bc[0] == SINE || D.bc[0] == IRREGULAR);
+  const bool wave_w = dir == 0 && west_driven(D.bc[0]);
   const bool fold_lo = s == 0 && !wave_w, fold_hi = s + m == n;
   T a0, b0, c0, am, bm, cm;
   tri_coef(dpos(Dl[0]), dpos(Dl[1]), dpos(Dl[2]), tc, a0, b0, c0);
@@ -229,6 +229,7 @@ __global__ void __launch_bounds__(256) k_init_ghosts(const DomDev<T>* Dp) {
     const T wv = D.w[0][g], p = D.P[0][g], qv = D.Q[0][g];
     ghost_cell(D, D.w[0], D.P[0], D.Q[0], i, j, wv, p, qv, D.st->gw, D.st->gP);
     const T h = fmax(wv + D.Dbar[(size_t)j * D.ipitch + i], T(0));
+    if (D.runup) D.wmax[(size_t)j * D.ipitch + i] = h > D.runup_delta ? wv : (T)__builtin_nan("");
     const T u = desing(p, h, D.eps), v = desing(qv, h, D.eps);
     const T c = sqrt(D.g * h);
     const T sx = (fabs(u) + c) / D.dx, sy = (fabs(v) + c) / D.dy;
@@ -249,13 +250,14 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_init_waves(const DomDev<T>* Dp) {
   const DomDev<T>& D = *Dp;
   double gw[2], gP[2];
-  wave_ghosts(D, D.st->t, gw, gP);
+  west_ghosts(D, D.st->t, gw, gP);
   if (threadIdx.x == 0) {
     D.st->gw[0] = gw[0]; D.st->gw[1] = gw[1]; D.st->gP[0] = gP[0]; D.st->gP[1] = gP[1];
   }
 }
 
-// gather the current level into io: which 0 eta, 1 P, 2 Q, 3 w
+// gather the current level into io: which 0 eta, 1 P, 2 Q, 3 w, 4 run-up
+// record, 5 local CFL number with the last step's Delta t
 template <typename T>
 __global__ void k_gather(const DomDev<T>* Dp, int which, int wslot, int pslot) {
   const DomDev<T>& D = *Dp;
@@ -268,6 +270,15 @@ __global__ void k_gather(const DomDev<T>* Dp, int which, int wslot, int pslot) {
     const double wv = (double)D.w[wslot][g];
     const double Db = (double)D.Dbar[(size_t)j * D.ipitch + i];
     v = which == 3 ? wv : (wv + Db) - (Db > 0.0 ? Db : 0.0);
+  } else if (which == 4) {
+    v = (double)D.wmax[(size_t)j * D.ipitch + i];
+  } else if (which == 5) {
+    // Eq. (22) in the field precision, as the step's CFL maximum
+    const T wv = D.w[wslot][g], p = D.P[pslot][g], qv = D.Q[pslot][g];
+    const T h = fmax(wv + D.Dbar[(size_t)j * D.ipitch + i], T(0));
+    const T u = desing(p, h, D.eps), vv = desing(qv, h, D.eps);
+    const T c = sqrt(D.g * h);
+    v = D.st->dt1 * (double)fmax((fabs(u) + c) / D.dx, (fabs(vv) + c) / D.dy);
   } else {
     v = (double)(which == 1 ? D.P[pslot][g] : D.Q[pslot][g]);
   }
@@ -362,6 +373,7 @@ struct Launch {
 struct bq_domain {
   bq_params p;
   std::vector<double> wamp, womg, wph;
+  std::vector<double> ts;       // time-series samples: eta then P
   int precision = BQ_FP64;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
@@ -397,7 +409,7 @@ struct bq_batch {
 // layout of a domain in its workspace
 struct Layout {
   size_t off_state, off_desc;
-  size_t off_w, off_P, off_Q, off_E, off_F, off_G, off_part;
+  size_t off_w, off_P, off_Q, off_E, off_F, off_G, off_part, off_wmax;
   size_t off_Dc, off_Dbar, off_xhP, off_xhQ;
   size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
   size_t ghosted, interior, total;
@@ -441,6 +453,7 @@ static Layout layout_for(const bq_params* p) {
   // per-tile CFL maxima and diagnostic partial sums (zeroed by set_state,
   // part of the checkpoint)
   L.off_part = take(sizeof(double) * ((size_t)L.tiles_x * L.tiles_y + 2 * NDIAG));
+  L.off_wmax = take(p->runup_delta > 0.0 ? L.interior : 0);   // run-up record (checkpointed)
   L.off_Dc = take((size_t)(NY + 5) * L.cpitch * sizeof(T));
   L.off_Dbar = take(L.interior);
   L.off_xhP = take(L.interior);
@@ -451,7 +464,9 @@ static Layout layout_for(const bq_params* p) {
   L.off_rsy = take(6 * (size_t)L.cy * nx * sizeof(T));
   L.off_ifx = take(2 * (size_t)L.cx * ny * sizeof(T));
   L.off_ify = take(2 * (size_t)L.cy * nx * sizeof(T));
-  L.off_wave = take(4 * (size_t)(p->n_waves > 0 ? p->n_waves : 1) * sizeof(double));
+  const size_t nwave = 4 * (size_t)(p->n_waves > 0 ? p->n_waves : 1);
+  const size_t nser = p->bc[0] == BQ_TIMESERIES ? 2 * (size_t)p->ts_n : 0;
+  L.off_wave = take((nwave > nser ? nwave : nser) * sizeof(double));
   L.off_io = take((size_t)(nx + 1) * (ny + 1) * sizeof(double));
   L.total = o;
   return L;
@@ -468,10 +483,15 @@ static int check_params(const bq_params* p) {
   if (p->fixed_dt && !(p->dt_init > 0)) return fail(BQ_EINVAL, "fixed_dt needs dt_init > 0");
   if (!(p->theta == 0.0 || (p->theta >= 1.0 && p->theta <= 2.0))) return fail(BQ_EINVAL, "theta must be 0 or in [1, 2]");
   for (int s = 0; s < 4; ++s) {
-    if (p->bc[s] < 0 || p->bc[s] > 3) return fail(BQ_EINVAL, "bad boundary type on side %d", s);
-    if (s > 0 && (p->bc[s] == BQ_SINE || p->bc[s] == BQ_IRREGULAR))
-      return fail(BQ_EINVAL, "wavemakers are supported on the west side only");
+    if (p->bc[s] < 0 || p->bc[s] > 4) return fail(BQ_EINVAL, "bad boundary type on side %d", s);
+    if (s > 0 && west_driven(p->bc[s]))
+      return fail(BQ_EINVAL, "wavemakers and time series are supported on the west side only");
   }
+  if (p->bc[0] == BQ_TIMESERIES &&
+      (p->ts_n < 1 || p->ts_n > (1 << 26) || !(p->ts_dt > 0) || !p->ts_eta || !p->ts_P))
+    return fail(BQ_EINVAL, "a time-series boundary needs 1 <= ts_n <= 2^26 samples, ts_dt > 0 and both arrays");
+  if (!(p->friction_f >= 0) || !(p->manning_n >= 0)) return fail(BQ_EINVAL, "friction coefficients must be >= 0");
+  if (!(p->runup_delta >= 0)) return fail(BQ_EINVAL, "runup_delta must be >= 0");
   const bool wave = p->bc[0] == BQ_SINE || p->bc[0] == BQ_IRREGULAR;
   if (p->n_waves < 0 || p->n_waves > BQ_MAX_WAVES) return fail(BQ_EINVAL, "n_waves out of range");
   if (wave && (p->n_waves < 1 || !p->wave_amp || !p->wave_omega))
@@ -523,6 +543,11 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.B = (T)p->B;
   D.Bc = (T)(p->B + 1.0 / 3.0);
   D.gn2 = (T)(p->g * p->manning_n * p->manning_n);
+  D.cf = (T)p->friction_f;
+  D.ts_n = p->bc[0] == BQ_TIMESERIES ? p->ts_n : 0;
+  D.ts_dt = p->ts_dt;
+  D.runup = p->runup_delta > 0.0 ? 1 : 0;
+  D.runup_delta = (T)p->runup_delta;
   {
     const double dx = p->dx, dy = p->dy, bc = p->B + 1.0 / 3.0;
     D.idx = (T)(1.0 / dx);
@@ -578,6 +603,7 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.smax_tile = (double*)(b + Ly.off_part);
   D.diag_part = D.smax_tile + (size_t)Ly.tiles_x * Ly.tiles_y;
   D.wave = (double*)(b + Ly.off_wave);
+  D.wmax = D.runup ? (T*)(b + Ly.off_wmax) : nullptr;
   D.io = (double*)(b + Ly.off_io);
   D.st = (DevState*)(b + Ly.off_state);
   d->st = D.st;
@@ -600,6 +626,8 @@ static int create_t(bq_domain* d, const double* depth_c) {
     }
     HIPCHK(hipMemcpyAsync(D.wave, wv.data(), wv.size() * sizeof(double), hipMemcpyHostToDevice, s));
   }
+  if (D.ts_n > 0)
+    HIPCHK(hipMemcpyAsync(D.wave, d->ts.data(), d->ts.size() * sizeof(double), hipMemcpyHostToDevice, s));
   const size_t nc = (size_t)(p->nx + 1) * (p->ny + 1);
   HIPCHK(hipMemcpyAsync(D.io, depth_c, nc * sizeof(double), hipMemcpyHostToDevice, s));
   const DomDev<T>* Dd = (const DomDev<T>*)d->ddev;
@@ -635,7 +663,7 @@ static int set_state_t(bq_domain* d, const double* eta, const double* P, const d
   DevState h;
   memset(&h, 0, sizeof(h));
   HIPCHK(hipMemcpyAsync(d->st, &h, sizeof(h), hipMemcpyHostToDevice, s));
-  if (D.n_waves > 0) k_init_waves<T><<<1, 64, 0, s>>>(Dd);
+  if (west_driven(D.bc[0])) k_init_waves<T><<<1, 64, 0, s>>>(Dd);
   k_init_ghosts<T><<<cdiv((int)n, 256), 256, 0, s>>>(Dd);
   HIPCHK(hipGetLastError());
   int hflag = 0;
@@ -1070,7 +1098,12 @@ int bq_domain_create(const bq_params* p, const double* depth_c, void* dev_worksp
     d->wph.assign(p->n_waves, 0.0);
     if (p->wave_phase) d->wph.assign(p->wave_phase, p->wave_phase + p->n_waves);
   }
+  if (p->bc[0] == BQ_TIMESERIES) {
+    d->ts.assign(p->ts_eta, p->ts_eta + p->ts_n);
+    d->ts.insert(d->ts.end(), p->ts_P, p->ts_P + p->ts_n);
+  }
   d->p.wave_amp = d->p.wave_omega = d->p.wave_phase = nullptr;
+  d->p.ts_eta = d->p.ts_P = nullptr;
   d->precision = p->precision;
   d->stream = (hipStream_t)hip_stream;
   d->ws = (char*)dev_workspace;
@@ -1124,7 +1157,8 @@ int bq_sync(bq_domain* d, bq_info* out) {
 
 int bq_read(bq_domain* d, int32_t which, double* host_out) {
   if (!d || !host_out) return fail(BQ_EINVAL, "NULL argument");
-  if (which < 0 || which > 3) return fail(BQ_EINVAL, "which must be 0..3");
+  if (which < 0 || which > 5) return fail(BQ_EINVAL, "which must be 0..5");
+  if (which == 4 && !(d->p.runup_delta > 0.0)) return fail(BQ_EINVAL, "the run-up record is not kept (runup_delta = 0)");
   return DISPATCH(d->precision, read_t, d, which, host_out);
 }
 

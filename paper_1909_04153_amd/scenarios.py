@@ -26,7 +26,7 @@ import numpy as np
 
 G = 9.81
 B_MS = 1.0 / 15.0
-WALL, SINE, SPONGE, IRREGULAR = 0, 1, 2, 3
+WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
 
 
 def base_params(nx, ny, dx, dy=None, **kw):
@@ -34,7 +34,7 @@ def base_params(nx, ny, dx, dy=None, **kw):
              manning_n=0.0, cfl=0.2, ema_alpha=0.1, dt_init=0.0, dt_max=1.0, dt_min=1e-9, fixed_dt=0,
              theta=1.3, eps_desing=0.0, bc=(WALL, WALL, WALL, WALL), sponge_width=(0.0, 0.0, 0.0, 0.0),
              sponge_sigma=0.0, wave_amp=[], wave_omega=[], wave_phase=[], wave_ramp=0.0, t_end=0.0,
-             fstar_order=2)
+             fstar_order=2, friction_f=0.0, runup_delta=0.0)
     p.update(kw)
     return p
 
@@ -140,6 +140,51 @@ def rip_beach(nx=2048, ny=2048, dx=0.5, seed=190904153, hs=1.0, tp=8.0, gamma=3.
     eta, P, Q = rest_state(nx, ny)
     return dict(name=f"rip_beach_{nx}x{ny}", params=p, depth_c=-b, eta=eta, P=P, Q=Q, t_end=t_end,
                 rip_y=ys)
+
+
+def series_beach(nx=256, ny=32, dx=0.05, h_off=0.4, x_toe=2.0, slope=0.1, hs=0.04, tp=1.2, n_waves=16,
+                 ts_dt=0.02, duration=120.0, friction_f=0.0025, seed=190904156, ramp=2.0, **kw):
+    """Plane beach driven by a time-series boundary with the knobs of the
+    paper's experiments (Sec. 3.3, 5.1, 5.3-5.4): the west boundary follows a
+    seeded JONSWAP surface record eta(t) = sum a_m sin(w_m t + p_m) sampled
+    every ts_dt, with the long-wave flux P = sqrt(g h_off) eta; quadratic
+    friction factor f; run-up record with threshold s dx / 3."""
+    rng = np.random.default_rng(seed)
+    a, om, ph = jonswap_components(hs, tp, 3.3, n_waves, rng=rng)
+    t = np.arange(int(round(duration / ts_dt)) + 1) * ts_dt
+    eta_t = np.sum(a[:, None] * np.sin(om[:, None] * t[None, :] + ph[:, None]), axis=0)
+    p = base_params(nx, ny, dx, bc=(TIMESERIES, WALL, WALL, WALL), ts_dt=ts_dt, ts_eta=list(eta_t),
+                    ts_P=list(math.sqrt(G * h_off) * eta_t), wave_ramp=ramp, friction_f=friction_f,
+                    runup_delta=slope * dx / 3.0, **kw)
+    Xc, _ = corner_coords(nx, ny, dx, p["dy"])
+    b = np.where(Xc < x_toe, -h_off, -h_off + (Xc - x_toe) * slope)
+    eta, P, Q = rest_state(nx, ny)
+    return dict(name=f"series_beach_{nx}x{ny}", params=p, depth_c=-b, eta=eta, P=P, Q=Q)
+
+
+def conical_island(nx=601, ny=601, dx=0.05, depth=0.32, rel_height=0.18, r_top=1.1, island_h=0.625,
+                   island_slope=0.25, x0=5.0, sponge=2.0, sponge_sigma=5.0, **kw):
+    """Stand-in for the conical-island run-up test (Sec. 5.1): a square basin
+    of nx x ny cells of dx (30 m at the defaults) and depth 0.32 m with a
+    conical island at its centre (top diameter 2.2 m, side slope 1:4, 0.625 m
+    high, so 7.2 m across at the base and a still-water shoreline radius of
+    2.32 m); a solitary wave of height 0.18 d starts at x0 near the west
+    side; sponge layers west and east, walls north and south, no friction.
+    2D dispersive case: CFL 0.125 and linear F* extrapolation.  The run-up
+    record uses the paper's threshold s dx / 3."""
+    kw.setdefault("cfl", 0.125)
+    kw.setdefault("fstar_order", 1)
+    p = base_params(nx, ny, dx, bc=(SPONGE, SPONGE, WALL, WALL), sponge_width=(sponge, sponge, 0.0, 0.0),
+                    sponge_sigma=sponge_sigma, runup_delta=island_slope * dx / 3.0, **kw)
+    Xc, Yc = corner_coords(nx, ny, dx, p["dy"])
+    xc, yc = 0.5 * nx * dx, 0.5 * ny * p["dy"]
+    r = np.hypot(Xc - xc, Yc - yc)
+    top = -depth + island_h
+    b = np.minimum(top, -depth + np.maximum(island_h - (r - r_top) * island_slope, 0.0))
+    X, _ = cell_coords(nx, ny, dx, p["dy"])
+    eta, P = solitary_profile(X, x0, rel_height * depth, depth)
+    return dict(name=f"conical_island_{nx}x{ny}", params=p, depth_c=-b, eta=eta, P=P, Q=np.zeros_like(eta),
+                center=(xc, yc), shore_radius=r_top + (island_h - depth) / island_slope)
 
 
 def rip_beach_scaled(nx, ny, seed=190904153, **kw):

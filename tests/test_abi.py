@@ -3,6 +3,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 
@@ -27,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     lib = ctypes.CDLL(bq.LIB_PATH)
     missing = [s for s in declared_symbols() if not hasattr(lib, s)]
     assert not missing, missing
-    assert lib.bq_abi_version() == 1
+    assert lib.bq_abi_version() == bq.ABI_VERSION
 
 
 def test_workspace_size_and_parameter_checks_on_host():
@@ -43,3 +44,43 @@ def test_workspace_size_and_parameter_checks_on_host():
         bq.workspace_bytes(bad)
     with pytest.raises(bq.BqError):
         bq.workspace_bytes(dict(spec["params"], nx=3))
+
+
+def test_binding_struct_layout_matches_the_header(tmp_path):
+    """offsets and sizes of bq_params / bq_info as the C compiler lays them out"""
+    fields = [f for f, _ in bq.Params._fields_]
+    info = [f for f, _ in bq.Info._fields_]
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "bq.h"', "int main(void) {",
+           '  printf("%zu\\n", sizeof(bq_params));', '  printf("%zu\\n", sizeof(bq_info));']
+    src += [f'  printf("%zu\\n", offsetof(bq_params, {f}));' for f in fields]
+    src += [f'  printf("%zu\\n", offsetof(bq_info, {f}));' for f in info]
+    src += ["  return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(bq.Params), ctypes.sizeof(bq.Info)]
+    want += [getattr(bq.Params, f).offset for f in fields] + [getattr(bq.Info, f).offset for f in info]
+    assert got == want
+
+
+def test_parameter_checks_of_the_experiment_knobs():
+    from paper_1909_04153_amd import scenarios as S
+
+    base = S.solitary_flat(64, 8)["params"]
+    ts = dict(base, bc=(bq.TIMESERIES, 0, 0, 0), ts_dt=0.1, ts_eta=[0.0, 0.01], ts_P=[0.0, 0.03])
+    assert bq.workspace_bytes(ts) > 0
+    for bad in (dict(ts, bc=(0, bq.TIMESERIES, 0, 0)),          # east side
+                dict(ts, ts_dt=0.0),                            # no spacing
+                dict(base, bc=(bq.TIMESERIES, 0, 0, 0)),        # no samples
+                dict(base, friction_f=-1e-3),
+                dict(base, runup_delta=-0.1)):
+        with pytest.raises(bq.BqError):
+            bq.workspace_bytes(bad)
+    with pytest.raises(ValueError):
+        bq.make_params(dict(ts, ts_P=[0.0]))
+    # the run-up record adds one interior field
+    n0 = bq.workspace_bytes(base, bq.FP32)
+    n1 = bq.workspace_bytes(dict(base, runup_delta=0.01), bq.FP32)
+    assert n1 > n0

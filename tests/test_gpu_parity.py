@@ -298,3 +298,47 @@ def test_two_lane_batch_profile_and_graphs_match_one_lane(bq):
     for x, y in zip(out[1], out[2]):
         for a, c in zip(x, y):
             assert np.array_equal(a, c)
+
+
+def _compare_maps(o, g, spec, scale):
+    """run-up record (NaN pattern and values) and local CFL map.  The CFL
+    speed holds sqrt(g h): on cells with a film of rounding-level depth the
+    square root turns an absolute difference of 1e-17 m in h into ~1e-8 of
+    celerity, so those cells are held to an absolute bar and the wet cells
+    (h > 1e-8 m) to the relative one."""
+    ro, rg = o.read("runup"), g.read("runup")
+    assert np.array_equal(np.isnan(ro), np.isnan(rg))
+    inund = ~np.isnan(ro)
+    assert inund.any()
+    assert np.max(np.abs(rg[inund] - ro[inund])) <= 1e-12 * scale
+    dc = spec["depth_c"]
+    bbar = -0.25 * (dc[:-1, :-1] + dc[1:, :-1] + dc[:-1, 1:] + dc[1:, 1:])
+    wet = (o.read("w") - bbar) > 1e-8
+    co, cg = o.read("cfl"), g.read("cfl")
+    assert rel(cg[wet], co[wet]) <= 1e-12
+    assert np.max(np.abs(cg - co)) <= 1e-6
+    assert abs(cg.max() - co.max()) <= 1e-12 * co.max()
+
+
+def test_fp64_time_series_quadratic_friction_runup(bq):
+    # the experiment knobs: a seeded JONSWAP record drives the west boundary
+    # of a 1:10 beach (time-series boundary), quadratic friction 0.0025, and
+    # the run-up record with threshold s dx / 3; ragged 150 x 12 grid
+    spec = S.series_beach(nx=150, ny=12, dx=0.05, x_toe=1.0)
+    worst, o, g = run_compare(bq, spec, 1800, 30, 1e-12)
+    print(f"series beach FP64 worst rel L2 {worst:.2e}")
+    _compare_maps(o, g, spec, 0.1)
+    # the wave reached land: cells dry at rest were inundated
+    dc = spec["depth_c"]
+    dcell = 0.25 * (dc[:-1, :-1] + dc[1:, :-1] + dc[:-1, 1:] + dc[1:, 1:])
+    assert np.any(~np.isnan(g.read("runup"))[dcell < 0])
+
+
+def test_fp64_conical_island_runup(bq):
+    # the conical-island geometry (Sec. 5.1) at 121 x 121 cells of 0.25 m:
+    # solitary wave H/d = 0.18, sponges west and east, walls north and south,
+    # run-up on the island
+    spec = S.conical_island(nx=121, ny=121, dx=0.25)
+    worst, o, g = run_compare(bq, spec, 500, 25, 1e-12)
+    print(f"conical island 121^2 FP64 worst rel L2 {worst:.2e}")
+    _compare_maps(o, g, spec, 0.3)
