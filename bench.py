@@ -312,6 +312,19 @@ def main():
                                  "effective_hbm_frac": WORDS_STEP * 4 * c * n / e / 1e9 / HBM_PEAK_GBS}
         del g, ds
         torch.cuda.synchronize()
+        # the same 64-domain batch with the Adams-Moulton corrector (two
+        # passes of the stencil and the line solves per step)
+        sp, dt_ = workload("batch64")
+        for s_ in sp:
+            s_["params"] = dict(s_["params"], corrector=1)
+        ds, g = make_group(bq, sp, dt_, args.lanes)
+        c = sum(s_["params"]["nx"] * s_["params"]["ny"] for s_ in sp)
+        n = max(20, args.steps // 2)
+        e = timed(torch, g, n, args.warmup)
+        out["fp32_batch64_corrector"] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s",
+                                         "ms_per_step": e / n * 1e3, "cells": c, "steps": n}
+        del g, ds
+        torch.cuda.synchronize()
         fp64 = {}
         for wl in ("beach1024x256_fp64", "solitary200x20"):
             sp, dt_ = workload(wl)

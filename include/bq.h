@@ -17,7 +17,12 @@
  *     variable-step finite differences of Eq. (44)-(46) for the time
  *     derivatives of F*, G* (Eq. 14-15), forward Euler for the first two
  *     steps (Sec. 3.2.1);
- *   - the tridiagonal systems of Eq. (19)-(21) for P and Q.
+ *   - the tridiagonal systems of Eq. (19)-(21) for P and Q;
+ *   - optionally (bq_params.corrector) an Adams-Moulton corrector after each
+ *     AB3 step, the corrector Celeris offered (Sec. 1), in variable-step form:
+ *     E, F, G of the predicted level enter the integral over [t_n, t_{n+1}]
+ *     of the cubic through t_{n+1}, t_n, t_{n-1}, t_{n-2} (built like
+ *     Eq. 30), and F*, G* their change from level n to the predicted level.
  *
  * Conventions.  Grid nx x ny cells of dx x dy; cell (i, j) is centred at
  * ((i + 1/2) dx, (j + 1/2) dy); host arrays are row-major with index
@@ -48,7 +53,7 @@
 extern "C" {
 #endif
 
-#define BQ_ABI_VERSION 2
+#define BQ_ABI_VERSION 3
 #define BQ_MAX_WAVES 256
 
 /* BQ_TIMESERIES: both west ghost columns take eta and P interpolated
@@ -110,6 +115,11 @@ typedef struct bq_params {
                               per cell the highest w over the states whose
                               depth exceeded runup_delta (Sec. 5.1: s dx / 3);
                               0 = not kept */
+  /* field added in ABI version 3 */
+  int32_t corrector;       /* 1 = AB3 predictor + Adams-Moulton corrector
+                              (two passes of the spatial operator and the
+                              line solves per step; fourth order in time
+                              where F* = G* = 0); 0 = AB3 only */
 } bq_params;
 
 typedef struct bq_info {
@@ -198,8 +208,9 @@ int bq_batch_lanes(const bq_batch* b);
  * line coupling, finalize): runs n_steps plain launches with hipEvents around
  * every kernel on the launch stream and returns the mean duration of one
  * launch of each in ms_out[4].  A two-lane batch runs both lanes at once, as
- * bq_batch_step does, each launch covering one group.  The steps advance the
- * state like bq_step / bq_batch_step. */
+ * bq_batch_step does, each launch covering one group.  With the corrector
+ * each entry is the sum over the step's two passes of that kernel.  The
+ * steps advance the state like bq_step / bq_batch_step. */
 int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out);
 int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
 

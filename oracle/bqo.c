@@ -147,6 +147,28 @@ void bqo_step_weights(int64_t n, int32_t fstar_order, double h0, double h1, doub
   }
 }
 
+/* Adams-Moulton corrector weights (the optional corrector of Celeris that
+ * the paper's introduction mentions), built like Eq. (30): the integral over
+ * [t_n, t_n + h0] of each Lagrange basis polynomial through t_{n+1} = h0,
+ * t_n = 0, t_{n-1} = -h1, t_{n-2} = -(h1 + h2) (fourth order, n >= 2),
+ * through the first three nodes at n = 1 and the first two at n = 0.
+ * Three-point Gauss-Legendre quadrature integrates these cubics exactly. */
+void bqo_am_weights(int64_t n, double h0, double h1, double h2, double g[4]) {
+  const double x[4] = {h0, 0.0, -h1, -(h1 + h2)};
+  const int m = n >= 2 ? 4 : (n == 1 ? 3 : 2);
+  const double r = sqrt(0.6);
+  const double gx[3] = {-r, 0.0, r}, gw[3] = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  for (int j = 0; j < 4; ++j) g[j] = 0.0;
+  for (int j = 0; j < m; ++j)
+    for (int q = 0; q < 3; ++q) {
+      const double t = 0.5 * h0 * (1.0 + gx[q]);
+      double l = 1.0;
+      for (int k = 0; k < m; ++k)
+        if (k != j) l *= (t - x[k]) / (x[j] - x[k]);
+      g[j] += 0.5 * h0 * gw[q] * l;
+    }
+}
+
 /* Eq. (47): drop at once, rise gradually. */
 double bqo_lazy_ema(double cand, double prev, double a) {
   if (cand <= prev) return cand;
@@ -753,6 +775,9 @@ static double gstar(const bqo_domain* d, const double* P, int i, int j) {
 /* One time step                                                              */
 /* ------------------------------------------------------------------------ */
 
+static void solve_lines(bqo_domain* d, double t1, double* Pnew, double* Qnew);
+static void sponge(bqo_domain* d, double* Pnew, double* Qnew, double dt);
+
 static int step_one(bqo_domain* d, double dt_prescribed) {
   if (d->status != BQO_OK) return d->status;
   const int nx = d->nx, ny = d->ny;
@@ -800,7 +825,11 @@ static int step_one(bqo_domain* d, double dt_prescribed) {
   const double* Eh[3] = {d->E[s0], d->E[s1], d->E[s2]};
   const double* Fh[3] = {d->F[s0], d->F[s1], d->F[s2]};
   const double* Gh[3] = {d->G[s0], d->G[s1], d->G[s2]};
+  const int pc = d->p.corrector != 0;
   double* wnew = (double*)malloc(sizeof(double) * (size_t)nx * ny);
+  double* wold = pc ? (double*)malloc(sizeof(double) * (size_t)nx * ny) : NULL;
+  double* Uold = pc ? (double*)malloc(sizeof(double) * (size_t)nx * ny) : NULL;
+  double* Vold = pc ? (double*)malloc(sizeof(double) * (size_t)nx * ny) : NULL;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       const size_t q = II(d, i, j);
@@ -824,15 +853,78 @@ static int step_one(bqo_domain* d, double dt_prescribed) {
       wnew[q] = wn;
       d->Us[q] = Un1;
       d->Vs[q] = Vn1;
+      if (pc) {
+        wold[q] = d->w[CI(d, i, j)];
+        Uold[q] = Un;
+        Vold[q] = Vn;
+      }
     }
   const double t1 = d->t + dt;
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) d->w[CI(d, i, j)] = wnew[II(d, i, j)];
-  free(wnew);
 
   /* Eq. (19): x-lines for P^{n+1} (into the slot of level n-2) */
   double* Pnew = d->P[s2];
   double* Qnew = d->Q[s2];
+  solve_lines(d, t1, Pnew, Qnew);
+  if (pc) {
+    /* corrector: the spatial operator at the predicted state (its ghosts at
+     * t_{n+1}), the Adams-Moulton sum from the same base w^n, U*^n, V*^n, and
+     * the F*, G* terms as their exact change from level n to the predicted
+     * level (no extrapolation is needed once level n+1 is estimated) */
+    double gam[4];
+    bqo_am_weights(n, h0, h1, h2, gam);
+    fill_ghosts(d, Pnew, Qnew, t1);
+    const size_t nint = (size_t)nx * ny;
+    double* Ec = (double*)malloc(sizeof(double) * nint);
+    double* Fc = (double*)malloc(sizeof(double) * nint);
+    double* Gc = (double*)malloc(sizeof(double) * nint);
+    compute_rhs(d, Pnew, Qnew, Ec, Fc, Gc);
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const size_t q = II(d, i, j);
+        const double Xe[4] = {Ec[q], Eh[0][q], Eh[1][q], Eh[2][q]};
+        const double Xf[4] = {Fc[q], Fh[0][q], Fh[1][q], Fh[2][q]};
+        const double Xg[4] = {Gc[q], Gh[0][q], Gh[1][q], Gh[2][q]};
+        double wc = wold[q], Uc = Uold[q], Vc = Vold[q];
+        for (int k = 0; k < 4; ++k) {
+          wc += gam[k] * Xe[k];
+          Uc += gam[k] * Xf[k];
+          Vc += gam[k] * Xg[k];
+        }
+        Uc += fstar(d, Qnew, i, j) - fstar(d, Qn, i, j);
+        Vc += gstar(d, Pnew, i, j) - gstar(d, Pn, i, j);
+        wnew[q] = wc;
+        d->Us[q] = Uc;
+        d->Vs[q] = Vc;
+      }
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) d->w[CI(d, i, j)] = wnew[II(d, i, j)];
+    solve_lines(d, t1, Pnew, Qnew);
+    free(Ec);
+    free(Fc);
+    free(Gc);
+    free(wold);
+    free(Uold);
+    free(Vold);
+  }
+  free(wnew);
+  /* sponge layers (Sec. 3.3): relax eta, P, Q of wet cells towards rest */
+  sponge(d, Pnew, Qnew, dt);
+  d->dt_hist[2] = d->dt_hist[1];
+  d->dt_hist[1] = d->dt_hist[0];
+  d->dt_hist[0] = dt;
+  d->t = t1;
+  d->n = n + 1;
+  fill_ghosts(d, Pnew, Qnew, t1);
+  record_runup(d, 0);
+  return BQO_OK;
+}
+
+/* Eq. (19)-(20): the x-line systems for P and the y-line systems for Q of
+ * the U*, V* in d->Us, d->Vs; west Dirichlet value at t1 for driven sides */
+static void solve_lines(bqo_domain* d, double t1, double* Pnew, double* Qnew) {
+  const int nx = d->nx, ny = d->ny;
   double Pg = 0.0;
   if (is_driven(d->p.bc[BQO_W])) {
     double e;
@@ -864,37 +956,32 @@ static int step_one(bqo_domain* d, double dt_prescribed) {
     solve_line(ny, d->la, d->lb, d->lc, d->lr, d->lx, d->lres, d->ldx);
     for (int j = 0; j < ny; ++j) Qnew[CI(d, i, j)] = d->lx[j];
   }
-  /* sponge layers (Sec. 3.3): relax eta, P, Q of wet cells towards rest */
+}
+
+/* sponge layers (Sec. 3.3): relax eta, P, Q of wet cells towards rest */
+static void sponge(bqo_domain* d, double* Pnew, double* Qnew, double dt) {
+  const int nx = d->nx, ny = d->ny;
   int any_sponge = 0;
   for (int sd = 0; sd < 4; ++sd)
     if (d->p.bc[sd] == BQO_SPONGE && d->p.sponge_width[sd] > 0.0) any_sponge = 1;
-  if (any_sponge) {
-    for (int j = 0; j < ny; ++j)
-      for (int i = 0; i < nx; ++i) {
-        if (!(d->dep[CI(d, i, j)] > 0.0)) continue;
-        const double dist[4] = {(i + 0.5) * d->p.dx, (nx - i - 0.5) * d->p.dx, (j + 0.5) * d->p.dy,
-                                (ny - j - 0.5) * d->p.dy};
-        double sig = 0.0;
-        for (int sd = 0; sd < 4; ++sd) {
-          const double L = d->p.sponge_width[sd];
-          if (d->p.bc[sd] == BQO_SPONGE && L > 0.0 && dist[sd] < L) sig += d->p.sponge_sigma * sq((L - dist[sd]) / L);
-        }
-        if (sig > 0.0) {
-          const double fac = exp(-sig * dt);
-          d->w[CI(d, i, j)] = 0.0 + (d->w[CI(d, i, j)] - 0.0) * fac;
-          Pnew[CI(d, i, j)] *= fac;
-          Qnew[CI(d, i, j)] *= fac;
-        }
+  if (!any_sponge) return;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      if (!(d->dep[CI(d, i, j)] > 0.0)) continue;
+      const double dist[4] = {(i + 0.5) * d->p.dx, (nx - i - 0.5) * d->p.dx, (j + 0.5) * d->p.dy,
+                              (ny - j - 0.5) * d->p.dy};
+      double sig = 0.0;
+      for (int sd = 0; sd < 4; ++sd) {
+        const double L = d->p.sponge_width[sd];
+        if (d->p.bc[sd] == BQO_SPONGE && L > 0.0 && dist[sd] < L) sig += d->p.sponge_sigma * sq((L - dist[sd]) / L);
       }
-  }
-  d->dt_hist[2] = d->dt_hist[1];
-  d->dt_hist[1] = d->dt_hist[0];
-  d->dt_hist[0] = dt;
-  d->t = t1;
-  d->n = n + 1;
-  fill_ghosts(d, Pnew, Qnew, t1);
-  record_runup(d, 0);
-  return BQO_OK;
+      if (sig > 0.0) {
+        const double fac = exp(-sig * dt);
+        d->w[CI(d, i, j)] = 0.0 + (d->w[CI(d, i, j)] - 0.0) * fac;
+        Pnew[CI(d, i, j)] *= fac;
+        Qnew[CI(d, i, j)] *= fac;
+      }
+    }
 }
 
 int bqo_step(bqo_domain* d, int32_t n_steps) {

@@ -72,6 +72,9 @@ typedef struct {
   double runup_delta; /* > 0: keep the run-up record, the highest w of every
                          cell over the states whose depth exceeded it (Sec. 5.1
                          uses s dx / 3) */
+  int32_t corrector; /* 1 = each AB3 step (the predictor) is followed by an
+                        Adams-Moulton corrector (Celeris' optional corrector,
+                        Sec. 1), in variable-step form */
 } bqo_params;
 
 typedef struct bqo_domain bqo_domain;
@@ -108,6 +111,9 @@ int bqo_wave_numbers(bqo_domain* d, double* k_out);
 
 /* building blocks exposed for the pin tests */
 void bqo_ab3_alpha(double h0, double h1, double h2, double alpha[3]);
+/* corrector weights of (E, F, G) at t_{n+1}, t_n, t_{n-1}, t_{n-2}: fourth
+ * order for n >= 2, third at n = 1, trapezoidal at n = 0 (unused ones 0) */
+void bqo_am_weights(int64_t n, double h0, double h1, double h2, double gamma[4]);
 void bqo_fd_weights(double h1, double h2, double D[9]);
 void bqo_step_weights(int64_t n, int32_t fstar_order, double h0, double h1, double h2, double alpha[3], double D[9]);
 double bqo_lazy_ema(double cand, double prev, double a);

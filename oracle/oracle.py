@@ -49,7 +49,7 @@ class _Params(ctypes.Structure):
         ("t_end", ctypes.c_double), ("fstar_order", ctypes.c_int32),
         ("friction_f", ctypes.c_double), ("ts_n", ctypes.c_int32), ("ts_dt", ctypes.c_double),
         ("ts_eta", ctypes.POINTER(ctypes.c_double)), ("ts_P", ctypes.POINTER(ctypes.c_double)),
-        ("runup_delta", ctypes.c_double),
+        ("runup_delta", ctypes.c_double), ("corrector", ctypes.c_int32),
     ]
 
 
@@ -81,6 +81,7 @@ def lib():
         L.bqo_wave_numbers.argtypes = [ctypes.c_void_p, dp]
         L.bqo_west_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
         L.bqo_ab3_alpha.argtypes = [ctypes.c_double] * 3 + [dp]
+        L.bqo_am_weights.argtypes = [ctypes.c_int64] + [ctypes.c_double] * 3 + [dp]
         L.bqo_fd_weights.argtypes = [ctypes.c_double] * 2 + [dp]
         L.bqo_step_weights.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_double] * 3 + [dp, dp]
         L.bqo_lazy_ema.restype = ctypes.c_double
@@ -111,6 +112,13 @@ def _f64(a) -> np.ndarray:
 def ab3_alpha(h0, h1, h2):
     out = np.zeros(3)
     lib().bqo_ab3_alpha(h0, h1, h2, _ptr(out))
+    return out
+
+
+def am_weights(n, h0, h1, h2):
+    """Adams-Moulton corrector weights of X^{n+1}, X^n, X^{n-1}, X^{n-2}"""
+    out = np.zeros(4)
+    lib().bqo_am_weights(int(n), h0, h1, h2, _ptr(out))
     return out
 
 
@@ -184,7 +192,7 @@ class OracleDomain:
     specs (nx, ny, dx, dy, g, B, manning_n, cfl, ema_alpha, dt_init, dt_max,
     dt_min, fixed_dt, theta, eps_desing, bc, sponge_width, sponge_sigma,
     wave_amp, wave_omega, wave_phase, wave_ramp, t_end, fstar_order,
-    friction_f, ts_dt, ts_eta, ts_P, runup_delta); ``depth_c`` is the
+    friction_f, ts_dt, ts_eta, ts_P, runup_delta, corrector); ``depth_c`` is the
     (ny+1, nx+1) still-water depth at cell corners.
     """
 
@@ -226,6 +234,7 @@ class OracleDomain:
         p.ts_eta = _ptr(self._ts_eta) if len(self._ts_eta) else None
         p.ts_P = _ptr(self._ts_P) if len(self._ts_P) else None
         p.runup_delta = float(params.get("runup_delta", 0.0))
+        p.corrector = int(params.get("corrector", 0))
         dc = _f64(depth_c)
         assert dc.shape == (p.ny + 1, p.nx + 1), dc.shape
         self._p = p

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbq.so")
 
 WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
-ABI_VERSION = 2
+ABI_VERSION = 3
 FP64, FP32 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDTMIN, ESTATE, EDONE = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENONFINITE: "ENONFINITE",
@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("t_end", ctypes.c_double), ("fstar_order", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("friction_f", ctypes.c_double), ("ts_n", ctypes.c_int32), ("ts_dt", ctypes.c_double),
         ("ts_eta", ctypes.POINTER(ctypes.c_double)), ("ts_P", ctypes.POINTER(ctypes.c_double)),
-        ("runup_delta", ctypes.c_double),
+        ("runup_delta", ctypes.c_double), ("corrector", ctypes.c_int32),
     ]
 
 
@@ -122,7 +122,7 @@ def make_params(params: dict, precision: int = FP64) -> tuple[Params, list]:
     and the numpy arrays it points to (keep them alive while it is used)."""
     p = Params()
     load().bq_params_default(ctypes.byref(p))
-    for k in ("nx", "ny", "fixed_dt", "fstar_order"):
+    for k in ("nx", "ny", "fixed_dt", "fstar_order", "corrector"):
         if k in params:
             setattr(p, k, int(params[k]))
     for k in ("dx", "dy", "g", "B", "manning_n", "cfl", "ema_alpha", "dt_init", "dt_max", "dt_min", "theta",

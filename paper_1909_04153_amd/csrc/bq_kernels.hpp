@@ -50,6 +50,7 @@ struct alignas(64) DevState {
   double dt;
   double alpha[3];
   double beta[3];
+  double gamma[4];          // corrector weights of X^{n+1*}, X^n, X^{n-1}, X^{n-2}
   double t_next;
   double gw[2], gP[2];      // wavemaker ghost values (cells -1, -2) at t_next
   double smax_used;         // CFL maximum the step's Delta t was taken from
@@ -73,6 +74,7 @@ struct DomDev {
   int fstar_order, fixed_dt, n_waves, any_sponge;
   int ts_n;                 // time-series samples (BC TIMESERIES on the west side)
   int runup;                // 1 = keep the run-up record wmax
+  int corrector;            // 1 = AB3 predictor + Adams-Moulton corrector
   T dx, dy, g, B, Bc, gn2, cf, theta, eps;
   T runup_delta;
   // reciprocals of the grid spacing combinations used by the stencils
@@ -82,7 +84,8 @@ struct DomDev {
   T sponge_w[4];
   T sponge_sigma;
   double dx_d, dy_d, g_d, cfl, ema_alpha, dt_init, dt_max, dt_min, wave_ramp, t_end, ts_dt;
-  T* w[2];
+  T* w[3];                  // surface double buffer; w[2] holds the predicted surface
+                            // of a predictor-corrector step
   T* P[3];
   T* Q[3];
   T* E[3];
@@ -613,8 +616,26 @@ __global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, d
                 b2 = h0 * (h0 + h1) / (h2 * s12);
               }
             }
+            // Adams-Moulton corrector: integral over [t_n, t_n + h0] of the
+            // Lagrange basis through t_{n+1}, t_n, t_{n-1}, t_{n-2} (closed
+            // forms with a = h1, b = h1 + h2), the cubic from n = 2 on, the
+            // quadratic at n = 1, the trapezoidal rule at n = 0
+            double g0 = 0.5 * h0, g1 = 0.5 * h0, g2 = 0.0, g3 = 0.0;
+            if (n == 1) {
+              const double a = h1;
+              g0 = h0 * (2.0 * h0 + 3.0 * a) / (6.0 * (h0 + a));
+              g1 = h0 * (h0 + 3.0 * a) / (6.0 * a);
+              g2 = -h0 * h0 * h0 / (6.0 * a * (a + h0));
+            } else if (n >= 2) {
+              const double a = h1, b = h1 + h2, hh = h0 * h0 * h0;
+              g0 = h0 * (3.0 * h0 * h0 + 4.0 * (a + b) * h0 + 6.0 * a * b) / (12.0 * (h0 + a) * (h0 + b));
+              g1 = h0 * (h0 * h0 + 2.0 * (a + b) * h0 + 6.0 * a * b) / (12.0 * a * b);
+              g2 = -hh * (h0 + 2.0 * b) / (12.0 * a * (a + h0) * h2);
+              g3 = hh * (h0 + 2.0 * a) / (12.0 * b * (b + h0) * h2);
+            }
             st->dt = dt;
             st->alpha[0] = a0; st->alpha[1] = a1; st->alpha[2] = a2;
+            st->gamma[0] = g0; st->gamma[1] = g1; st->gamma[2] = g2; st->gamma[3] = g3;
             st->beta[0] = b0; st->beta[1] = b1; st->beta[2] = b2;
             st->t_next = st->t + dt;
             st->smax_used = s;
@@ -677,7 +698,13 @@ struct alignas(16) RhsSmem {
   T dc[CYN * CXN];
 };
 
-template <typename T, int TY, int MX>
+// CORR = false: the AB3 step of Eq. (42)-(43) from level n (the predictor
+// when the domain runs the corrector, which then writes the surface to w[2]).
+// CORR = true: the Adams-Moulton corrector from the same base w^n, U*^n, V*^n
+// with the spatial operator of the predicted level (slot of level n+1, w[2])
+// and the F*, G* terms as their change F*(P*) - F*(P^n); domains without the
+// corrector are skipped.
+template <typename T, int TY, int MX, bool CORR>
 __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                            int nd) {
   using S = RhsSmem<T, TY, MX>;
@@ -690,12 +717,15 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   const DomDev<T>& D = doms[dom];
   const DevState* st = D.st;
   if (st->halt) return;
+  if (CORR && !D.corrector) return;
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int slot = uni(st->slot), par = uni((int)(st->n & 1));
   const int s1 = slot == 0 ? 2 : slot - 1, s2 = slot == 2 ? 0 : slot + 1;
-  const T beta0 = (T)st->beta[0], beta1 = (T)st->beta[1], beta2 = (T)st->beta[2];
-  const bool hist = st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
+  const T beta0 = CORR ? T(1) : (T)st->beta[0];
+  const T beta1 = CORR ? T(-1) : (T)st->beta[1];
+  const T beta2 = CORR ? T(0) : (T)st->beta[2];
+  const bool hist = CORR || st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
   const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
   // Cells of a thread in the per-cell phases: column cY, rows rY0 .. rY0+CPT-1
   // (consecutive rows, so the vertical stencils of a thread's cells overlap).
@@ -723,16 +753,18 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   auto rowB = [&](int k) { return k < KB - 1 ? rB + RGB * k : min(rB + RGB * k, S::BY - 1); };
   // E, F, G history of this thread's cells (consumed in phase 2)
   // combined as the AB3 history terms alpha_1 X^{n-1} + alpha_2 X^{n-2}
-  // (Eq. 42) right away, so three values per cell stay live, not six
-  const T a1 = (T)st->alpha[1], a2 = (T)st->alpha[2];
+  // (Eq. 42) right away, so three values per cell stay live, not six; the
+  // corrector's terms are gamma_1 X^n + gamma_2 X^{n-1} + gamma_3 X^{n-2}
+  const T a1 = (T)(CORR ? st->gamma[1] : st->alpha[1]), a2 = (T)(CORR ? st->gamma[2] : st->alpha[2]);
   T hE[CPT], hF[CPT], hG[CPT];
   {
-    const T* E1 = uni((const T*)D.E[s1]);
-    const T* E2 = uni((const T*)D.E[s2]);
-    const T* F1 = uni((const T*)D.F[s1]);
-    const T* F2 = uni((const T*)D.F[s2]);
-    const T* G1 = uni((const T*)D.G[s1]);
-    const T* G2 = uni((const T*)D.G[s2]);
+    const int l1 = CORR ? slot : s1, l2 = CORR ? s1 : s2;
+    const T* E1 = uni((const T*)D.E[l1]);
+    const T* E2 = uni((const T*)D.E[l2]);
+    const T* F1 = uni((const T*)D.F[l1]);
+    const T* F2 = uni((const T*)D.F[l2]);
+    const T* G1 = uni((const T*)D.G[l1]);
+    const T* G2 = uni((const T*)D.G[l2]);
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const unsigned o = oI + (unsigned)(q * ipitch);
@@ -740,12 +772,26 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       hF[q] = a1 * ldu(F1, o) + a2 * ldu(F2, o);
       hG[q] = a1 * ldu(G1, o) + a2 * ldu(G2, o);
     }
+    if (CORR) {
+      const T a3 = (T)st->gamma[3];
+      const T* E3 = uni((const T*)D.E[s2]);
+      const T* F3 = uni((const T*)D.F[s2]);
+      const T* G3 = uni((const T*)D.G[s2]);
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const unsigned o = oI + (unsigned)(q * ipitch);
+        hE[q] += a3 * ldu(E3, o);
+        hF[q] += a3 * ldu(F3, o);
+        hG[q] += a3 * ldu(G3, o);
+      }
+    }
   }
   T rw[KW], rp[KW], rq[KW], rc[KC], h1p[KB], h2p[KB], h1q[KB], h2q[KB];
   {
-    const T* w = uni((const T*)D.w[par]);
-    const T* Pn = uni((const T*)D.P[slot]);
-    const T* Qn = uni((const T*)D.Q[slot]);
+    // the state the spatial operator is taken of: level n, or the predicted level
+    const T* w = uni((const T*)(CORR ? D.w[2] : D.w[par]));
+    const T* Pn = uni((const T*)D.P[CORR ? s2 : slot]);
+    const T* Qn = uni((const T*)D.Q[CORR ? s2 : slot]);
     const unsigned oW = (unsigned)(j0 * pitch + xoff + i0 - 2 + cW);       // radius-2 tile
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
@@ -759,7 +805,18 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
     for (int k = 0; k < KC; ++k) rc[k] = ldu(Dc, oC + (unsigned)(rowC(k) * cpitch));
     const unsigned oB = (unsigned)((j0 + 1) * pitch + xoff + i0 - 1 + cB);   // radius-1 tile
-    if (hist) {
+    if (CORR) {
+      // level n, for the change of the F*, G* terms
+      const T* P1 = uni((const T*)D.P[slot]);
+      const T* Q1 = uni((const T*)D.Q[slot]);
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const unsigned o = oB + (unsigned)(rowB(k) * pitch);
+        h1p[k] = ldu(P1, o);
+        h1q[k] = ldu(Q1, o);
+        h2p[k] = h2q[k] = T(0);
+      }
+    } else if (hist) {
       const T* P1 = uni((const T*)D.P[s1]);
       const T* P2 = uni((const T*)D.P[s2]);
       const T* Q1 = uni((const T*)D.Q[s1]);
@@ -935,8 +992,9 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
   const T B = D.B, Bc = D.Bc, gn2 = D.gn2, cf = D.cf;
-  const T a0 = (T)st->alpha[0];
-  T* const wn = uni(D.w[par ^ 1]);
+  const T a0 = (T)(CORR ? st->gamma[0] : st->alpha[0]);
+  T* const wn = uni(CORR ? D.w[par ^ 1] : (D.corrector ? D.w[2] : D.w[par ^ 1]));
+  const T* const wbase = uni((const T*)D.w[par]);   // w^n (the corrector's base)
   T* const E0 = uni(D.E[slot]);
   T* const F0 = uni(D.F[slot]);
   T* const G0 = uni(D.G[slot]);
@@ -996,10 +1054,13 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     // Eq. (42)-(43)
     if (in) {
       const unsigned ii = oI + (unsigned)(q * ipitch);
-      stu(E0, ii, e_);
-      stu(F0, ii, f_);
-      stu(G0, ii, g_);
-      stu(wn, oG + (unsigned)(q * pitch), sm.w[C0] + (a0 * e_ + hE[q]));
+      const unsigned og = oG + (unsigned)(q * pitch);
+      if (!CORR) {
+        stu(E0, ii, e_);
+        stu(F0, ii, f_);
+        stu(G0, ii, g_);
+      }
+      stu(wn, og, (CORR ? ldu(wbase, og) : sm.w[C0]) + (a0 * e_ + hE[q]));
     }
     // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
     // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
@@ -1032,7 +1093,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
         // Dirichlet ghost: the increment of P_{-1} from t_n to t_{n+1}
         T a, b, c;
         tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c);
-        rhs[0] -= a * ((T)st->gP[0] - sm.p[(r + 2) * LW + 1]);
+        const T pg = CORR ? D.P[slot][(size_t)(j + 2) * pitch + xoff - 1] : sm.p[(r + 2) * LW + 1];
+        rhs[0] -= a * ((T)st->gP[0] - pg);
       }
       chunk_solve_db<T, MX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs, 1);
       const int cgl = is / MX;
@@ -1055,16 +1117,20 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     }
   }
   __syncthreads();
-  // local solutions (cells outside the domain land in the fields' padding)
+  // local solutions (cells outside the domain land in the fields' padding),
+  // on the base P^n, Q^n
   T* const xhP = uni(D.xhP);
   T* const xhQ = uni(D.xhQ);
+  const T* const Pb = uni((const T*)D.P[slot]);
+  const T* const Qb = uni((const T*)D.Q[slot]);
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int r = rY0 + q;
     const int C0 = (r + 2) * LW + cY + 2;
     const unsigned ii = oI + (unsigned)(q * ipitch);
-    stu(xhP, ii, sm.p[C0] + sm.x.s.u[r * TXP + cY]);
-    stu(xhQ, ii, sm.q[C0] + sm.x.s.v[r * TXP + cY]);
+    const unsigned og = oG + (unsigned)(q * pitch);
+    stu(xhP, ii, (CORR ? ldu(Pb, og) : sm.p[C0]) + sm.x.s.u[r * TXP + cY]);
+    stu(xhQ, ii, (CORR ? ldu(Qb, og) : sm.q[C0]) + sm.x.s.v[r * TXP + cY]);
   }
 }
 
@@ -1141,13 +1207,14 @@ __device__ __forceinline__ void reduce_line(int C, int L, int line, const gp<con
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ doms, const int* __restrict__ line_map,
-                                                int nd, int lines) {
+                                                int nd, int lines, int pass) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= lines) return;
   int dom, l;
   locate(line_map, nd, gid, dom, l);
   const DomDev<T>& D = doms[dom];
   if (D.st->halt) return;
+  if (pass == 1 && !D.corrector) return;      // the corrector pass
   if (l < D.ny) reduce_line<T>(D.cx, D.ny, l, gbl((const T*)D.chx), gbl((const T*)D.rsx), gbl(D.ifx));
   else reduce_line<T>(D.cy, D.nx, l - D.ny, gbl((const T*)D.chy), gbl((const T*)D.rsy), gbl(D.ify));
 }
@@ -1216,7 +1283,11 @@ struct alignas(16) FinSmem {
   } u;
 };
 
-template <typename T, int TY, int MX>
+// MODE 0: finalizes the AB3 step in a launch where no domain runs the
+// corrector.  MODE 1: the same where some do; for those it finalizes the
+// predicted level (surface in w[2], no sponge, no run-up record).  MODE 2:
+// finalizes the corrector of the domains that run it.
+template <typename T, int TY, int MX, int MODE>
 __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                              int nd) {
   using S = FinSmem<T, TY, MX>;
@@ -1228,11 +1299,13 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   const DomDev<T>& D = doms[dom];
   DevState* st = D.st;
   if (st->halt) return;
+  if (MODE == 2 && !D.corrector) return;
+  const bool pred = MODE == 1 && D.corrector;          // the predictor's level
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
   const int ns = uni(st->slot == 2 ? 0 : st->slot + 1);   // slot of level n + 1
   const int par = uni((int)((st->n + 1) & 1));
-  T* const w = uni(D.w[par]);
+  T* const w = uni(pred ? D.w[2] : D.w[par]);
   T* const P = uni(D.P[ns]);
   T* const Q = uni(D.Q[ns]);
   const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
@@ -1335,7 +1408,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     const T Db = sm.db[(r + 1) * BX + cY + 1];
     if (i >= nx || j >= ny) continue;
     const unsigned og = oG + (unsigned)(q * pitch);
-    if (D.any_sponge && Db > T(0)) {
+    if (D.any_sponge && !pred && Db > T(0)) {
       const T dist[4] = {(T(i) + T(0.5)) * D.dx, (T(nx - i) - T(0.5)) * D.dx, (T(j) + T(0.5)) * D.dy,
                          (T(ny - j) - T(0.5)) * D.dy};
       T sig = T(0);
@@ -1358,7 +1431,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     stu(P, og, p);
     stu(Q, og, qv);
     const T h = fmax(wv + Db, T(0));
-    if (D.runup && h > D.runup_delta) {
+    if (D.runup && !pred && h > D.runup_delta) {
       // run-up record: highest surface over the inundated states (NaN until
       // the first one)
       const gp<T> wm = gbl(D.wmax);

@@ -365,6 +365,7 @@ struct Launch {
   int* tile_map = nullptr;      // per tile: domain << MAP_SHIFT | tile (batches; NULL for one domain)
   int* line_map = nullptr;      // per line: domain << MAP_SHIFT | line
   int nd = 0, tiles = 0, lines = 0;
+  int any_pc = 0;               // some member runs the corrector pass
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;          // steps per replay (0 = none)
   int graph_built = 0;          // steps captured in `graph`
@@ -444,7 +445,7 @@ static Layout layout_for(const bq_params* p) {
   };
   L.off_state = take(sizeof(DevState));
   L.off_desc = take(sizeof(DomDev<T>));
-  L.off_w = take(2 * L.ghosted);
+  L.off_w = take((p->corrector ? 3 : 2) * L.ghosted);   // + the predicted surface
   L.off_P = take(3 * L.ghosted);
   L.off_Q = take(3 * L.ghosted);
   L.off_E = take(3 * L.interior);
@@ -492,6 +493,7 @@ static int check_params(const bq_params* p) {
     return fail(BQ_EINVAL, "a time-series boundary needs 1 <= ts_n <= 2^26 samples, ts_dt > 0 and both arrays");
   if (!(p->friction_f >= 0) || !(p->manning_n >= 0)) return fail(BQ_EINVAL, "friction coefficients must be >= 0");
   if (!(p->runup_delta >= 0)) return fail(BQ_EINVAL, "runup_delta must be >= 0");
+  if (p->corrector != 0 && p->corrector != 1) return fail(BQ_EINVAL, "corrector must be 0 or 1");
   const bool wave = p->bc[0] == BQ_SINE || p->bc[0] == BQ_IRREGULAR;
   if (p->n_waves < 0 || p->n_waves > BQ_MAX_WAVES) return fail(BQ_EINVAL, "n_waves out of range");
   if (wave && (p->n_waves < 1 || !p->wave_amp || !p->wave_omega))
@@ -547,6 +549,7 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.ts_n = p->bc[0] == BQ_TIMESERIES ? p->ts_n : 0;
   D.ts_dt = p->ts_dt;
   D.runup = p->runup_delta > 0.0 ? 1 : 0;
+  D.corrector = p->corrector ? 1 : 0;
   D.runup_delta = (T)p->runup_delta;
   {
     const double dx = p->dx, dy = p->dy, bc = p->B + 1.0 / 3.0;
@@ -582,7 +585,7 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.dt_min = p->dt_min;
   D.wave_ramp = p->wave_ramp;
   D.t_end = p->t_end;
-  for (int k = 0; k < 2; ++k) D.w[k] = (T*)(b + Ly.off_w + k * Ly.ghosted);
+  for (int k = 0; k < 3; ++k) D.w[k] = k < 2 || D.corrector ? (T*)(b + Ly.off_w + k * Ly.ghosted) : nullptr;
   for (int k = 0; k < 3; ++k) {
     D.P[k] = (T*)(b + Ly.off_P + k * Ly.ghosted);
     D.Q[k] = (T*)(b + Ly.off_Q + k * Ly.ghosted);
@@ -615,6 +618,7 @@ static int create_t(bq_domain* d, const double* depth_c) {
   d->L.table = d->ddev;
   d->L.tile_map = d->L.line_map = nullptr;
   d->L.nd = 1;
+  d->L.any_pc = D.corrector;
   d->L.tiles = Ly.tiles_x * Ly.tiles_y;
   d->L.lines = p->nx + p->ny;
   if (D.n_waves > 0) {
@@ -687,9 +691,17 @@ static void enqueue_step(const Launch& L, hipStream_t s, double dt_prescribed) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
   k_dt<T><<<L.nd, 64, 0, s>>>(tab, dt_prescribed);
-  k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
-  k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines);
-  k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+  k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+  k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
+  if (!L.any_pc) {
+    k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+  } else {
+    k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    // corrector pass of the domains that run it (the others return at once)
+    k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
+    k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+  }
 }
 
 template <typename T>
@@ -731,29 +743,39 @@ template <typename T>
 static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
-  hipEvent_t ev[5];
-  for (int k = 0; k < 5; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  hipEvent_t ev[8];
+  for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&ev[k]));
   double acc[4] = {0, 0, 0, 0};
   int rc = BQ_OK;
+  const int last = L.any_pc ? 7 : 4;
   for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
     if (hipEventRecord(ev[0], s) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventRecord"); break; }
     k_dt<T><<<L.nd, 64, 0, s>>>(tab, 0.0);
     (void)hipEventRecord(ev[1], s);
-    k_rhs<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     (void)hipEventRecord(ev[2], s);
-    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines);
+    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
     (void)hipEventRecord(ev[3], s);
-    k_final<T, TY, MX><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    if (L.any_pc) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    else k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     (void)hipEventRecord(ev[4], s);
-    if (hipEventSynchronize(ev[4]) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventSynchronize"); break; }
-    for (int k = 0; k < 4; ++k) {
+    if (L.any_pc) {
+      k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+      (void)hipEventRecord(ev[5], s);
+      k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
+      (void)hipEventRecord(ev[6], s);
+      k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+      (void)hipEventRecord(ev[7], s);
+    }
+    if (hipEventSynchronize(ev[last]) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventSynchronize"); break; }
+    for (int k = 0; k < last; ++k) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
-      acc[k] += ms;
+      acc[k < 4 ? k : k - 3] += ms;     // the corrector pass adds to its kernels' entries
     }
   }
   enqueue_commit<T>(L, s);
-  for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+  for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[k]);
   if (rc) return rc;
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -905,6 +927,8 @@ static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, 
   L.nd = nd;
   L.tiles = (int)tmap.size();
   L.lines = (int)lmap.size();
+  L.any_pc = 0;
+  for (int k = 0; k < nd; ++k) L.any_pc |= tab[k].corrector;
   return BQ_OK;
 }
 
@@ -999,10 +1023,11 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   if (b->lanes == 1) return profile_t<T>(b->L, b->stream, n_steps, ms_out);
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   hipStream_t ss[2] = {b->stream, b->aux};
-  hipEvent_t ev[2][5];
+  hipEvent_t ev[2][8];
   for (int l = 0; l < 2; ++l)
-    for (int k = 0; k < 5; ++k) HIPCHK(hipEventCreate(&ev[l][k]));
+    for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&ev[l][k]));
   double acc[4] = {0, 0, 0, 0};
+  const int last = (b->G[0].any_pc || b->G[1].any_pc) ? 7 : 4;
   int rc = fork_aux(b);
   for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
     for (int l = 0; l < 2; ++l) (void)hipEventRecord(ev[l][0], ss[l]);
@@ -1011,35 +1036,42 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
       k_dt<T><<<L.nd, 64, 0, ss[l]>>>((const DomDev<T>*)L.table, 0.0);
       (void)hipEventRecord(ev[l][1], ss[l]);
     }
-    for (int l = 0; l < 2; ++l) {
-      const Launch& L = b->G[l];
-      k_rhs<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
-      (void)hipEventRecord(ev[l][2], ss[l]);
-    }
-    for (int l = 0; l < 2; ++l) {
-      const Launch& L = b->G[l];
-      k_reduced<T><<<cdiv(L.lines, 256), 256, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_map, L.nd,
-                                                          L.lines);
-      (void)hipEventRecord(ev[l][3], ss[l]);
-    }
-    for (int l = 0; l < 2; ++l) {
-      const Launch& L = b->G[l];
-      k_final<T, TY, MX><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
-      (void)hipEventRecord(ev[l][4], ss[l]);
+    for (int pass = 0; pass < (last == 7 ? 2 : 1); ++pass) {
+      const int e0 = pass == 0 ? 1 : 4;
+      for (int l = 0; l < 2; ++l) {
+        const Launch& L = b->G[l];
+        if (pass == 0) k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
+        else k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
+        (void)hipEventRecord(ev[l][e0 + 1], ss[l]);
+      }
+      for (int l = 0; l < 2; ++l) {
+        const Launch& L = b->G[l];
+        k_reduced<T><<<cdiv(L.lines, 256), 256, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_map, L.nd,
+                                                            L.lines, pass);
+        (void)hipEventRecord(ev[l][e0 + 2], ss[l]);
+      }
+      for (int l = 0; l < 2; ++l) {
+        const Launch& L = b->G[l];
+        const DomDev<T>* tb = (const DomDev<T>*)L.table;
+        if (pass == 1) k_final<T, TY, MX, 2><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
+        else if (L.any_pc) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
+        else k_final<T, TY, MX, 0><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
+        (void)hipEventRecord(ev[l][e0 + 3], ss[l]);
+      }
     }
     for (int l = 0; l < 2 && rc == BQ_OK; ++l)
-      if (hipEventSynchronize(ev[l][4]) != hipSuccess) rc = fail(BQ_EDEVICE, "hipEventSynchronize");
+      if (hipEventSynchronize(ev[l][last]) != hipSuccess) rc = fail(BQ_EDEVICE, "hipEventSynchronize");
     for (int l = 0; l < 2 && rc == BQ_OK; ++l)
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < last; ++k) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev[l][k], ev[l][k + 1]);
-        acc[k] += 0.5 * ms;
+        acc[k < 4 ? k : k - 3] += 0.5 * ms;
       }
   }
   for (int l = 0; l < 2; ++l) enqueue_commit<T>(b->G[l], ss[l]);
   const int rj = join_aux(b);
   for (int l = 0; l < 2; ++l)
-    for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[l][k]);
+    for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[l][k]);
   if (rc) return rc;
   if (rj) return rj;
   HIPCHK(hipGetLastError());

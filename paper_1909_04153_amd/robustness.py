@@ -125,10 +125,17 @@ def largest_stable_fixed_dt(spec, t_end, lo, hi, precision=bq.FP32, rel_tol=0.03
     return lo, runs
 
 
-def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0), log=None):
-    """The conical-island comparison at nx x nx cells over the same 30 m basin."""
+def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0), log=None, corrector=False,
+          cfl=None):
+    """The conical-island comparison at nx x nx cells over the same 30 m basin
+    (optionally with the Adams-Moulton corrector, and another CFL target)."""
     dx = 30.0 / (nx - 1) if nx != 601 else 0.05
-    spec = S.conical_island(nx=nx, ny=nx, dx=dx)
+    kw = {}
+    if corrector:
+        kw.update(corrector=1, fstar_order=2)
+    if cfl is not None:
+        kw.update(cfl=float(cfl))
+    spec = S.conical_island(nx=nx, ny=nx, dx=dx, **kw)
     t0 = time.perf_counter()
     ad = run(spec, t_end, precision, snapshots=snapshots)
     t_ad = time.perf_counter() - t0
@@ -144,6 +151,7 @@ def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0
     t_fx = time.perf_counter() - t0
     res = dict(
         scenario=spec["name"], t_end=t_end, precision="fp32" if precision == bq.FP32 else "fp64",
+        corrector=bool(corrector), cfl=spec["params"]["cfl"], fstar_order=spec["params"]["fstar_order"],
         adaptive=dict(stable=ad["stable"], reason=ad["reason"], steps=ad["steps"], dt_first=float(dts[0]),
                       dt_min=float(dts.min()), dt_max=float(dts.max()), dt_mean=float(ad["t"] / ad["steps"]),
                       t_min_dt=float(ad["trace"][1 + int(np.argmin(dts))][0]), seconds=t_ad,
@@ -166,9 +174,12 @@ def main():
     ap.add_argument("--nx", type=int, default=601)
     ap.add_argument("--t-end", type=float, default=20.0)
     ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--corrector", action="store_true", help="AB3 predictor + Adams-Moulton corrector")
+    ap.add_argument("--cfl", type=float, default=None, help="CFL target of the adaptive run")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
-    res = study(a.nx, a.t_end, bq.FP64 if a.fp64 else bq.FP32, log=lambda m: print(m, flush=True))
+    res = study(a.nx, a.t_end, bq.FP64 if a.fp64 else bq.FP32, log=lambda m: print(m, flush=True),
+                corrector=a.corrector, cfl=a.cfl)
     txt = json.dumps(res)
     print(txt, flush=True)
     if a.out:

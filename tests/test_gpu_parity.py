@@ -102,9 +102,16 @@ CASES = {
     "tiny_4x4": lambda: S.closed_basin_hump(nx=4, ny=4, dx=0.5, cfl=0.125, fstar_order=1),
     # x-lines of 2100 cells: more chunks than one wave of the line coupling
     "long_lines": lambda: S.solitary_flat(nx=2100, ny=8, dx=0.05, x0=50.0),
+    # Adams-Moulton corrector: 2D with the paper's quadratic F* extrapolation
+    # in the predictor at CFL 0.25; wavemaker Dirichlet rows, friction and
+    # wet/dry run-up; sponges and the island's run-up
+    "pc_hump_2d": lambda: S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.25, fstar_order=2, corrector=1),
+    "pc_beach_ragged": lambda: S.sloping_beach(nx=133, ny=21, dx=0.1, x_toe=1.0, amp=0.05, ramp=1.0, t_end=0.0,
+                                               corrector=1),
+    "pc_conical_island": lambda: S.conical_island(nx=121, ny=121, dx=0.25, corrector=1, cfl=0.25, fstar_order=2),
 }
 STEPS = {"beach_ragged": 700, "rip_2d": 150, "hump_2d": 300, "dam_break": 200, "central_slopes": 300,
-         "tiny_4x4": 100, "long_lines": 100}
+         "tiny_4x4": 100, "long_lines": 100, "pc_hump_2d": 300, "pc_beach_ragged": 700, "pc_conical_island": 300}
 
 
 # The dry-bed dam break is the one case whose per-step bar is set by the
@@ -141,6 +148,7 @@ FP32_CASES = {
     # that it stays clear of the walls, a 2D hump in a closed basin
     "solitary": lambda: S.solitary_flat(nx=480, ny=8, x0=8.0),
     "hump_2d": lambda: S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.125, fstar_order=1),
+    "pc_hump_2d": lambda: S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.25, fstar_order=2, corrector=1),
 }
 
 
@@ -342,3 +350,46 @@ def test_fp64_conical_island_runup(bq):
     worst, o, g = run_compare(bq, spec, 500, 25, 1e-12)
     print(f"conical island 121^2 FP64 worst rel L2 {worst:.2e}")
     _compare_maps(o, g, spec, 0.3)
+
+
+def test_corrector_batch_mixed_with_plain_domains(bq):
+    # predictor-corrector and plain domains in one batch, one and two lanes,
+    # graph replays: every member bitwise equal to its solo run
+    specs = [S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.25, fstar_order=2, corrector=1),
+             S.solitary_flat(nx=130, ny=70, x0=2.0),
+             S.sloping_beach(nx=200, ny=40, dx=0.1, x_toe=2.0, t_end=0.0, corrector=1),
+             S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0)]
+    solo = []
+    for sp in specs:
+        g = bq.domain_from_spec(sp, precision=bq.FP32)
+        g.set_graph_steps(0)
+        g.step(24)
+        g.sync()
+        solo.append([g.read(f) for f in FIELDS])
+    for lanes in (1, 2):
+        doms = [bq.domain_from_spec(sp, precision=bq.FP32) for sp in specs]
+        b = bq.Batch(doms, lanes=lanes)
+        b.set_graph_steps(8)
+        ms = b.profile(2)
+        assert all(v > 0.0 for v in ms.values())
+        b.step(22)
+        b.sync()
+        for d, ref in zip(doms, solo):
+            assert d.sync().n == 24
+            for f, r in zip(FIELDS, ref):
+                assert np.array_equal(d.read(f), r), (lanes, f)
+        b.close()
+
+
+def test_corrector_checkpoint_resume_is_bitwise(bq):
+    spec = S.conical_island(nx=121, ny=121, dx=0.25, corrector=1, cfl=0.25, fstar_order=2)
+    a = bq.domain_from_spec(spec, precision=bq.FP32)
+    a.step(40)
+    blob = a.save()
+    a.step(30)
+    ref = [a.read(f) for f in FIELDS + ("runup",)]
+    b = bq.domain_from_spec(spec, precision=bq.FP32)
+    b.load_checkpoint(blob)
+    b.step(30)
+    for f, r in zip(FIELDS + ("runup",), ref):
+        assert np.array_equal(b.read(f), r, equal_nan=True), f
