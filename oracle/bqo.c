@@ -34,6 +34,9 @@
  *       brute-force running maximum over every step's state.
  *   local CFL map (Eq. 22) ......................... pinned: flat lake at rest
  *       equals the CFL number.
+ *   Adams-Moulton corrector (Sec. 1, built like Eq. 30) ... pinned: constant-
+ *       step coefficients, exactness on polynomials, order 4 on an ODE and
+ *       fourth-order self-convergence of the full step on a smooth case.
  *   wavemaker ghost values, sponge (Sec. 3.3, readings) ... parity unpinned
  *       beyond the MS wave number (bisection vs. relation).
  */
