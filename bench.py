@@ -89,12 +89,23 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def make_group(bq, specs, dtype, lanes=2):
+def make_group(bq, specs, dtype, lanes=2, batch=False):
+    """the domains and what advances them: the domain itself, or a batch
+    (always for several domains; for one domain when `batch`, so that its
+    schedule can be tuned)"""
     prec = bq.FP32 if dtype == "fp32" else bq.FP64
     doms = [bq.domain_from_spec(s, precision=prec) for s in specs]
-    if len(doms) == 1:
+    if len(doms) == 1 and not batch:
         return doms, doms[0]
     return doms, bq.Batch(doms, lanes=lanes)
+
+
+def tuned(group, args):
+    """apply the autotuned (or cached) schedule to a batch; returns it"""
+    if args.no_autotune or not hasattr(group, "autotune"):
+        return None
+    t = group.autotune(steps_per_trial=32, cache=args.tune_cache)
+    return {k: t[k] for k in ("lanes", "graph_steps", "reduce_block", "swizzle", "cached")}
 
 
 def timed(torch, group, steps, warmup):
@@ -223,7 +234,11 @@ def main():
     ap.add_argument("--workload", default="batch64")
     ap.add_argument("--profile-steps", type=int, default=20)
     ap.add_argument("--lanes", type=int, default=2, choices=(1, 2),
-                    help="launch lanes of a batch (two groups on two streams, or one)")
+                    help="launch lanes of a batch (two groups on two streams, or one) with --no-autotune")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default batch schedule instead of running the library's autotuner")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of autotuned schedules per batch shape (read, and written after tuning)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -256,6 +271,12 @@ def main():
     specs, dtype = workload(args.workload)
     cells = sum(s["params"]["nx"] * s["params"]["ny"] for s in specs)
     doms, group = make_group(bq, specs, dtype, args.lanes)
+    schedule = None
+    if isinstance(group, bq.Batch):
+        if not args.no_autotune:
+            # trial steps are ordinary steps of the batch, before the warm-up
+            schedule = group.autotune(steps_per_trial=32, cache=args.tune_cache)
+        schedule = dict(group.tune, **({"cached": schedule["cached"]} if schedule else {"autotuned": False}))
     lanes = getattr(group, "lanes", 1)
     el = timed(torch, group, args.steps, args.warmup)
     value = cells * args.steps / el / 1e9
@@ -288,7 +309,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
            "config": {"workload": args.workload, "domains": len(specs), "cells": cells,
-                      "graph_steps": 16, "precision": dtype, "lanes": lanes},
+                      "precision": dtype, "lanes": lanes, "schedule": schedule},
            "effective_hbm_frac": WORDS_STEP * wsize * cells * args.steps / el / 1e9 / HBM_PEAK_GBS,
            "kernels_ms": kms, "roofline": roof}
     if kms2 is not None:
@@ -303,12 +324,13 @@ def main():
     if not args.no_fp64:
         # one C3-type domain (2048 x 2048 rip beach, FP32): the single-domain rate
         sp, dt_ = workload("rip2048")
-        ds, g = make_group(bq, sp, dt_)
+        ds, g = make_group(bq, sp, dt_, batch=True)
+        sched_c3 = tuned(g, args)
         c = sum(s["params"]["nx"] * s["params"]["ny"] for s in sp)
         n = max(20, args.steps // 2)
         e = timed(torch, g, n, args.warmup)
         out["fp32_single_c3"] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / n * 1e3,
-                                 "cells": c, "steps": n,
+                                 "cells": c, "steps": n, "schedule": sched_c3,
                                  "effective_hbm_frac": WORDS_STEP * 4 * c * n / e / 1e9 / HBM_PEAK_GBS}
         del g, ds
         torch.cuda.synchronize()
@@ -318,11 +340,12 @@ def main():
         for s_ in sp:
             s_["params"] = dict(s_["params"], corrector=1)
         ds, g = make_group(bq, sp, dt_, args.lanes)
+        sched_pc = tuned(g, args)
         c = sum(s_["params"]["nx"] * s_["params"]["ny"] for s_ in sp)
         n = max(20, args.steps // 2)
         e = timed(torch, g, n, args.warmup)
         out["fp32_batch64_corrector"] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s",
-                                         "ms_per_step": e / n * 1e3, "cells": c, "steps": n}
+                                         "ms_per_step": e / n * 1e3, "cells": c, "steps": n, "schedule": sched_pc}
         del g, ds
         torch.cuda.synchronize()
         fp64 = {}

@@ -193,14 +193,17 @@ int bq_batch_free(bq_batch* b);
 
 /* Launch lanes of a batch (1 or 2; default 2).  With 2 lanes the members are
  * split into two groups of about equal cell count and each group is advanced
- * on its own stream: the batch's stream and one the batch owns, joined to
- * the batch's stream by events at the end of every bq_batch_step, so the
- * caller sees one stream.  One group's stencil/update kernel (arithmetic
- * bound) then runs beside the other group's line-coupling and finalize
- * kernels (latency and bandwidth bound).  Each domain's arithmetic is the
- * same for any lane count, so results are bitwise identical.  Changing the
- * lane count waits for the batch's queued work.  bq_batch_lanes returns the
- * lanes in use (1 when the batch has one member). */
+ * on its own stream; the batch creates both streams itself, one after the
+ * other, so the runtime gives them different hardware queues.  The lanes
+ * start after the work queued on the batch's stream and the batch's stream
+ * waits for both (events at the start and end of every bq_batch_step), so
+ * the caller sees one stream.  One group's stencil/update kernel
+ * (arithmetic bound) then runs beside the other group's line-coupling and
+ * finalize kernels (latency and bandwidth bound).  Each domain's arithmetic
+ * is the same for any lane count, so results are bitwise identical.
+ * Changing the lane count waits for the batch's queued work.
+ * bq_batch_lanes returns the lanes in use (1 when the batch has one
+ * member). */
 int bq_batch_set_lanes(bq_batch* b, int32_t lanes);
 int bq_batch_lanes(const bq_batch* b);
 
@@ -213,6 +216,31 @@ int bq_batch_lanes(const bq_batch* b);
  * steps advance the state like bq_step / bq_batch_step. */
 int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out);
 int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
+
+/* Schedule of a batch: launch lanes, steps per hipGraph replay, threads per
+ * block of the line-coupling kernel (64, 128 or 256) and the XCD-aware tile
+ * order of the stencil kernel (1 on, 0 off).  Every schedule gives bitwise
+ * the same results; they differ only in speed. */
+typedef struct bq_tune {
+  int32_t lanes;
+  int32_t graph_steps;
+  int32_t reduce_block;
+  int32_t swizzle;
+  double ms_per_step;      /* bq_batch_autotune: measured time of one step */
+} bq_tune;
+
+/* Autotuner: times steps_per_trial steps of the batch under each candidate
+ * schedule (lanes 1-2 x graph replays of 4 or 16 steps x line-coupling blocks
+ * of 64 or 256 threads; XCD-aware tile order on) twice, in forward then
+ * reverse order,
+ * keeps the one of the lowest mean time and returns it.  The
+ * trial steps are real steps (the domains advance by them, with the same
+ * results as under any schedule).  bq_batch_set_tune applies a schedule, for
+ * instance one cached from an earlier autotune of a batch of the same shape;
+ * bq_batch_get_tune reports the current one (ms_per_step 0). */
+int bq_batch_autotune(bq_batch* b, int32_t steps_per_trial, bq_tune* out);
+int bq_batch_set_tune(bq_batch* b, const bq_tune* t);
+int bq_batch_get_tune(const bq_batch* b, bq_tune* out);
 
 /* Number of steps captured per hipGraph replay (0 = plain launches). */
 int bq_set_graph_steps(bq_domain* d, int32_t steps);

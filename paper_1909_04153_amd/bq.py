@@ -55,11 +55,19 @@ class Info(ctypes.Structure):
                 ("mass", ctypes.c_double), ("energy", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("lanes", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("reduce_block", ctypes.c_int32),
+                ("swizzle", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 EXPORTS = ["bq_abi_version", "bq_last_error", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
            "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
            "bq_batch_create", "bq_batch_set", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
            "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps",
-           "bq_batch_set_lanes", "bq_batch_lanes"]
+           "bq_batch_set_lanes", "bq_batch_lanes", "bq_batch_autotune", "bq_batch_set_tune", "bq_batch_get_tune"]
 KERNELS = ("k_dt", "k_rhs", "k_reduced", "k_final")
 
 _lib = None
@@ -100,6 +108,9 @@ def load(path: str | None = None):
     L.bq_batch_profile_steps.argtypes = [vp, ip, dp]
     L.bq_batch_set_lanes.argtypes = [vp, ip]
     L.bq_batch_lanes.argtypes = [vp]
+    L.bq_batch_autotune.argtypes = [vp, ip, ctypes.POINTER(Tune)]
+    L.bq_batch_set_tune.argtypes = [vp, ctypes.POINTER(Tune)]
+    L.bq_batch_get_tune.argtypes = [vp, ctypes.POINTER(Tune)]
     if L.bq_abi_version() != ABI_VERSION:
         raise RuntimeError("libbq ABI version mismatch")
     if path is None:
@@ -312,6 +323,56 @@ class Batch:
 
     def set_graph_steps(self, k: int):
         _check(load().bq_batch_set_graph_steps(self._h, int(k)))
+
+    @property
+    def tune(self) -> dict:
+        t = Tune()
+        _check(load().bq_batch_get_tune(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tune(self, tune: dict):
+        t = Tune(int(tune["lanes"]), int(tune["graph_steps"]), int(tune["reduce_block"]), int(tune["swizzle"]), 0.0)
+        _check(load().bq_batch_set_tune(self._h, ctypes.byref(t)))
+
+    def shape_key(self) -> str:
+        """cache key: device, precision, member count and total cells (both
+        rounded up to powers of two), and whether the corrector runs"""
+        torch = _torch()
+        cells = sum(d.nx * d.ny for d in self.domains)
+        prec = {FP64: "fp64", FP32: "fp32"}[self.domains[0].precision]
+        pc = "|pc" if any(d.params.get("corrector") for d in self.domains) else ""
+        # the architecture and compute-unit count name the device (the
+        # marketing name is not reported under every tool)
+        props = torch.cuda.get_device_properties(self.domains[0].workspace.device)
+        dev = f"{(getattr(props, 'gcnArchName', '') or 'gpu').split(':')[0]}x{props.multi_processor_count}"
+        return (f"{dev}|{prec}|n{1 << max(0, (len(self.domains) - 1).bit_length())}"
+                f"|c{1 << max(0, (cells - 1).bit_length())}{pc}")
+
+    def autotune(self, steps_per_trial: int = 16, cache: str | None = None) -> dict:
+        """Run the library's schedule autotuner (the trial steps advance the
+        domains like ordinary steps) or apply the schedule cached for this
+        batch's shape in the JSON file `cache`; returns the schedule."""
+        import json
+
+        key = self.shape_key() if cache else None
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                known = json.load(fh)
+            if key in known:
+                self.set_tune(known[key])
+                return dict(known[key], cached=True)
+        t = Tune()
+        _check(load().bq_batch_autotune(self._h, int(steps_per_trial), ctypes.byref(t)))
+        res = t.as_dict()
+        if cache:
+            known = {}
+            if os.path.exists(cache):
+                with open(cache) as fh:
+                    known = json.load(fh)
+            known[key] = res
+            with open(cache, "w") as fh:
+                json.dump(known, fh, indent=1, sort_keys=True)
+        return dict(res, cached=False)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -706,14 +706,15 @@ struct alignas(16) RhsSmem {
 // corrector are skipped.
 template <typename T, int TY, int MX, bool CORR>
 __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
-                                           int nd) {
+                                           int nd, int swizzle) {
   using S = RhsSmem<T, TY, MX>;
   constexpr int WX = S::WX, LW = S::LW, AXP = S::AXP, BX = S::BX, CXN = S::CXN, TXP = S::TXP;
   constexpr int CPT = (TX * TY) / NT;                 // cells per thread
   static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
   __shared__ S sm;
   int dom, tile;
-  locate(tile_map, nd, xcd_tile(blockIdx.x, gridDim.x), dom, tile);
+  // swizzle = 1: XCD-aware tile order (each XCD walks a contiguous run)
+  locate(tile_map, nd, swizzle ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x, dom, tile);
   const DomDev<T>& D = doms[dom];
   const DevState* st = D.st;
   if (st->halt) return;

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <algorithm>
@@ -366,6 +367,10 @@ struct Launch {
   int* line_map = nullptr;      // per line: domain << MAP_SHIFT | line
   int nd = 0, tiles = 0, lines = 0;
   int any_pc = 0;               // some member runs the corrector pass
+  // schedule (tuned per batch): threads per block of the line-coupling
+  // kernel, XCD-aware tile order of the stencil kernel
+  int rblock = 256;
+  int swizzle = 1;
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;          // steps per replay (0 = none)
   int graph_built = 0;          // steps captured in `graph`
@@ -396,15 +401,19 @@ struct bq_batch {
   size_t mem_bytes = 0;
   Launch L;                     // all members, one lane
   // Two lanes: the members split into two groups of about equal cell count,
-  // each advanced on its own stream (the batch's stream and `aux`), so one
-  // group's stencil kernel (arithmetic-bound) runs beside the other group's
-  // line-coupling and finalize kernels (bandwidth- and latency-bound).
+  // each advanced on a stream of its own, so one group's stencil kernel
+  // (arithmetic-bound) runs beside the other group's line-coupling and
+  // finalize kernels (bandwidth- and latency-bound).  The batch creates both
+  // lane streams itself, one right after the other, so the runtime puts them
+  // on different hardware queues (two streams sharing a queue run one after
+  // the other, and the lanes would not overlap).
   Launch G[2];
   int lanes_req = 2;            // requested lanes (1 or 2)
   int lanes = 1;                // lanes in use (1 if there is one member)
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t lane[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int graph_steps = 16;
+  int rblock = 256, swizzle = 1;  // schedule copied into the launches
 };
 
 // layout of a domain in its workspace
@@ -691,15 +700,15 @@ static void enqueue_step(const Launch& L, hipStream_t s, double dt_prescribed) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
   k_dt<T><<<L.nd, 64, 0, s>>>(tab, dt_prescribed);
-  k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
-  k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
+  k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+  k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
   if (!L.any_pc) {
     k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
   } else {
     k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     // corrector pass of the domains that run it (the others return at once)
-    k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
-    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
+    k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+    k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
     k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
   }
 }
@@ -752,17 +761,17 @@ static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
     if (hipEventRecord(ev[0], s) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventRecord"); break; }
     k_dt<T><<<L.nd, 64, 0, s>>>(tab, 0.0);
     (void)hipEventRecord(ev[1], s);
-    k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
     (void)hipEventRecord(ev[2], s);
-    k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
+    k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
     (void)hipEventRecord(ev[3], s);
     if (L.any_pc) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     else k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     (void)hipEventRecord(ev[4], s);
     if (L.any_pc) {
-      k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+      k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
       (void)hipEventRecord(ev[5], s);
-      k_reduced<T><<<cdiv(L.lines, 256), 256, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
+      k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
       (void)hipEventRecord(ev[6], s);
       k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
       (void)hipEventRecord(ev[7], s);
@@ -943,7 +952,8 @@ static int batch_build_t(bq_batch* b) {
   }
   // the previous tables may still be read by queued work
   HIPCHK(hipStreamSynchronize(b->stream));
-  if (b->aux) HIPCHK(hipStreamSynchronize(b->aux));
+  for (hipStream_t ls : b->lane)
+    if (ls) HIPCHK(hipStreamSynchronize(ls));
   b->lanes = (b->lanes_req == 2 && nd >= 2) ? 2 : 1;
   std::vector<bq_domain*> part[2];
   if (b->lanes == 2) {
@@ -975,13 +985,21 @@ static int batch_build_t(bq_batch* b) {
   char* m = (char*)b->mem;
   int rc = fill_launch<T>(b->L, m, b->doms, b->stream);
   if (rc) return rc;
+  b->L.rblock = b->rblock;
+  b->L.swizzle = b->swizzle;
   if (b->lanes == 2) {
     rc = fill_launch<T>(b->G[0], m + s0, part[0], b->stream);
     if (!rc) rc = fill_launch<T>(b->G[1], m + s0 + s1, part[1], b->stream);
     if (rc) return rc;
-    if (!b->aux) HIPCHK(hipStreamCreateWithFlags(&b->aux, hipStreamNonBlocking));
+    for (int l = 0; l < 2; ++l) {
+      b->G[l].rblock = b->rblock;
+      b->G[l].swizzle = b->swizzle;
+    }
+    for (int l = 0; l < 2; ++l)
+      if (!b->lane[l]) HIPCHK(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
     if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-    if (!b->ev_join) HIPCHK(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
+    for (int l = 0; l < 2; ++l)
+      if (!b->ev_join[l]) HIPCHK(hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming));
   } else {
     drop_graph<T>(b->G[0]);
     drop_graph<T>(b->G[1]);
@@ -990,17 +1008,19 @@ static int batch_build_t(bq_batch* b) {
   return BQ_OK;
 }
 
-// the aux lane starts after the work queued so far on the batch's stream, and
-// the batch's stream continues only after the aux lane's work
-static int fork_aux(bq_batch* b) {
+// the lanes start after the work queued so far on the batch's stream, and
+// the batch's stream continues only after both lanes' work
+static int fork_lanes(bq_batch* b) {
   HIPCHK(hipEventRecord(b->ev_fork, b->stream));
-  HIPCHK(hipStreamWaitEvent(b->aux, b->ev_fork, 0));
+  for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(b->lane[l], b->ev_fork, 0));
   return BQ_OK;
 }
 
-static int join_aux(bq_batch* b) {
-  HIPCHK(hipEventRecord(b->ev_join, b->aux));
-  HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join, 0));
+static int join_lanes(bq_batch* b) {
+  for (int l = 0; l < 2; ++l) {
+    HIPCHK(hipEventRecord(b->ev_join[l], b->lane[l]));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[l], 0));
+  }
   return BQ_OK;
 }
 
@@ -1008,10 +1028,10 @@ template <typename T>
 static int batch_run_t(bq_batch* b, int n_steps) {
   if (b->lanes == 1) return run_steps<T>(b->L, b->stream, n_steps, b->graph_steps);
   if (n_steps <= 0) return BQ_OK;
-  int rc = fork_aux(b);
-  if (!rc) rc = run_steps<T>(b->G[0], b->stream, n_steps, b->graph_steps);
-  if (!rc) rc = run_steps<T>(b->G[1], b->aux, n_steps, b->graph_steps);
-  const int rj = join_aux(b);
+  int rc = fork_lanes(b);
+  if (!rc) rc = run_steps<T>(b->G[0], b->lane[0], n_steps, b->graph_steps);
+  if (!rc) rc = run_steps<T>(b->G[1], b->lane[1], n_steps, b->graph_steps);
+  const int rj = join_lanes(b);
   return rc ? rc : rj;
 }
 
@@ -1022,13 +1042,13 @@ template <typename T>
 static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   if (b->lanes == 1) return profile_t<T>(b->L, b->stream, n_steps, ms_out);
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
-  hipStream_t ss[2] = {b->stream, b->aux};
+  hipStream_t ss[2] = {b->lane[0], b->lane[1]};
   hipEvent_t ev[2][8];
   for (int l = 0; l < 2; ++l)
     for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&ev[l][k]));
   double acc[4] = {0, 0, 0, 0};
   const int last = (b->G[0].any_pc || b->G[1].any_pc) ? 7 : 4;
-  int rc = fork_aux(b);
+  int rc = fork_lanes(b);
   for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
     for (int l = 0; l < 2; ++l) (void)hipEventRecord(ev[l][0], ss[l]);
     for (int l = 0; l < 2; ++l) {
@@ -1040,13 +1060,14 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
       const int e0 = pass == 0 ? 1 : 4;
       for (int l = 0; l < 2; ++l) {
         const Launch& L = b->G[l];
-        if (pass == 0) k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
-        else k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, ss[l]>>>((const DomDev<T>*)L.table, L.tile_map, L.nd);
+        const DomDev<T>* tb0 = (const DomDev<T>*)L.table;
+        if (pass == 0) k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, ss[l]>>>(tb0, L.tile_map, L.nd, L.swizzle);
+        else k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, ss[l]>>>(tb0, L.tile_map, L.nd, L.swizzle);
         (void)hipEventRecord(ev[l][e0 + 1], ss[l]);
       }
       for (int l = 0; l < 2; ++l) {
         const Launch& L = b->G[l];
-        k_reduced<T><<<cdiv(L.lines, 256), 256, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_map, L.nd,
+        k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_map, L.nd,
                                                             L.lines, pass);
         (void)hipEventRecord(ev[l][e0 + 2], ss[l]);
       }
@@ -1069,7 +1090,7 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
       }
   }
   for (int l = 0; l < 2; ++l) enqueue_commit<T>(b->G[l], ss[l]);
-  const int rj = join_aux(b);
+  const int rj = join_lanes(b);
   for (int l = 0; l < 2; ++l)
     for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[l][k]);
   if (rc) return rc;
@@ -1085,6 +1106,92 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
 // ---------------------------------------------------------------------------
 
 #define DISPATCH(prec, fn, ...) ((prec) == BQ_FP32 ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
+
+// ---------------------------------------------------------------------------
+// schedule autotuner
+// ---------------------------------------------------------------------------
+
+static void apply_schedule(bq_batch* b, int rblock, int swizzle) {
+  b->rblock = rblock;
+  b->swizzle = swizzle;
+  Launch* ls[3] = {&b->L, &b->G[0], &b->G[1]};
+  for (Launch* L : ls) {
+    L->rblock = rblock;
+    L->swizzle = swizzle;
+    // graphs hold the launch parameters they were captured with
+    if (L->graph) (void)hipGraphExecDestroy(L->graph);
+    L->graph = nullptr;
+  }
+}
+
+static int set_tune(bq_batch* b, const bq_tune* t) {
+  if (t->lanes != 1 && t->lanes != 2) return fail(BQ_EINVAL, "lanes must be 1 or 2");
+  if (t->graph_steps < 0) return fail(BQ_EINVAL, "graph_steps must be >= 0");
+  if (t->reduce_block != 64 && t->reduce_block != 128 && t->reduce_block != 256)
+    return fail(BQ_EINVAL, "reduce_block must be 64, 128 or 256");
+  if (t->swizzle != 0 && t->swizzle != 1) return fail(BQ_EINVAL, "swizzle must be 0 or 1");
+  if (t->lanes != b->lanes_req) {
+    b->lanes_req = t->lanes;
+    const int rc = DISPATCH(b->precision, batch_build_t, b);
+    if (rc) return rc;
+  }
+  b->graph_steps = t->graph_steps;
+  apply_schedule(b, t->reduce_block, t->swizzle);
+  return BQ_OK;
+}
+
+// Each candidate runs real steps of the method (every schedule gives the
+// same results bit for bit), so tuning costs no simulation work: warm-up
+// (which also captures the graph), then steps_per_trial timed steps.
+template <typename T>
+static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
+  std::vector<bq_tune> cands;
+  const int max_lanes = b->doms.size() >= 2 ? 2 : 1;
+  // The XCD-aware tile order is not searched: it cuts the stencil kernel's
+  // HBM traffic by a third (measured) while its effect on a whole step is
+  // below the trials' timing noise, so a search would pick it by chance.
+  for (int lanes = 1; lanes <= max_lanes; ++lanes)
+    for (int graph : {4, 16})
+      for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 0.0});
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  int rc = BQ_OK;
+  auto trial = [&](bq_tune& c) -> int {
+    int r = set_tune(b, &c);
+    const int warm = c.graph_steps > steps / 4 ? c.graph_steps : steps / 4;
+    if (!r) r = batch_run_t<T>(b, warm);
+    if (r) return r;
+    if (hipEventRecord(e0, b->stream) != hipSuccess) return fail(BQ_EDEVICE, "hipEventRecord");
+    r = batch_run_t<T>(b, steps);
+    if (r) return r;
+    if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(BQ_EDEVICE, "hipEvent");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    c.ms_per_step += 0.5 * ms / steps;
+    return BQ_OK;
+  };
+  // every candidate twice, in forward then reverse order, scored by the mean:
+  // a drift of the clocks over the tuning run (boost after idle, then
+  // settling) cancels instead of favouring the first candidates
+  for (size_t k = 0; k < cands.size() && rc == BQ_OK; ++k) rc = trial(cands[k]);
+  for (size_t k = cands.size(); k-- > 0 && rc == BQ_OK;) rc = trial(cands[k]);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (getenv("BQ_TUNE_LOG"))
+    for (const bq_tune& c : cands)
+      fprintf(stderr, "bq tune: lanes %d graph %d reduce_block %d swizzle %d: %.4f ms/step\n", c.lanes,
+              c.graph_steps, c.reduce_block, c.swizzle, c.ms_per_step);
+  int best = 0;
+  for (size_t k = 1; k < cands.size(); ++k)
+    if (cands[k].ms_per_step < cands[best].ms_per_step) best = (int)k;
+  rc = set_tune(b, &cands[best]);
+  if (rc) return rc;
+  *out = cands[best];
+  return BQ_OK;
+}
 
 extern "C" {
 
@@ -1255,7 +1362,8 @@ int bq_batch_step(bq_batch* b, int32_t n_steps) {
 int bq_batch_sync(bq_batch* b) {
   if (!b) return fail(BQ_EINVAL, "NULL batch");
   HIPCHK(hipStreamSynchronize(b->stream));
-  if (b->aux) HIPCHK(hipStreamSynchronize(b->aux));
+  for (hipStream_t ls : b->lane)
+    if (ls) HIPCHK(hipStreamSynchronize(ls));
   return BQ_OK;
 }
 
@@ -1274,16 +1382,35 @@ int bq_batch_set_graph_steps(bq_batch* b, int32_t steps) {
   return BQ_OK;
 }
 
+int bq_batch_autotune(bq_batch* b, int32_t steps_per_trial, bq_tune* out) {
+  if (!b || !out || steps_per_trial < 1) return fail(BQ_EINVAL, "bad argument");
+  return DISPATCH(b->precision, batch_autotune_t, b, steps_per_trial, out);
+}
+
+int bq_batch_set_tune(bq_batch* b, const bq_tune* t) {
+  if (!b || !t) return fail(BQ_EINVAL, "NULL argument");
+  return set_tune(b, t);
+}
+
+int bq_batch_get_tune(const bq_batch* b, bq_tune* out) {
+  if (!b || !out) return fail(BQ_EINVAL, "NULL argument");
+  *out = bq_tune{b->lanes, b->graph_steps, b->rblock, b->swizzle, 0.0};
+  return BQ_OK;
+}
+
 int bq_batch_free(bq_batch* b) {
   if (!b) return fail(BQ_EINVAL, "NULL batch");
   (void)hipStreamSynchronize(b->stream);
-  if (b->aux) (void)hipStreamSynchronize(b->aux);
+  for (hipStream_t ls : b->lane)
+    if (ls) (void)hipStreamSynchronize(ls);
   if (b->L.graph) (void)hipGraphExecDestroy(b->L.graph);
   for (int l = 0; l < 2; ++l)
     if (b->G[l].graph) (void)hipGraphExecDestroy(b->G[l].graph);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
-  if (b->aux) (void)hipStreamDestroy(b->aux);
+  for (int l = 0; l < 2; ++l) {
+    if (b->ev_join[l]) (void)hipEventDestroy(b->ev_join[l]);
+    if (b->lane[l]) (void)hipStreamDestroy(b->lane[l]);
+  }
   if (b->mem) (void)hipFree(b->mem);
   delete b;
   return BQ_OK;

@@ -50,18 +50,22 @@ def test_binding_struct_layout_matches_the_header(tmp_path):
     """offsets and sizes of bq_params / bq_info as the C compiler lays them out"""
     fields = [f for f, _ in bq.Params._fields_]
     info = [f for f, _ in bq.Info._fields_]
+    tune = [f for f, _ in bq.Tune._fields_]
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "bq.h"', "int main(void) {",
-           '  printf("%zu\\n", sizeof(bq_params));', '  printf("%zu\\n", sizeof(bq_info));']
+           '  printf("%zu\\n", sizeof(bq_params));', '  printf("%zu\\n", sizeof(bq_info));',
+           '  printf("%zu\\n", sizeof(bq_tune));']
     src += [f'  printf("%zu\\n", offsetof(bq_params, {f}));' for f in fields]
     src += [f'  printf("%zu\\n", offsetof(bq_info, {f}));' for f in info]
+    src += [f'  printf("%zu\\n", offsetof(bq_tune, {f}));' for f in tune]
     src += ["  return 0;", "}"]
     c = tmp_path / "layout.c"
     c.write_text("\n".join(src) + "\n")
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
-    want = [ctypes.sizeof(bq.Params), ctypes.sizeof(bq.Info)]
+    want = [ctypes.sizeof(bq.Params), ctypes.sizeof(bq.Info), ctypes.sizeof(bq.Tune)]
     want += [getattr(bq.Params, f).offset for f in fields] + [getattr(bq.Info, f).offset for f in info]
+    want += [getattr(bq.Tune, f).offset for f in tune]
     assert got == want
 
 

@@ -393,3 +393,37 @@ def test_corrector_checkpoint_resume_is_bitwise(bq):
     b.step(30)
     for f, r in zip(FIELDS + ("runup",), ref):
         assert np.array_equal(b.read(f), r, equal_nan=True), f
+
+
+def test_autotuner_schedules_are_bitwise_equal_and_cached(bq, tmp_path):
+    # the autotuner runs every candidate schedule on the batch itself; the
+    # members must end bitwise equal to solo runs of the same step count
+    specs = [S.sloping_beach(nx=200, ny=40, dx=0.1, x_toe=2.0, t_end=0.0),
+             S.solitary_flat(nx=130, ny=70, x0=2.0),
+             S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0),
+             S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.25, fstar_order=2, corrector=1)]
+    doms = [bq.domain_from_spec(sp, precision=bq.FP32) for sp in specs]
+    b = bq.Batch(doms)
+    cache = str(tmp_path / "tune.json")
+    t = b.autotune(steps_per_trial=4, cache=cache)
+    assert not t["cached"] and t["ms_per_step"] > 0
+    assert b.tune["lanes"] == t["lanes"] and b.tune["reduce_block"] == t["reduce_block"]
+    b.step(5)
+    b.sync()
+    n = doms[0].sync().n
+    assert n > 5 and all(d.sync().n == n for d in doms)
+    for sp, d in zip(specs, doms):
+        g = bq.domain_from_spec(sp, precision=bq.FP32)
+        g.step(n)
+        g.sync()
+        for f in FIELDS:
+            assert np.array_equal(d.read(f), g.read(f)), (sp.get("name"), f)
+    b.close()
+    # a batch of the same shape takes the cached schedule without trials
+    doms2 = [bq.domain_from_spec(sp, precision=bq.FP32) for sp in specs]
+    b2 = bq.Batch(doms2)
+    t2 = b2.autotune(steps_per_trial=4, cache=cache)
+    assert t2["cached"] and doms2[0].sync().n == 0
+    assert {k: b2.tune[k] for k in ("lanes", "graph_steps", "reduce_block", "swizzle")} == \
+        {k: t[k] for k in ("lanes", "graph_steps", "reduce_block", "swizzle")}
+    b2.close()
