@@ -105,7 +105,7 @@ def tuned(group, args):
     if args.no_autotune or not hasattr(group, "autotune"):
         return None
     t = group.autotune(steps_per_trial=32, cache=args.tune_cache)
-    return {k: t[k] for k in ("lanes", "graph_steps", "reduce_block", "swizzle", "cached")}
+    return {k: t[k] for k in ("lanes", "graph_steps", "reduce_block", "reduce_segments", "swizzle", "cached")}
 
 
 def timed(torch, group, steps, warmup):

@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define BQ_ABI_VERSION 3
+#define BQ_ABI_VERSION 4
 #define BQ_MAX_WAVES 256
 
 /* BQ_TIMESERIES: both west ghost columns take eta and P interpolated
@@ -218,24 +218,28 @@ int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out);
 int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
 
 /* Schedule of a batch: launch lanes, steps per hipGraph replay, threads per
- * block of the line-coupling kernel (64, 128 or 256) and the XCD-aware tile
- * order of the stencil kernel (1 on, 0 off).  Every schedule gives bitwise
- * the same results; they differ only in speed. */
+ * block of the line-coupling kernel (64, 128 or 256), the XCD-aware tile
+ * order of the stencil kernel (1 on, 0 off), and the line-coupling variant:
+ * reduce_segments 1 = one thread per line running over its chunks, 4 = the
+ * chunks of a line cut into 4 segments swept by 4 waves that exchange their
+ * composed maps (reduce_block is then 256).  With reduce_segments 1 every
+ * schedule gives bitwise the same results; the segmented variant
+ * reassociates the line-coupling products and differs at rounding level. */
 typedef struct bq_tune {
   int32_t lanes;
   int32_t graph_steps;
   int32_t reduce_block;
   int32_t swizzle;
+  int32_t reduce_segments;
   double ms_per_step;      /* bq_batch_autotune: measured time of one step */
 } bq_tune;
 
 /* Autotuner: times steps_per_trial steps of the batch under each candidate
- * schedule (lanes 1-2 x graph replays of 4 or 16 steps x line-coupling blocks
- * of 64 or 256 threads; XCD-aware tile order on) twice, in forward then
- * reverse order,
+ * schedule (lanes 1-2 x graph replays of 4 or 16 steps x line coupling by
+ * one thread per line in blocks of 64 or 256, or segmented; XCD-aware tile
+ * order on) twice, in forward then reverse order,
  * keeps the one of the lowest mean time and returns it.  The
- * trial steps are real steps (the domains advance by them, with the same
- * results as under any schedule).  bq_batch_set_tune applies a schedule, for
+ * trial steps are real steps (the domains advance by them).  bq_batch_set_tune applies a schedule, for
  * instance one cached from an earlier autotune of a batch of the same shape;
  * bq_batch_get_tune reports the current one (ms_per_step 0). */
 int bq_batch_autotune(bq_batch* b, int32_t steps_per_trial, bq_tune* out);

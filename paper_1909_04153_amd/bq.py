@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbq.so")
 
 WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
-ABI_VERSION = 3
+ABI_VERSION = 4
 FP64, FP32 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDTMIN, ESTATE, EDONE = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENONFINITE: "ENONFINITE",
@@ -57,7 +57,7 @@ class Info(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("reduce_block", ctypes.c_int32),
-                ("swizzle", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+                ("swizzle", ctypes.c_int32), ("reduce_segments", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -331,7 +331,8 @@ class Batch:
         return t.as_dict()
 
     def set_tune(self, tune: dict):
-        t = Tune(int(tune["lanes"]), int(tune["graph_steps"]), int(tune["reduce_block"]), int(tune["swizzle"]), 0.0)
+        t = Tune(int(tune["lanes"]), int(tune["graph_steps"]), int(tune["reduce_block"]), int(tune["swizzle"]),
+                 int(tune.get("reduce_segments", 1)), 0.0)
         _check(load().bq_batch_set_tune(self._h, ctypes.byref(t)))
 
     def shape_key(self) -> str:

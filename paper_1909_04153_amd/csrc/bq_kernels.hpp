@@ -528,7 +528,7 @@ __device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP
   __shared__ double red[4][64];
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   const int nw = D.n_waves;
-  for (int m = tid; m < nw; m += 64) {
+  for (int m = tid; tid < 64 && m < nw; m += 64) {
     const double amp = D.wave[m], om = D.wave[nw + m], ph = D.wave[2 * nw + m], k = D.wave[3 * nw + m];
     const double s1 = r * amp * sin(om * t + 0.5 * k * D.dx_d + ph);
     const double s2 = r * amp * sin(om * t + 1.5 * k * D.dx_d + ph);
@@ -537,7 +537,9 @@ __device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP
     a2 += s2;
     a3 += om / k * s2;
   }
-  red[0][tid] = a0; red[1][tid] = a1; red[2][tid] = a2; red[3][tid] = a3;
+  if (tid < 64) {
+    red[0][tid] = a0; red[1][tid] = a1; red[2][tid] = a2; red[3][tid] = a3;
+  }
   __syncthreads();
   if (tid == 0) {
     double s[4] = {0, 0, 0, 0};
@@ -548,8 +550,11 @@ __device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP
   __syncthreads();
 }
 
+// one block of DT_THREADS per domain
+constexpr int DT_THREADS = 256;
+
 template <typename T>
-__global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, double dt_prescribed) {
+__global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__ doms, double dt_prescribed) {
   const DomDev<T>& D = doms[blockIdx.x];
   DevState* st = D.st;
   __shared__ int go;
@@ -558,10 +563,28 @@ __global__ void __launch_bounds__(64) k_dt(const DomDev<T>* __restrict__ doms, d
   // (a NaN there is already +inf) and the initial state's value
   double tmax = 0.0;
   {
+    // eight independent loads in flight per lane (a large domain has
+    // thousands of tiles; one dependent load at a time would serialise them)
     const int ntiles = D.tiles_x * D.tiles_y;
     const gp<const double> sp = gbl((const double*)D.smax_tile);
-    for (int k = threadIdx.x; k < ntiles; k += 64) tmax = fmax(tmax, sp[k]);
+    double tm[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tm[u] = 0.0;
+    for (int k0 = threadIdx.x; k0 < ntiles; k0 += 8 * DT_THREADS) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = k0 + DT_THREADS * u;
+        tm[u] = fmax(tm[u], k < ntiles ? sp[k] : 0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tmax = fmax(tmax, tm[u]);
     for (int o = 32; o > 0; o >>= 1) tmax = fmax(tmax, __shfl_xor(tmax, o, 64));
+    __shared__ double wmax[DT_THREADS / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = tmax;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < DT_THREADS / 64; ++w) tmax = fmax(tmax, wmax[w]);
   }
   if (threadIdx.x == 0) {
     commit(st);
@@ -1218,6 +1241,161 @@ __global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ d
   if (pass == 1 && !D.corrector) return;      // the corrector pass
   if (l < D.ny) reduce_line<T>(D.cx, D.ny, l, gbl((const T*)D.chx), gbl((const T*)D.rsx), gbl(D.ifx));
   else reduce_line<T>(D.cy, D.nx, l - D.ny, gbl((const T*)D.chy), gbl((const T*)D.rsy), gbl(D.ify));
+}
+
+// The same recurrences with each line's chunks cut into NSEG segments, one
+// wave per segment (a block holds 64 lines x NSEG segments).  Both sweeps are
+// affine recurrences (alpha_c = A_c alpha_{c-1} + B_c forward, with
+// A_c = m1 + m2 k2 and B_c = xh_e + m2 k1 xh_s; X_s(c) = tau_c X_s(c+1) +
+// sigma_c backward), so each segment first composes its maps, the segments
+// exchange them through LDS, and each then runs its part with the right
+// incoming value: twice the arithmetic, a quarter of the serial length.  The
+// results equal the serial sweep's up to rounding (the composition
+// reassociates the products).
+constexpr int NSEG = 4;
+
+template <typename T>
+__device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg, bool active, const gp<const T> ch,
+                                                const gp<const T> rs, const gp<T> itf, T (*xa)[64], T (*xb)[64],
+                                                int lane) {
+  // the loads of RB chunks are issued together ahead of their serial steps
+  constexpr int RB = 8;
+  const size_t CL = (size_t)C * L;
+  const int c0 = (int)(((long long)seg * C) / NSEG), c1 = (int)(((long long)(seg + 1) * C) / NSEG);
+  const int n = active ? c1 - c0 : 0;
+  // forward, pass 1: the segment's composite map alpha_out = A alpha_in + B
+  T A = T(1), B = T(0);
+  for (int b0 = 0; b0 < n; b0 += RB) {
+    T k1[RB], k2[RB], m1[RB], m2[RB], xs[RB], xe[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const size_t o = (size_t)(c0 + min(b0 + k, n - 1)) * L + line;
+      k1[k] = rs[o];
+      k2[k] = rs[CL + o];
+      m1[k] = rs[2 * CL + o];
+      m2[k] = rs[3 * CL + o];
+      xs[k] = ch[o];
+      xe[k] = ch[CL + o];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (b0 + k < n) {
+        const T Ac = m1[k] + m2[k] * k2[k], Bc = xe[k] + m2[k] * k1[k] * xs[k];
+        A = Ac * A;
+        B = Ac * B + Bc;
+      }
+  }
+  xa[seg][lane] = A;
+  xb[seg][lane] = B;
+  __syncthreads();
+  T al = T(0);
+  for (int k = 0; k < seg; ++k) al = xa[k][lane] * al + xb[k][lane];
+  __syncthreads();
+  // forward, pass 2: sigma_c, alpha_c of the segment's chunks
+  for (int b0 = 0; b0 < n; b0 += RB) {
+    T r0[RB], r1[RB], r2[RB], r3[RB], xs[RB], xe[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const size_t o = (size_t)(c0 + min(b0 + k, n - 1)) * L + line;
+      r0[k] = rs[o];
+      r1[k] = rs[CL + o];
+      r2[k] = rs[2 * CL + o];
+      r3[k] = rs[3 * CL + o];
+      xs[k] = ch[o];
+      xe[k] = ch[CL + o];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (b0 + k < n) {
+        const size_t o = (size_t)(c0 + b0 + k) * L + line;
+        const T sg = r0[k] * xs[k] + r1[k] * al;
+        al = xe[k] + r2[k] * al + r3[k] * sg;
+        itf[o] = sg;
+        itf[CL + o] = al;
+      }
+  }
+  // backward, pass 1: X_s(c0) = R X_s(c1) + S over the segment
+  T R = T(1), Sv = T(0);
+  for (int b1 = 0; b1 < n; b1 += RB) {
+    T tau[RB], sg[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const size_t o = (size_t)(c1 - 1 - min(b1 + k, n - 1)) * L + line;
+      tau[k] = rs[4 * CL + o];
+      sg[k] = itf[o];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (b1 + k < n) {
+        R = tau[k] * R;
+        Sv = tau[k] * Sv + sg[k];
+      }
+  }
+  xa[seg][lane] = R;
+  xb[seg][lane] = Sv;
+  __syncthreads();
+  T xs_next = T(0);
+  for (int k = NSEG - 1; k > seg; --k) xs_next = xa[k][lane] * xs_next + xb[k][lane];
+  // backward, pass 2; the left-neighbour value of the next segment's first
+  // chunk is written after the barrier (that segment reads the slot first)
+  T held = T(0);
+  bool hold = false;
+  for (int b1 = 0; b1 < n; b1 += RB) {
+    T sg[RB], a[RB], r4[RB], r5[RB];
+#pragma unroll
+    for (int k = 0; k < RB; ++k) {
+      const size_t o = (size_t)(c1 - 1 - min(b1 + k, n - 1)) * L + line;
+      sg[k] = itf[o];
+      a[k] = itf[CL + o];
+      r4[k] = rs[4 * CL + o];
+      r5[k] = rs[5 * CL + o];
+    }
+#pragma unroll
+    for (int k = 0; k < RB; ++k)
+      if (b1 + k < n) {
+        const int c = c1 - 1 - (b1 + k);
+        const size_t o = (size_t)c * L + line;
+        const T Xs = sg[k] + r4[k] * xs_next;
+        const T Xe = a[k] + r5[k] * xs_next;
+        itf[CL + o] = xs_next;                    // right neighbour of chunk c
+        if (c + 1 < C) {
+          if (c == c1 - 1) {
+            held = Xe;
+            hold = true;
+          } else {
+            itf[o + L] = Xe;                      // left neighbour of chunk c + 1
+          }
+        }
+        xs_next = Xs;
+      }
+  }
+  __syncthreads();
+  if (hold) itf[(size_t)c1 * L + line] = held;
+  if (active && seg == 0) itf[line] = T(0);       // chunk 0 has no left neighbour
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64 * NSEG) k_reduced_seg(const DomDev<T>* __restrict__ doms,
+                                                          const int* __restrict__ line_map, int nd, int lines,
+                                                          int pass) {
+  __shared__ T xa[NSEG][64], xb[NSEG][64];
+  const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
+  const int gid = blockIdx.x * 64 + lane;
+  // every thread reaches the barriers; inactive ones carry identity maps
+  bool active = gid < lines;
+  int dom = 0, l = 0;
+  if (active) {
+    locate(line_map, nd, gid, dom, l);
+    const DomDev<T>& D = doms[dom];
+    active = !D.st->halt && !(pass == 1 && !D.corrector);
+  }
+  // one call site: the barriers inside must be met by every wave once, and
+  // the lanes of a wave may hold x-lines and y-lines
+  const DomDev<T>& D = doms[dom];
+  const bool xl = l < D.ny;
+  reduce_line_seg<T>(xl ? D.cx : D.cy, xl ? D.ny : D.nx, xl ? l : l - D.ny, seg, active,
+                     gbl((const T*)(xl ? D.chx : D.chy)), gbl((const T*)(xl ? D.rsx : D.rsy)),
+                     gbl(xl ? D.ifx : D.ify), xa, xb, lane);
 }
 
 // ---------------------------------------------------------------------------

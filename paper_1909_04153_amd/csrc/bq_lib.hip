@@ -371,6 +371,7 @@ struct Launch {
   // kernel, XCD-aware tile order of the stencil kernel
   int rblock = 256;
   int swizzle = 1;
+  int segs = 1;                 // 1: one thread per line; NSEG: segmented sweeps
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;          // steps per replay (0 = none)
   int graph_built = 0;          // steps captured in `graph`
@@ -413,7 +414,7 @@ struct bq_batch {
   hipStream_t lane[2] = {nullptr, nullptr};
   hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   int graph_steps = 16;
-  int rblock = 256, swizzle = 1;  // schedule copied into the launches
+  int rblock = 256, swizzle = 1, segs = 1;  // schedule copied into the launches
 };
 
 // layout of a domain in its workspace
@@ -696,19 +697,28 @@ static int set_state_t(bq_domain* d, const double* eta, const double* P, const d
 // ---------------------------------------------------------------------------
 
 template <typename T>
+static void launch_reduced(const Launch& L, hipStream_t s, int pass) {
+  const DomDev<T>* tab = (const DomDev<T>*)L.table;
+  if (L.segs > 1)
+    k_reduced_seg<T><<<cdiv(L.lines, 64), 64 * NSEG, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
+  else
+    k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
+}
+
+template <typename T>
 static void enqueue_step(const Launch& L, hipStream_t s, double dt_prescribed) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
-  k_dt<T><<<L.nd, 64, 0, s>>>(tab, dt_prescribed);
+  k_dt<T><<<L.nd, DT_THREADS, 0, s>>>(tab, dt_prescribed);
   k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
-  k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
+  launch_reduced<T>(L, s, 0);
   if (!L.any_pc) {
     k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
   } else {
     k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     // corrector pass of the domains that run it (the others return at once)
     k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
-    k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
+    launch_reduced<T>(L, s, 1);
     k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
   }
 }
@@ -759,11 +769,11 @@ static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
   const int last = L.any_pc ? 7 : 4;
   for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
     if (hipEventRecord(ev[0], s) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventRecord"); break; }
-    k_dt<T><<<L.nd, 64, 0, s>>>(tab, 0.0);
+    k_dt<T><<<L.nd, DT_THREADS, 0, s>>>(tab, 0.0);
     (void)hipEventRecord(ev[1], s);
     k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
     (void)hipEventRecord(ev[2], s);
-    k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 0);
+    launch_reduced<T>(L, s, 0);
     (void)hipEventRecord(ev[3], s);
     if (L.any_pc) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
     else k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
@@ -771,7 +781,7 @@ static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
     if (L.any_pc) {
       k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
       (void)hipEventRecord(ev[5], s);
-      k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, 1);
+      launch_reduced<T>(L, s, 1);
       (void)hipEventRecord(ev[6], s);
       k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
       (void)hipEventRecord(ev[7], s);
@@ -987,6 +997,7 @@ static int batch_build_t(bq_batch* b) {
   if (rc) return rc;
   b->L.rblock = b->rblock;
   b->L.swizzle = b->swizzle;
+  b->L.segs = b->segs;
   if (b->lanes == 2) {
     rc = fill_launch<T>(b->G[0], m + s0, part[0], b->stream);
     if (!rc) rc = fill_launch<T>(b->G[1], m + s0 + s1, part[1], b->stream);
@@ -994,6 +1005,7 @@ static int batch_build_t(bq_batch* b) {
     for (int l = 0; l < 2; ++l) {
       b->G[l].rblock = b->rblock;
       b->G[l].swizzle = b->swizzle;
+      b->G[l].segs = b->segs;
     }
     for (int l = 0; l < 2; ++l)
       if (!b->lane[l]) HIPCHK(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
@@ -1053,7 +1065,7 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
     for (int l = 0; l < 2; ++l) (void)hipEventRecord(ev[l][0], ss[l]);
     for (int l = 0; l < 2; ++l) {
       const Launch& L = b->G[l];
-      k_dt<T><<<L.nd, 64, 0, ss[l]>>>((const DomDev<T>*)L.table, 0.0);
+      k_dt<T><<<L.nd, DT_THREADS, 0, ss[l]>>>((const DomDev<T>*)L.table, 0.0);
       (void)hipEventRecord(ev[l][1], ss[l]);
     }
     for (int pass = 0; pass < (last == 7 ? 2 : 1); ++pass) {
@@ -1067,8 +1079,7 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
       }
       for (int l = 0; l < 2; ++l) {
         const Launch& L = b->G[l];
-        k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, ss[l]>>>((const DomDev<T>*)L.table, L.line_map, L.nd,
-                                                            L.lines, pass);
+        launch_reduced<T>(L, ss[l], pass);
         (void)hipEventRecord(ev[l][e0 + 2], ss[l]);
       }
       for (int l = 0; l < 2; ++l) {
@@ -1111,13 +1122,15 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
 // schedule autotuner
 // ---------------------------------------------------------------------------
 
-static void apply_schedule(bq_batch* b, int rblock, int swizzle) {
+static void apply_schedule(bq_batch* b, int rblock, int swizzle, int segs) {
   b->rblock = rblock;
   b->swizzle = swizzle;
+  b->segs = segs;
   Launch* ls[3] = {&b->L, &b->G[0], &b->G[1]};
   for (Launch* L : ls) {
     L->rblock = rblock;
     L->swizzle = swizzle;
+    L->segs = segs;
     // graphs hold the launch parameters they were captured with
     if (L->graph) (void)hipGraphExecDestroy(L->graph);
     L->graph = nullptr;
@@ -1130,13 +1143,15 @@ static int set_tune(bq_batch* b, const bq_tune* t) {
   if (t->reduce_block != 64 && t->reduce_block != 128 && t->reduce_block != 256)
     return fail(BQ_EINVAL, "reduce_block must be 64, 128 or 256");
   if (t->swizzle != 0 && t->swizzle != 1) return fail(BQ_EINVAL, "swizzle must be 0 or 1");
+  if (t->reduce_segments != 1 && t->reduce_segments != NSEG)
+    return fail(BQ_EINVAL, "reduce_segments must be 1 or %d", NSEG);
   if (t->lanes != b->lanes_req) {
     b->lanes_req = t->lanes;
     const int rc = DISPATCH(b->precision, batch_build_t, b);
     if (rc) return rc;
   }
   b->graph_steps = t->graph_steps;
-  apply_schedule(b, t->reduce_block, t->swizzle);
+  apply_schedule(b, t->reduce_block, t->swizzle, t->reduce_segments);
   return BQ_OK;
 }
 
@@ -1151,8 +1166,10 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   // HBM traffic by a third (measured) while its effect on a whole step is
   // below the trials' timing noise, so a search would pick it by chance.
   for (int lanes = 1; lanes <= max_lanes; ++lanes)
-    for (int graph : {4, 16})
-      for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 0.0});
+    for (int graph : {4, 16}) {
+      for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 1, 0.0});
+      cands.push_back(bq_tune{lanes, graph, 64 * NSEG, 1, NSEG, 0.0});
+    }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
@@ -1182,8 +1199,8 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   if (rc) return rc;
   if (getenv("BQ_TUNE_LOG"))
     for (const bq_tune& c : cands)
-      fprintf(stderr, "bq tune: lanes %d graph %d reduce_block %d swizzle %d: %.4f ms/step\n", c.lanes,
-              c.graph_steps, c.reduce_block, c.swizzle, c.ms_per_step);
+      fprintf(stderr, "bq tune: lanes %d graph %d reduce_block %d segments %d swizzle %d: %.4f ms/step\n",
+              c.lanes, c.graph_steps, c.reduce_block, c.reduce_segments, c.swizzle, c.ms_per_step);
   int best = 0;
   for (size_t k = 1; k < cands.size(); ++k)
     if (cands[k].ms_per_step < cands[best].ms_per_step) best = (int)k;
@@ -1394,7 +1411,7 @@ int bq_batch_set_tune(bq_batch* b, const bq_tune* t) {
 
 int bq_batch_get_tune(const bq_batch* b, bq_tune* out) {
   if (!b || !out) return fail(BQ_EINVAL, "NULL argument");
-  *out = bq_tune{b->lanes, b->graph_steps, b->rblock, b->swizzle, 0.0};
+  *out = bq_tune{b->lanes, b->graph_steps, b->rblock, b->swizzle, b->segs, 0.0};
   return BQ_OK;
 }
 
