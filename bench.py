@@ -242,8 +242,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.0,
-                    help="also run the request loop for about this long and report p50/p99")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="run the request loop for about this long and report p50/p99 (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times), for counter calibration")
     args = ap.parse_args()
@@ -351,12 +351,13 @@ def main():
         fp64 = {}
         for wl in ("beach1024x256_fp64", "solitary200x20"):
             sp, dt_ = workload(wl)
-            ds, g = make_group(bq, sp, dt_)
+            ds, g = make_group(bq, sp, dt_, batch=True)
+            sched = tuned(g, args)
             c = sum(s["params"]["nx"] * s["params"]["ny"] for s in sp)
             n = max(20, args.steps)
             e = timed(torch, g, n, args.warmup)
             fp64[wl] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / n * 1e3,
-                        "cells": c, "steps": n}
+                        "cells": c, "steps": n, "schedule": sched}
             del g, ds
         out["fp64_plain"] = fp64
     if args.serve_seconds > 0:
