@@ -233,7 +233,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="batch64")
     ap.add_argument("--profile-steps", type=int, default=20)
-    ap.add_argument("--lanes", type=int, default=2, choices=(1, 2),
+    ap.add_argument("--lanes", type=int, default=2, choices=(1, 2, 3, 4),
                     help="launch lanes of a batch (two groups on two streams, or one) with --no-autotune")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default batch schedule instead of running the library's autotuner")
@@ -287,15 +287,15 @@ def main():
             raise SystemExit(f"domain {d.params} latched status {st}")
     # Per-kernel durations with HIP events on the launch stream (plain
     # launches).  The roofline is taken with one lane, each kernel alone on
-    # the GPU and one launch covering every cell; with two lanes the kernels
-    # of the two groups share the GPU, so their event times are also given.
+    # the GPU and one launch covering every cell; with several lanes the
+    # kernels of the groups share the GPU, so their event times are also given.
     kms2 = None
-    if lanes == 2:
+    if lanes > 1:
         kms2 = group.profile(args.profile_steps)
         group.set_lanes(1)
     kms = group.profile(args.profile_steps)
-    if lanes == 2:
-        group.set_lanes(2)
+    if lanes > 1:
+        group.set_lanes(lanes)
     dom_k = max(kms, key=kms.get)
     wsize = 4 if dtype == "fp32" else 8
     cells_launch = cells
@@ -313,7 +313,7 @@ def main():
            "effective_hbm_frac": WORDS_STEP * wsize * cells * args.steps / el / 1e9 / HBM_PEAK_GBS,
            "kernels_ms": kms, "roofline": roof}
     if kms2 is not None:
-        out["kernels_ms_two_lane"] = kms2
+        out["kernels_ms_lanes"] = kms2
     del group, doms
     torch.cuda.synchronize()
     out["copy_gbs"] = copy_bandwidth(torch)

@@ -191,19 +191,18 @@ int bq_batch_step(bq_batch* b, int32_t n_steps);
 int bq_batch_sync(bq_batch* b);
 int bq_batch_free(bq_batch* b);
 
-/* Launch lanes of a batch (1 or 2; default 2).  With 2 lanes the members are
- * split into two groups of about equal cell count and each group is advanced
- * on its own stream; the batch creates both streams itself, one after the
- * other, so the runtime gives them different hardware queues.  The lanes
- * start after the work queued on the batch's stream and the batch's stream
- * waits for both (events at the start and end of every bq_batch_step), so
- * the caller sees one stream.  One group's stencil/update kernel
- * (arithmetic bound) then runs beside the other group's line-coupling and
- * finalize kernels (latency and bandwidth bound).  Each domain's arithmetic
- * is the same for any lane count, so results are bitwise identical.
- * Changing the lane count waits for the batch's queued work.
- * bq_batch_lanes returns the lanes in use (1 when the batch has one
- * member). */
+/* Launch lanes of a batch (1 to 4; default 2, at most the member count).
+ * With several lanes the members are split into groups of about equal cell
+ * count and each group is advanced on its own stream; the batch creates the
+ * streams itself, one after the other, so the runtime gives them different
+ * hardware queues.  The lanes start after the work queued on the batch's
+ * stream and the batch's stream waits for all of them (events at the start
+ * and end of every bq_batch_step), so the caller sees one stream.  One
+ * group's stencil/update kernel (arithmetic bound) then runs beside another
+ * group's line-coupling and finalize kernels (latency and bandwidth bound).
+ * Each domain's arithmetic is the same for any lane count, so results are
+ * bitwise identical.  Changing the lane count waits for the batch's queued
+ * work.  bq_batch_lanes returns the lanes in use. */
 int bq_batch_set_lanes(bq_batch* b, int32_t lanes);
 int bq_batch_lanes(const bq_batch* b);
 
@@ -235,7 +234,7 @@ typedef struct bq_tune {
 } bq_tune;
 
 /* Autotuner: times steps_per_trial steps of the batch under each candidate
- * schedule (lanes 1-2 x graph replays of 4 or 16 steps x line coupling by
+ * schedule (lanes 1-4 x graph replays of 4 or 16 steps x line coupling by
  * one thread per line in blocks of 64 or 256, or segmented; XCD-aware tile
  * order on) twice, in forward then reverse order,
  * keeps the one of the lowest mean time and returns it.  The

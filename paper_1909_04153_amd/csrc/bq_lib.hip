@@ -394,25 +394,27 @@ struct bq_domain {
   int graph_steps = 16;
 };
 
+constexpr int MAX_LANES = 4;     // launch lanes of a batch (hardware queues per process)
+
 struct bq_batch {
   std::vector<bq_domain*> doms;
   int precision = BQ_FP64;
   hipStream_t stream = nullptr;
-  void* mem = nullptr;          // tables + prefixes of L, G[0], G[1]
+  void* mem = nullptr;          // tables of L and of the lane groups G[]
   size_t mem_bytes = 0;
   Launch L;                     // all members, one lane
-  // Two lanes: the members split into two groups of about equal cell count,
-  // each advanced on a stream of its own, so one group's stencil kernel
-  // (arithmetic-bound) runs beside the other group's line-coupling and
-  // finalize kernels (bandwidth- and latency-bound).  The batch creates both
+  // Several lanes: the members split into groups of about equal cell
+  // count, each advanced on a stream of its own, so one group's stencil
+  // kernel (arithmetic-bound) runs beside another group's line-coupling and
+  // finalize kernels (bandwidth- and latency-bound).  The batch creates the
   // lane streams itself, one right after the other, so the runtime puts them
   // on different hardware queues (two streams sharing a queue run one after
-  // the other, and the lanes would not overlap).
-  Launch G[2];
-  int lanes_req = 2;            // requested lanes (1 or 2)
-  int lanes = 1;                // lanes in use (1 if there is one member)
-  hipStream_t lane[2] = {nullptr, nullptr};
-  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
+  // the other, and their lanes would not overlap).
+  Launch G[MAX_LANES];
+  int lanes_req = 2;            // requested lanes (1 .. MAX_LANES)
+  int lanes = 1;                // lanes in use (at most the member count)
+  hipStream_t lane[MAX_LANES] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[MAX_LANES] = {};
   int graph_steps = 16;
   int rblock = 256, swizzle = 1, segs = 1;  // schedule copied into the launches
 };
@@ -964,28 +966,31 @@ static int batch_build_t(bq_batch* b) {
   HIPCHK(hipStreamSynchronize(b->stream));
   for (hipStream_t ls : b->lane)
     if (ls) HIPCHK(hipStreamSynchronize(ls));
-  b->lanes = (b->lanes_req == 2 && nd >= 2) ? 2 : 1;
-  std::vector<bq_domain*> part[2];
-  if (b->lanes == 2) {
-    // greedy split by cell count, largest first; members keep their order
+  b->lanes = b->lanes_req < nd ? b->lanes_req : nd;
+  const int nl = b->lanes;
+  std::vector<bq_domain*> part[MAX_LANES];
+  if (nl > 1) {
+    // greedy split by cell count, largest first, each to the lightest
+    // group; members keep their order within a group
     std::vector<int> ord(nd);
     for (int k = 0; k < nd; ++k) ord[k] = k;
     std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
       return (long long)b->doms[x]->nx * b->doms[x]->ny > (long long)b->doms[y]->nx * b->doms[y]->ny;
     });
     std::vector<int> grp(nd, 0);
-    long long cells[2] = {0, 0};
+    long long cells[MAX_LANES] = {};
     for (int k : ord) {
-      const int gsel = cells[1] < cells[0] ? 1 : 0;
+      int gsel = 0;
+      for (int g = 1; g < nl; ++g)
+        if (cells[g] < cells[gsel]) gsel = g;
       grp[k] = gsel;
       cells[gsel] += (long long)b->doms[k]->nx * b->doms[k]->ny;
     }
     for (int k = 0; k < nd; ++k) part[grp[k]].push_back(b->doms[k]);
   }
   const size_t s0 = launch_bytes<T>(b->doms);
-  const size_t s1 = b->lanes == 2 ? launch_bytes<T>(part[0]) : 0;
-  const size_t s2 = b->lanes == 2 ? launch_bytes<T>(part[1]) : 0;
-  const size_t need = s0 + s1 + s2;
+  size_t sg[MAX_LANES] = {}, need = s0;
+  for (int g = 0; g < nl && nl > 1; ++g) need += (sg[g] = launch_bytes<T>(part[g]));
   if (need > b->mem_bytes) {
     if (b->mem) HIPCHK(hipFree(b->mem));
     b->mem = nullptr;
@@ -998,38 +1003,38 @@ static int batch_build_t(bq_batch* b) {
   b->L.rblock = b->rblock;
   b->L.swizzle = b->swizzle;
   b->L.segs = b->segs;
-  if (b->lanes == 2) {
-    rc = fill_launch<T>(b->G[0], m + s0, part[0], b->stream);
-    if (!rc) rc = fill_launch<T>(b->G[1], m + s0 + s1, part[1], b->stream);
-    if (rc) return rc;
-    for (int l = 0; l < 2; ++l) {
-      b->G[l].rblock = b->rblock;
-      b->G[l].swizzle = b->swizzle;
-      b->G[l].segs = b->segs;
+  for (int g = 0; g < MAX_LANES; ++g) drop_graph<T>(b->G[g]);
+  if (nl > 1) {
+    size_t off = s0;
+    for (int g = 0; g < nl && !rc; ++g) {
+      rc = fill_launch<T>(b->G[g], m + off, part[g], b->stream);
+      off += sg[g];
+      b->G[g].rblock = b->rblock;
+      b->G[g].swizzle = b->swizzle;
+      b->G[g].segs = b->segs;
     }
-    for (int l = 0; l < 2; ++l)
+    if (rc) return rc;
+    // the lane streams are created together, one after the other
+    for (int l = 0; l < MAX_LANES; ++l)
       if (!b->lane[l]) HIPCHK(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
     if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
-    for (int l = 0; l < 2; ++l)
+    for (int l = 0; l < MAX_LANES; ++l)
       if (!b->ev_join[l]) HIPCHK(hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming));
-  } else {
-    drop_graph<T>(b->G[0]);
-    drop_graph<T>(b->G[1]);
   }
   HIPCHK(hipStreamSynchronize(b->stream));
   return BQ_OK;
 }
 
 // the lanes start after the work queued so far on the batch's stream, and
-// the batch's stream continues only after both lanes' work
+// the batch's stream continues only after every lane's work
 static int fork_lanes(bq_batch* b) {
   HIPCHK(hipEventRecord(b->ev_fork, b->stream));
-  for (int l = 0; l < 2; ++l) HIPCHK(hipStreamWaitEvent(b->lane[l], b->ev_fork, 0));
+  for (int l = 0; l < b->lanes; ++l) HIPCHK(hipStreamWaitEvent(b->lane[l], b->ev_fork, 0));
   return BQ_OK;
 }
 
 static int join_lanes(bq_batch* b) {
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < b->lanes; ++l) {
     HIPCHK(hipEventRecord(b->ev_join[l], b->lane[l]));
     HIPCHK(hipStreamWaitEvent(b->stream, b->ev_join[l], 0));
   }
@@ -1041,48 +1046,50 @@ static int batch_run_t(bq_batch* b, int n_steps) {
   if (b->lanes == 1) return run_steps<T>(b->L, b->stream, n_steps, b->graph_steps);
   if (n_steps <= 0) return BQ_OK;
   int rc = fork_lanes(b);
-  if (!rc) rc = run_steps<T>(b->G[0], b->lane[0], n_steps, b->graph_steps);
-  if (!rc) rc = run_steps<T>(b->G[1], b->lane[1], n_steps, b->graph_steps);
+  for (int l = 0; l < b->lanes && !rc; ++l) rc = run_steps<T>(b->G[l], b->lane[l], n_steps, b->graph_steps);
   const int rj = join_lanes(b);
   return rc ? rc : rj;
 }
 
-// Kernel timing with both lanes running: hipEvents around every kernel on
+// Kernel timing with all lanes running: hipEvents around every kernel on
 // its own lane's stream; ms_out[k] is the mean duration of one launch of
 // kernel k (a launch covers one group).
 template <typename T>
 static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   if (b->lanes == 1) return profile_t<T>(b->L, b->stream, n_steps, ms_out);
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
-  hipStream_t ss[2] = {b->lane[0], b->lane[1]};
-  hipEvent_t ev[2][8];
-  for (int l = 0; l < 2; ++l)
+  const int nl = b->lanes;
+  hipStream_t* ss = b->lane;
+  hipEvent_t ev[MAX_LANES][8];
+  for (int l = 0; l < nl; ++l)
     for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&ev[l][k]));
   double acc[4] = {0, 0, 0, 0};
-  const int last = (b->G[0].any_pc || b->G[1].any_pc) ? 7 : 4;
+  bool pc = false;
+  for (int l = 0; l < nl; ++l) pc |= b->G[l].any_pc != 0;
+  const int last = pc ? 7 : 4;
   int rc = fork_lanes(b);
   for (int it = 0; it < n_steps && rc == BQ_OK; ++it) {
-    for (int l = 0; l < 2; ++l) (void)hipEventRecord(ev[l][0], ss[l]);
-    for (int l = 0; l < 2; ++l) {
+    for (int l = 0; l < nl; ++l) (void)hipEventRecord(ev[l][0], ss[l]);
+    for (int l = 0; l < nl; ++l) {
       const Launch& L = b->G[l];
       k_dt<T><<<L.nd, DT_THREADS, 0, ss[l]>>>((const DomDev<T>*)L.table, 0.0);
       (void)hipEventRecord(ev[l][1], ss[l]);
     }
     for (int pass = 0; pass < (last == 7 ? 2 : 1); ++pass) {
       const int e0 = pass == 0 ? 1 : 4;
-      for (int l = 0; l < 2; ++l) {
+      for (int l = 0; l < nl; ++l) {
         const Launch& L = b->G[l];
         const DomDev<T>* tb0 = (const DomDev<T>*)L.table;
         if (pass == 0) k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, ss[l]>>>(tb0, L.tile_map, L.nd, L.swizzle);
         else k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, ss[l]>>>(tb0, L.tile_map, L.nd, L.swizzle);
         (void)hipEventRecord(ev[l][e0 + 1], ss[l]);
       }
-      for (int l = 0; l < 2; ++l) {
+      for (int l = 0; l < nl; ++l) {
         const Launch& L = b->G[l];
         launch_reduced<T>(L, ss[l], pass);
         (void)hipEventRecord(ev[l][e0 + 2], ss[l]);
       }
-      for (int l = 0; l < 2; ++l) {
+      for (int l = 0; l < nl; ++l) {
         const Launch& L = b->G[l];
         const DomDev<T>* tb = (const DomDev<T>*)L.table;
         if (pass == 1) k_final<T, TY, MX, 2><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
@@ -1091,18 +1098,18 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
         (void)hipEventRecord(ev[l][e0 + 3], ss[l]);
       }
     }
-    for (int l = 0; l < 2 && rc == BQ_OK; ++l)
+    for (int l = 0; l < nl && rc == BQ_OK; ++l)
       if (hipEventSynchronize(ev[l][last]) != hipSuccess) rc = fail(BQ_EDEVICE, "hipEventSynchronize");
-    for (int l = 0; l < 2 && rc == BQ_OK; ++l)
+    for (int l = 0; l < nl && rc == BQ_OK; ++l)
       for (int k = 0; k < last; ++k) {
         float ms = 0.f;
         (void)hipEventElapsedTime(&ms, ev[l][k], ev[l][k + 1]);
-        acc[k < 4 ? k : k - 3] += 0.5 * ms;
+        acc[k < 4 ? k : k - 3] += ms / nl;
       }
   }
-  for (int l = 0; l < 2; ++l) enqueue_commit<T>(b->G[l], ss[l]);
+  for (int l = 0; l < nl; ++l) enqueue_commit<T>(b->G[l], ss[l]);
   const int rj = join_lanes(b);
-  for (int l = 0; l < 2; ++l)
+  for (int l = 0; l < nl; ++l)
     for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[l][k]);
   if (rc) return rc;
   if (rj) return rj;
@@ -1126,7 +1133,8 @@ static void apply_schedule(bq_batch* b, int rblock, int swizzle, int segs) {
   b->rblock = rblock;
   b->swizzle = swizzle;
   b->segs = segs;
-  Launch* ls[3] = {&b->L, &b->G[0], &b->G[1]};
+  Launch* ls[1 + MAX_LANES] = {&b->L};
+  for (int g = 0; g < MAX_LANES; ++g) ls[1 + g] = &b->G[g];
   for (Launch* L : ls) {
     L->rblock = rblock;
     L->swizzle = swizzle;
@@ -1138,7 +1146,7 @@ static void apply_schedule(bq_batch* b, int rblock, int swizzle, int segs) {
 }
 
 static int set_tune(bq_batch* b, const bq_tune* t) {
-  if (t->lanes != 1 && t->lanes != 2) return fail(BQ_EINVAL, "lanes must be 1 or 2");
+  if (t->lanes < 1 || t->lanes > MAX_LANES) return fail(BQ_EINVAL, "lanes must be 1 .. %d", MAX_LANES);
   if (t->graph_steps < 0) return fail(BQ_EINVAL, "graph_steps must be >= 0");
   if (t->reduce_block != 64 && t->reduce_block != 128 && t->reduce_block != 256)
     return fail(BQ_EINVAL, "reduce_block must be 64, 128 or 256");
@@ -1161,7 +1169,7 @@ static int set_tune(bq_batch* b, const bq_tune* t) {
 template <typename T>
 static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   std::vector<bq_tune> cands;
-  const int max_lanes = b->doms.size() >= 2 ? 2 : 1;
+  const int max_lanes = (int)b->doms.size() < MAX_LANES ? (int)b->doms.size() : MAX_LANES;
   // The XCD-aware tile order is not searched: it cuts the stencil kernel's
   // HBM traffic by a third (measured) while its effect on a whole step is
   // below the trials' timing noise, so a search would pick it by chance.
@@ -1385,7 +1393,7 @@ int bq_batch_sync(bq_batch* b) {
 }
 
 int bq_batch_set_lanes(bq_batch* b, int32_t lanes) {
-  if (!b || (lanes != 1 && lanes != 2)) return fail(BQ_EINVAL, "lanes must be 1 or 2");
+  if (!b || lanes < 1 || lanes > MAX_LANES) return fail(BQ_EINVAL, "lanes must be 1 .. %d", MAX_LANES);
   if (lanes == b->lanes_req) return BQ_OK;
   b->lanes_req = lanes;
   return DISPATCH(b->precision, batch_build_t, b);

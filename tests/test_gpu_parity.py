@@ -271,10 +271,10 @@ def test_batch_members_equal_solo_runs(bq):
         g.step(30)
         g.sync()
         solo.append([g.read(f) for f in FIELDS])
-    for lanes in (1, 2):
+    for lanes in (1, 2, 3, 4):
         doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
         b = bq.Batch(doms, lanes=lanes)
-        assert b.lanes == lanes
+        assert b.lanes == min(lanes, len(specs))
         b.step(30)
         b.sync()
         for d, ref in zip(doms, solo):
@@ -292,7 +292,7 @@ def test_two_lane_batch_profile_and_graphs_match_one_lane(bq):
              S.rip_beach_scaled(96, 72, cfl=0.125, fstar_order=1, t_end=0.0),
              S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.125, fstar_order=1)]
     out = {}
-    for lanes in (1, 2):
+    for lanes in (1, 2, 4):
         doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
         b = bq.Batch(doms, lanes=lanes)
         ms = b.profile(3)
@@ -303,9 +303,10 @@ def test_two_lane_batch_profile_and_graphs_match_one_lane(bq):
         out[lanes] = [[d.read(f) for f in FIELDS] for d in doms]
         assert all(d.sync().n == 12 for d in doms)
         b.close()
-    for x, y in zip(out[1], out[2]):
-        for a, c in zip(x, y):
-            assert np.array_equal(a, c)
+    for lanes in (2, 4):
+        for x, y in zip(out[1], out[lanes]):
+            for a, c in zip(x, y):
+                assert np.array_equal(a, c)
 
 
 def _compare_maps(o, g, spec, scale):
