@@ -125,3 +125,22 @@ def test_corrector_keeps_the_invariants():
     m0 = o.info().mass
     assert o.step(300) == 0
     assert abs(o.info().mass - m0) <= 1e-13 * m0
+
+
+def test_corrector_stabilises_the_quadratic_fstar_extrapolation_in_2d():
+    # reading of Eq. 43-46 in 2D: AB3 with the paper's quadratic F*
+    # extrapolation grows without bound on a 2D closed basin at any CFL
+    # number; with the corrector (exact F* change from level n to the
+    # predicted level) the same case stays bounded at twice the CFL number
+    def peak(corrector, cfl):
+        spec = S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=cfl, fstar_order=2, corrector=corrector)
+        o = OracleDomain(spec["params"], spec["depth_c"])
+        assert o.set_state(spec["eta"], spec["P"], spec["Q"]) == 0
+        rc = o.step(800)
+        return rc, float(np.nanmax(np.abs(o.read("eta"))))
+
+    amp0 = 0.05                      # the hump's initial height
+    rc, m = peak(1, 0.25)
+    assert rc == 0 and m < amp0
+    rc, m = peak(0, 0.125)
+    assert rc != 0 or m > 10 * amp0
