@@ -478,3 +478,27 @@ def test_fp64_parity_segmented_line_coupling(bq, case):
             assert e <= 1e-12, (case, (k + 1) * 10, f, e)
     print(f"{case} segmented FP64 worst rel L2 {worst:.2e}")
     b.close()
+
+
+def test_fp32_run_up_cases(bq):
+    # wet/dry run-up cases (small waves, no breaking) in FP32 against the
+    # FP64 oracle: eta within 1e-4, and the run-up record's inundated set
+    # equal up to a few cells at the threshold
+    cases = (("series_beach", lambda: S.series_beach(nx=150, ny=12, dx=0.05, x_toe=1.0), 1000),
+             ("conical_island", lambda: S.conical_island(nx=121, ny=121, dx=0.25), 500),
+             ("pc_conical_island", lambda: S.conical_island(nx=121, ny=121, dx=0.25, corrector=1, cfl=0.25,
+                                                            fstar_order=2), 300))
+    for name, make, steps in cases:
+        spec = make()
+        o, g = pair(bq, spec, bq.FP32)
+        assert o.step(steps) == 0
+        g.step(steps)
+        assert g.sync().status == 0
+        sc = scales(spec)
+        errs = {f: rel(g.read(f), o.read(f), sc[f]) for f in FIELDS}
+        ro, rg = o.read("runup"), g.read("runup")
+        mism = int(np.sum(np.isnan(ro) != np.isnan(rg)))
+        print(f"{name} FP32 after {steps} steps: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) +
+              f"; run-up cells differing in inundation {mism} of {int(np.sum(~np.isnan(ro)))}")
+        assert errs["eta"] <= 1e-4
+        assert mism <= max(2, int(0.002 * np.sum(~np.isnan(ro))))
