@@ -119,6 +119,27 @@ def timed(torch, group, steps, warmup):
     return time.perf_counter() - t0
 
 
+def single_line(bq, torch, args, wl, steps):
+    """one domain (as a batch of one, schedule tuned): throughput, and the
+    simulated seconds advanced per wall-clock second over the timed steps"""
+    sp, dt_ = workload(wl)
+    ds, g = make_group(bq, sp, dt_, batch=True)
+    sched = tuned(g, args)
+    c = sum(s_["params"]["nx"] * s_["params"]["ny"] for s_ in sp)
+    g.step(args.warmup)
+    g.wait()
+    t_a = ds[0].sync().t
+    e = timed(torch, g, steps, 0)
+    t_b = ds[0].sync().t
+    wsize = 4 if dt_ == "fp32" else 8
+    out = {"value": c * steps / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / steps * 1e3, "cells": c,
+           "steps": steps, "schedule": sched, "sim_s_per_wall_s": (t_b - t_a) / e,
+           "effective_hbm_frac": WORDS_STEP * wsize * c * steps / e / 1e9 / HBM_PEAK_GBS}
+    del g, ds
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_baseline(specs, budget_s):
     """the oracle as it stands, one host core, on a bounded sample"""
     from oracle.oracle import OracleDomain
@@ -322,18 +343,10 @@ def main():
         roof["traffic_gbs"] = tr / (kms[dom_k] * 1e-3) / 1e9
         roof["traffic_frac"] = roof["traffic_gbs"] / HBM_PEAK_GBS
     if not args.no_fp64:
-        # one C3-type domain (2048 x 2048 rip beach, FP32): the single-domain rate
-        sp, dt_ = workload("rip2048")
-        ds, g = make_group(bq, sp, dt_, batch=True)
-        sched_c3 = tuned(g, args)
-        c = sum(s["params"]["nx"] * s["params"]["ny"] for s in sp)
-        n = max(20, args.steps // 2)
-        e = timed(torch, g, n, args.warmup)
-        out["fp32_single_c3"] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / n * 1e3,
-                                 "cells": c, "steps": n, "schedule": sched_c3,
-                                 "effective_hbm_frac": WORDS_STEP * 4 * c * n / e / 1e9 / HBM_PEAK_GBS}
-        del g, ds
-        torch.cuda.synchronize()
+        # single domains in FP32: C3 (2048 x 2048 rip beach) and C2 (1024 x
+        # 256 beach)
+        out["fp32_single_c3"] = single_line(bq, torch, args, "rip2048", max(20, args.steps // 2))
+        out["fp32_single_c2"] = single_line(bq, torch, args, "beach1024x256", max(20, args.steps))
         # the same 64-domain batch with the Adams-Moulton corrector (two
         # passes of the stencil and the line solves per step)
         sp, dt_ = workload("batch64")
@@ -350,15 +363,7 @@ def main():
         torch.cuda.synchronize()
         fp64 = {}
         for wl in ("beach1024x256_fp64", "solitary200x20"):
-            sp, dt_ = workload(wl)
-            ds, g = make_group(bq, sp, dt_, batch=True)
-            sched = tuned(g, args)
-            c = sum(s["params"]["nx"] * s["params"]["ny"] for s in sp)
-            n = max(20, args.steps)
-            e = timed(torch, g, n, args.warmup)
-            fp64[wl] = {"value": c * n / e / 1e9, "unit": "Gcell-steps/s", "ms_per_step": e / n * 1e3,
-                        "cells": c, "steps": n, "schedule": sched}
-            del g, ds
+            fp64[wl] = single_line(bq, torch, args, wl, max(20, args.steps))
         out["fp64_plain"] = fp64
     if args.serve_seconds > 0:
         out["serving"] = serve_run(bq, args.serve_seconds)

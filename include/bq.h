@@ -35,7 +35,8 @@
  * bq_domain_create (for instance a torch uint8 tensor on the GPU) and must
  * keep it alive until bq_domain_free.  The library allocates nothing on the
  * device for a domain beyond that workspace; a batch allocates its own small
- * descriptor tables.  Host pointers passed in are only read during the call.
+ * descriptor tables and creates the streams and events of its lanes.  Host
+ * pointers passed in are only read during the call.
  *
  * Errors.  Every call returns 0 (BQ_OK) or a negative bq_status; nothing
  * throws across the ABI.  bq_last_error() returns a message for the calling
@@ -237,7 +238,8 @@ typedef struct bq_tune {
  * schedule (lanes 1-4 x graph replays of 4 or 16 steps x line coupling by
  * one thread per line in blocks of 64 or 256, or segmented; XCD-aware tile
  * order on) twice, in forward then reverse order,
- * keeps the one of the lowest mean time and returns it.  The
+ * keeps the one of the lowest mean time (among those within 0.5 % of it,
+ * the one with the longest graph replays) and returns it.  The
  * trial steps are real steps (the domains advance by them).  bq_batch_set_tune applies a schedule, for
  * instance one cached from an earlier autotune of a batch of the same shape;
  * bq_batch_get_tune reports the current one (ms_per_step 0). */

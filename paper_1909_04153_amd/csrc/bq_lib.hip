@@ -1212,6 +1212,12 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   int best = 0;
   for (size_t k = 1; k < cands.size(); ++k)
     if (cands[k].ms_per_step < cands[best].ms_per_step) best = (int)k;
+  // candidates within half a percent of the fastest are ties at the trials'
+  // resolution: take the one with the longest graph replays among them
+  // (fewest host launches over a long run)
+  const double tie = 1.005 * cands[best].ms_per_step;
+  for (size_t k = 0; k < cands.size(); ++k)
+    if (cands[k].ms_per_step <= tie && cands[k].graph_steps > cands[best].graph_steps) best = (int)k;
   rc = set_tune(b, &cands[best]);
   if (rc) return rc;
   *out = cands[best];
