@@ -291,7 +291,9 @@ def main():
     bq.load()
     specs, dtype = workload(args.workload)
     cells = sum(s["params"]["nx"] * s["params"]["ny"] for s in specs)
-    doms, group = make_group(bq, specs, dtype, args.lanes)
+    # a single-domain workload runs as a batch of one, so that its schedule
+    # is tuned like the other lines'
+    doms, group = make_group(bq, specs, dtype, args.lanes, batch=not args.no_autotune)
     schedule = None
     if isinstance(group, bq.Batch):
         if not args.no_autotune:
