@@ -22,16 +22,17 @@ using namespace bqk;
 // ---------------------------------------------------------------------------
 // Tile height (= y-chunk length) and x-chunk length of the line solves;
 // the chunk lengths are build-time tunables (BQ_MX_F32 / BQ_MX_F64, a
-// divisor of the 64-cell tile width).  FP32 takes 16-cell x-chunks: the
-// finalize kernel's x solves then use a whole wave (16 rows x 4 chunks) and
-// run half as long; the line coupling gets twice the chunks, which the
-// segmented variant absorbs (measured: k_final -12 %, k_rhs -3 %, C3 domain
-// +6 %, 64-domain batch unchanged).
+// divisor of the 64-cell tile width).  Both take 16-cell x-chunks: the
+// finalize kernel's x solves then run half as long (in FP32 on a whole wave,
+// 16 rows x 4 chunks); the line coupling gets twice the chunks, which the
+// segmented variant absorbs (measured against 32 in FP32: k_final -12 %,
+// k_rhs -3 %, C3 domain +6 %, 64-domain batch unchanged; in FP64: 200 x 20
+// domain +9 %, 1024 x 256 +1 %).
 #ifndef BQ_MX_F32
 #define BQ_MX_F32 16
 #endif
 #ifndef BQ_MX_F64
-#define BQ_MX_F64 32
+#define BQ_MX_F64 16
 #endif
 template <typename T> struct Cfg;
 template <> struct Cfg<float> {
