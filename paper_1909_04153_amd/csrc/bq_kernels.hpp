@@ -191,12 +191,13 @@ __device__ __forceinline__ float gmm<float>(float a, float b, float c) {
 
 // half the limited slope (times the cell size) of q at a cell from its two
 // neighbours, ht = theta / 2: minmod(ht (q0 - qm), (qp - qm) / 4, ht (qp - q0));
-// theta = 0 selects the unlimited central slope.  Halving is exact, so the
-// face values q0 -/+ hslope equal q0 -/+ slope / 2.
-template <typename T>
+// theta = 0 (LIM false; the caller takes that choice once per tile) selects
+// the unlimited central slope.  Halving is exact, so the face values
+// q0 -/+ hslope equal q0 -/+ slope / 2.
+template <bool LIM, typename T>
 __device__ __forceinline__ T hslope(T qm, T q0, T qp, T ht) {
   const T c = T(0.25) * (qp - qm);
-  return ht > T(0) ? gmm(ht * (q0 - qm), c, ht * (qp - q0)) : c;
+  return LIM ? gmm(ht * (q0 - qm), c, ht * (qp - q0)) : c;
 }
 
 // Velocity factor of the KP07 desingularisation, u = q * vfac(h):
@@ -221,16 +222,41 @@ __device__ __forceinline__ T dbar4(T a, T b, T c, T d) {
   return T(0.25) * (a + b + c + d);
 }
 
+// max(D, 0) and min(D, 0) of a still-water depth (always finite).  FP32 takes
+// one median-of-three: a plain fmax of a value read from memory costs a
+// second instruction that quiets a possible signalling NaN first.
 template <typename T>
 __device__ __forceinline__ T dpos(T D) {
   return fmax(D, T(0));
 }
+template <>
+__device__ __forceinline__ float dpos<float>(float D) {
+  return __builtin_amdgcn_fmed3f(D, 0.0f, 3.402823466e38f);
+}
+template <typename T>
+__device__ __forceinline__ T dneg(T D) {
+  return fmin(D, T(0));
+}
+template <>
+__device__ __forceinline__ float dneg<float>(float D) {
+  return __builtin_amdgcn_fmed3f(D, 0.0f, -3.402823466e38f);
+}
+
+// max(a, b) of finite values; FP32 again without the quieting instruction
+template <typename T>
+__device__ __forceinline__ T dmax_nq(T a, T b) {
+  return fmax(a, b);
+}
+template <>
+__device__ __forceinline__ float dmax_nq<float>(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, 3.402823466e38f);
+}
 
 // Piecewise-linear w at a cell's low/high faces with the KP07 positivity
 // correction; Dlo/Dhi are the still-water depths at the faces (bed = -D).
-template <typename T>
+template <bool LIM, typename T>
 __device__ __forceinline__ void recon_w(T wm, T w0, T wp, T ht, T Dlo, T Dhi, T& wlo, T& whi) {
-  const T s = hslope(wm, w0, wp, ht);
+  const T s = hslope<LIM>(wm, w0, wp, ht);
   wlo = w0 - s;
   whi = w0 + s;
   if (whi + Dhi < T(0)) {
@@ -248,7 +274,7 @@ __device__ __forceinline__ void recon_w(T wm, T w0, T wp, T ht, T Dlo, T Dhi, T&
 //   h - D+ = w (wet face below the still-water line), -D (dry there), h (land).
 // The still-water parts of the flux differences and of the well-balanced bed
 // source cancel exactly except in cells whose two faces straddle the
-// still-water line (see shore_term); keeping them would leave FP32 with a
+// still-water line (see add_shore); keeping them would leave FP32 with a
 // difference of large numbers in deep water.
 template <typename T>
 struct Side {
@@ -280,8 +306,9 @@ __device__ __forceinline__ Side<T> make_side(T w, T qn, T qt, T Dface, T eps, T 
     s.qn = s.h * s.un;
     s.qt = s.h * s.ut;
   }
-  const T Dp = fmax(Dface, T(0));
-  s.dev = Dface > T(0) ? (s.h > T(0) ? w : -Dface) : s.h;
+  const T Dp = dpos(Dface);
+  // (h > 0 exactly when w > -D, so below the still-water line dev is max(w, -D))
+  s.dev = Dface > T(0) ? dmax_nq(w, -Dface) : s.h;
   s.pp = T(0.5) * g * s.dev * (s.h + Dp);
   return s;
 }
@@ -296,7 +323,7 @@ __device__ __forceinline__ void cu_flux(const Side<T>& L, const Side<T>& R, T g,
   const T den = ap - am;
   if (den == T(0)) {
     // both sides dry and at rest: the full flux is zero
-    const T Dp = fmax(Dface, T(0));
+    const T Dp = dpos(Dface);
     f0 = ft = T(0);
     fn = -T(0.5) * g * Dp * Dp;
     return;
@@ -321,10 +348,12 @@ __device__ __forceinline__ T face_dev(T wf, T Df) {
 // whose low/high faces have still-water depths Dl, Dh: zero unless exactly
 // one of them is below the still-water line
 template <typename T>
-__device__ __forceinline__ T shore_term(T Dl, T Dh, T g) {
-  if ((Dl > T(0)) == (Dh > T(0))) return T(0);
-  const T pl = fmax(Dl, T(0)), ph = fmax(Dh, T(0));
-  return T(0.5) * g * ((Dh - Dl) * (ph + pl) - (ph * ph - pl * pl));
+__device__ __forceinline__ void add_shore(T& bed, T Dl, T Dh, T g) {
+  // a branch, not a select: shore faces are rare, so most waves skip it
+  if (__builtin_expect((Dl > T(0)) != (Dh > T(0)), 0)) {
+    const T pl = dpos(Dl), ph = dpos(Dh);
+    bed += T(0.5) * g * ((Dh - Dl) * (ph + pl) - (ph * ph - pl * pl));
+  }
 }
 
 // Coefficients of Eq. (21) at a cell from the still-water depths of the cell
@@ -933,16 +962,22 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     for (int k = 0; k < CPT + 3; ++k) Dfx[k] = T(0.5) * (c0[k] + c0[k + CXN]);
     // cell cx0 - 1 + k at its low (l) and high (h) faces
     T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
+    // limited (theta > 0) or central slopes: one uniform branch per tile
+    auto recon = [&](auto lim) {
+      constexpr bool LIM = decltype(lim)::value;
 #pragma unroll
-    for (int k = 0; k < CPT + 2; ++k) {
-      recon_w(wr[k], wr[k + 1], wr[k + 2], ht, Dfx[k], Dfx[k + 1], wl[k], wh[k]);
-      const T sp = hslope(pr[k], pr[k + 1], pr[k + 2], ht);
-      const T sq = hslope(qr[k], qr[k + 1], qr[k + 2], ht);
-      pl[k] = pr[k + 1] - sp;
-      ph[k] = pr[k + 1] + sp;
-      ql[k] = qr[k + 1] - sq;
-      qh[k] = qr[k + 1] + sq;
-    }
+      for (int k = 0; k < CPT + 2; ++k) {
+        recon_w<LIM>(wr[k], wr[k + 1], wr[k + 2], ht, Dfx[k], Dfx[k + 1], wl[k], wh[k]);
+        const T sp = hslope<LIM>(pr[k], pr[k + 1], pr[k + 2], ht);
+        const T sq = hslope<LIM>(qr[k], qr[k + 1], qr[k + 2], ht);
+        pl[k] = pr[k + 1] - sp;
+        ph[k] = pr[k + 1] + sp;
+        ql[k] = qr[k + 1] - sq;
+        qh[k] = qr[k + 1] + sq;
+      }
+    };
+    if (ht > T(0)) recon(std::true_type{});
+    else recon(std::false_type{});
     T f0w = T(0), fnw = T(0), ftw = T(0), dvw = T(0);  // west face of the cell being closed
 #pragma unroll
     for (int m = 0; m <= CPT; ++m) {
@@ -957,7 +992,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
         // of its own face depths; with the still-water parts of the pressure
         // fluxes taken out only the face-depth departures remain
         const T Dw = Dfx[m], De = Dfx[m + 1];
-        const T bed = g * (De - Dw) * (T(0.5) * (L.dev + dvw)) + shore_term(Dw, De, g);
+        T bed = g * (De - Dw) * (T(0.5) * (L.dev + dvw));
+        add_shore(bed, Dw, De, g);
         const int o = rx * AXP + cx0 + m - 1;
         sm.x.ax[0][o] = -(f0 - f0w) * idx;
         sm.x.ax[1][o] = (bed - (fn - fnw)) * idx;
@@ -981,16 +1017,21 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
     for (int k = 0; k < CPT + 3; ++k) Dfy[k] = T(0.5) * (c0[k * CXN] + c0[k * CXN + 1]);
     T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
+    auto recon = [&](auto lim) {
+      constexpr bool LIM = decltype(lim)::value;
 #pragma unroll
-    for (int k = 0; k < CPT + 2; ++k) {
-      recon_w(wc[k * LW], wc[(k + 1) * LW], wc[(k + 2) * LW], ht, Dfy[k], Dfy[k + 1], wl[k], wh[k]);
-      const T sp = hslope(pc[k * LW], pc[(k + 1) * LW], pc[(k + 2) * LW], ht);
-      const T sq = hslope(qc[k * LW], qc[(k + 1) * LW], qc[(k + 2) * LW], ht);
-      pl[k] = pc[(k + 1) * LW] - sp;
-      ph[k] = pc[(k + 1) * LW] + sp;
-      ql[k] = qc[(k + 1) * LW] - sq;
-      qh[k] = qc[(k + 1) * LW] + sq;
-    }
+      for (int k = 0; k < CPT + 2; ++k) {
+        recon_w<LIM>(wc[k * LW], wc[(k + 1) * LW], wc[(k + 2) * LW], ht, Dfy[k], Dfy[k + 1], wl[k], wh[k]);
+        const T sp = hslope<LIM>(pc[k * LW], pc[(k + 1) * LW], pc[(k + 2) * LW], ht);
+        const T sq = hslope<LIM>(qc[k * LW], qc[(k + 1) * LW], qc[(k + 2) * LW], ht);
+        pl[k] = pc[(k + 1) * LW] - sp;
+        ph[k] = pc[(k + 1) * LW] + sp;
+        ql[k] = qc[(k + 1) * LW] - sq;
+        qh[k] = qc[(k + 1) * LW] + sq;
+      }
+    };
+    if (ht > T(0)) recon(std::true_type{});
+    else recon(std::false_type{});
     T f0s = T(0), fns = T(0), fts = T(0), dvs = T(0);
 #pragma unroll
     for (int m = 0; m <= CPT; ++m) {
@@ -1001,7 +1042,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       cu_flux(Sd, Nd, g, Df, f0, fn, ft);
       if (m > 0) {
         const T Ds = Dfy[m], Dn = Dfy[m + 1];
-        const T bed = g * (Dn - Ds) * (T(0.5) * (Sd.dev + dvs)) + shore_term(Ds, Dn, g);
+        T bed = g * (Dn - Ds) * (T(0.5) * (Sd.dev + dvs));
+        add_shore(bed, Ds, Dn, g);
         acc_e[m - 1] = -(f0 - f0s) * idy;
         acc_f[m - 1] = -(ft - fts) * idy;              // x-momentum through y-faces
         acc_g[m - 1] = (bed - (fn - fns)) * idy;       // y-momentum
@@ -1029,7 +1071,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   const T i2dx = D.i2dx, i2dy = D.i2dy, idx2 = D.idx2, idy2 = D.idy2, i4dxdy = D.i4dxdy;
   const T i2dx3 = D.i2dx3, i2dy3 = D.i2dy3, i2dxdy2 = D.i2dxdy2, i2dx2dy = D.i2dx2dy;
   const T Bg = B * g;
-  T ures[CPT], vres[CPT];
+  static_assert(S::AXP == TXP, "U*, V* alias the x-parts cell by cell");
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int r = rY0 + q, c = cY;
@@ -1047,7 +1089,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0); they
     // vanish with d0 on land
     {
-#define ETA(o) (sm.w[C0 + (o)] + fmin(sm.db[C0 + (o)], T(0)))
+#define ETA(o) (sm.w[C0 + (o)] + dneg(sm.db[C0 + (o)]))
       const T e00 = ETA(0);
       const T exm = ETA(-1), exp_ = ETA(1), eym = ETA(-LW), eyp = ETA(LW);
       const T emm = ETA(-LW - 1), epm = ETA(-LW + 1), emp = ETA(LW - 1), epp = ETA(LW + 1);
@@ -1088,15 +1130,11 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     }
     // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
     // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
-    // U*^n = T P^n with the same matrix
-    ures[q] = in ? a0 * f_ + hF[q] : T(0);
-    vres[q] = in ? a0 * g_ + hG[q] : T(0);
-  }
-  __syncthreads();  // x-parts consumed; the union now holds U*, V*
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    sm.x.s.u[(rY0 + q) * TXP + cY] = ures[q];
-    sm.x.s.v[(rY0 + q) * TXP + cY] = vres[q];
+    // U*^n = T P^n with the same matrix.  They overwrite this cell's own
+    // x-parts (same word of the union), which no other thread reads, so no
+    // barrier is needed between the two.
+    sm.x.s.u[o] = in ? a0 * f_ + hF[q] : T(0);
+    sm.x.s.v[o] = in ? a0 * g_ + hG[q] : T(0);
   }
   __syncthreads();
 
