@@ -53,24 +53,46 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload_name, dtype, lanes):
-    """bytes per launch from the committed counter summaries, or None when
-    none matches this kernel, workload, lane count and the current kernel
-    sources"""
+def _profile_record(tag, kernel, workload_name, dtype, lanes):
+    """the `tag:` record of the committed counter summaries for this kernel,
+    workload, lane count and the current kernel sources, or None"""
     want = kernel_source_hash()
     if not os.path.isdir(PROFILE_SUMMARIES):
         return None
     for fn in sorted(os.listdir(PROFILE_SUMMARIES)):
         with open(os.path.join(PROFILE_SUMMARIES, fn)) as fh:
             for line in fh:
-                if not line.startswith("traffic:"):
+                if not line.startswith(tag + ":"):
                     continue
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
                 if (kv.get("kernel") == kernel and kv.get("workload") == workload_name
                         and kv.get("dtype") == dtype and kv.get("lanes", "1") == str(lanes)
                         and kv.get("source_sha256_16") == want):
-                    return float(kv["bytes_per_launch"])
+                    return kv
     return None
+
+
+def measured_traffic(kernel, workload_name, dtype, lanes):
+    """HBM bytes per launch (FETCH_SIZE / WRITE_SIZE, calibrated) from the
+    committed counter summaries, or None"""
+    kv = _profile_record("traffic", kernel, workload_name, dtype, lanes)
+    return float(kv["bytes_per_launch"]) if kv else None
+
+
+SIMDS, CLOCK_HZ, CYCLES_PER_VALU = 1024, 2.4e9, 4   # MI355X: 256 CUs x 4 SIMDs; wave64 FP32 op in 4 cycles
+
+
+def valu_issue(kernel, workload_name, dtype, mean_ms):
+    """VALU issue time of one launch (SQ_INSTS_VALU / SQ_WAVES from the
+    committed counter summaries x waves x 4 cycles over 1024 SIMDs at
+    2.4 GHz) against its measured duration, or None"""
+    kv = _profile_record("valu", kernel, workload_name, dtype, 1)
+    if not kv or not mean_ms:
+        return None
+    ipw, waves = float(kv["insts_per_wave"]), float(kv["waves_per_launch"])
+    issue_ms = ipw * waves * CYCLES_PER_VALU / (SIMDS * CLOCK_HZ) * 1e3
+    return {"insts_per_wave": ipw, "waves_per_launch": waves, "issue_ms": issue_ms,
+            "frac": issue_ms / mean_ms}
 
 
 def workload(name):
@@ -327,7 +349,8 @@ def main():
             "frac": achieved / HBM_PEAK_GBS if achieved else None,
             "traffic": measured_traffic(dom_k, args.workload, dtype, 1), "traffic_unit": "bytes/launch",
             "algorithmic_bytes_per_cell": WORDS[dom_k] * wsize, "cells_per_launch": cells_launch,
-            "mean_ms": kms[dom_k], "profiled": "one lane, plain launches, HIP events on the launch stream"}
+            "mean_ms": kms[dom_k], "profiled": "one lane, plain launches, HIP events on the launch stream",
+            "valu_issue": valu_issue(dom_k, args.workload, dtype, kms[dom_k])}
     out = {"metric": METRIC, "value": value, "unit": "Gcell-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": dtype, "data": "synthetic",
