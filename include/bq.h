@@ -149,8 +149,11 @@ int bq_workspace_bytes(const bq_params* p, size_t* bytes);
 
 /* Create a domain in the caller's device workspace; hip_stream is a
  * hipStream_t (NULL = the null stream).  depth_c is the host corner
- * still-water depth, (ny+1) x (nx+1) row-major.  Precomputes the static
- * fields and the factorisation data of Eq. (19)-(21).  State: lake at rest. */
+ * still-water depth, (ny+1) x (nx+1) row-major; a non-finite value is
+ * rejected with BQ_EINVAL before anything reaches the device (so are
+ * non-finite wave components and time-series samples, here and in
+ * bq_workspace_bytes).  Precomputes the static fields and the factorisation
+ * data of Eq. (19)-(21).  State: lake at rest. */
 int bq_domain_create(const bq_params* p, const double* depth_c, void* dev_workspace, size_t bytes,
                      void* hip_stream, bq_domain** out);
 int bq_domain_free(bq_domain* d);

@@ -337,13 +337,6 @@ __device__ __forceinline__ void cu_flux(const Side<T>& L, const Side<T>& R, T g,
   ft = (ap * L.qn * L.ut - am * R.qn * R.ut) * inv + dis * (R.qt - L.qt);
 }
 
-// departure of a face depth from the face's still-water depth D+ (as above)
-template <typename T>
-__device__ __forceinline__ T face_dev(T wf, T Df) {
-  const T h = fmax(wf + Df, T(0));
-  return Df > T(0) ? (h > T(0) ? wf : -Df) : h;
-}
-
 // still-water remainder of (bed source - pressure flux difference) in a cell
 // whose low/high faces have still-water depths Dl, Dh: zero unless exactly
 // one of them is below the still-water line

@@ -517,6 +517,16 @@ static int check_params(const bq_params* p) {
     return fail(BQ_EINVAL, "a wavemaker needs n_waves >= 1 with amplitudes and frequencies");
   if (p->fstar_order < 0 || p->fstar_order > 2) return fail(BQ_EINVAL, "fstar_order must be 0, 1 or 2");
   if (p->precision != BQ_FP64 && p->precision != BQ_FP32) return fail(BQ_EINVAL, "bad precision");
+  // the forcing must be finite (the kernels take it as given)
+  if (p->bc[0] == BQ_TIMESERIES)
+    for (int k = 0; k < p->ts_n; ++k)
+      if (!std::isfinite(p->ts_eta[k]) || !std::isfinite(p->ts_P[k]))
+        return fail(BQ_EINVAL, "time-series sample %d is not finite", k);
+  if (wave)
+    for (int m = 0; m < p->n_waves; ++m)
+      if (!std::isfinite(p->wave_amp[m]) || !std::isfinite(p->wave_omega[m]) ||
+          (p->wave_phase && !std::isfinite(p->wave_phase[m])))
+        return fail(BQ_EINVAL, "wave component %d is not finite", m);
   return BQ_OK;
 }
 
@@ -1263,6 +1273,10 @@ int bq_domain_create(const bq_params* p, const double* depth_c, void* dev_worksp
   if (rc) return rc;
   if (!depth_c || !dev_workspace || !out) return fail(BQ_EINVAL, "NULL argument");
   if (((uintptr_t)dev_workspace) % 256 != 0) return fail(BQ_EINVAL, "workspace must be 256-byte aligned");
+  // still-water depths must be finite (the kernels take max(D, 0) and
+  // min(D, 0) of finite values); checked before anything reaches the device
+  for (size_t k = 0, nc = (size_t)(p->nx + 1) * (p->ny + 1); k < nc; ++k)
+    if (!std::isfinite(depth_c[k])) return fail(BQ_EINVAL, "depth_c[%zu] is not finite", k);
   bq_domain* d = new (std::nothrow) bq_domain();
   if (!d) return fail(BQ_EINVAL, "out of host memory");
   d->p = *p;

@@ -84,6 +84,14 @@ def test_parameter_checks_of_the_experiment_knobs():
             bq.workspace_bytes(bad)
     with pytest.raises(ValueError):
         bq.make_params(dict(ts, ts_P=[0.0]))
+    # non-finite forcing is rejected on the host
+    for bad in (dict(ts, ts_eta=[0.0, float("nan")]), dict(ts, ts_P=[float("inf"), 0.0])):
+        with pytest.raises(bq.BqError):
+            bq.workspace_bytes(bad)
+    sine = S.sloping_beach()["params"]
+    assert bq.workspace_bytes(sine) > 0
+    with pytest.raises(bq.BqError):
+        bq.workspace_bytes(dict(sine, wave_amp=[float("nan")]))
     # the run-up record adds one interior field
     n0 = bq.workspace_bytes(base, bq.FP32)
     n1 = bq.workspace_bytes(dict(base, runup_delta=0.01), bq.FP32)

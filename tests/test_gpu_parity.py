@@ -206,6 +206,11 @@ def test_status_latching(bq):
     bad[3, 3] = -5.0
     with pytest.raises(bq.BqError):
         g.set_state(bad, spec["P"], spec["Q"])
+    # so is a non-finite still-water depth, before the domain exists
+    dc = spec["depth_c"].copy()
+    dc[2, 5] = np.inf
+    with pytest.raises(bq.BqError):
+        bq.Domain(spec["params"], dc, precision=bq.FP32)
     # NaN in the state latches ENONFINITE and stops the domain
     g.set_state(spec["eta"], spec["P"], spec["Q"])
     P = spec["P"].copy()
