@@ -37,8 +37,12 @@
  *   Adams-Moulton corrector (Sec. 1, built like Eq. 30) ... pinned: constant-
  *       step coefficients, exactness on polynomials, order 4 on an ODE and
  *       fourth-order self-convergence of the full step on a smooth case.
- *   wavemaker ghost values, sponge (Sec. 3.3, readings) ... parity unpinned
- *       beyond the MS wave number (bisection vs. relation).
+ *   wavemaker ghost values, sponge (Sec. 3.3, readings) ... pinned by what
+ *       they produce: the linear-theory amplitude and phase advance k dx of
+ *       the incident wave, linear superposition of components, and a flat
+ *       amplitude envelope (no reflection) in front of a sponge band.  The
+ *       formulas themselves follow references the paper cites and does not
+ *       restate.
  */
 #include "bqo.h"
 
