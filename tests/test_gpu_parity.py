@@ -314,6 +314,50 @@ def test_two_lane_batch_profile_and_graphs_match_one_lane(bq):
                 assert np.array_equal(a, c)
 
 
+def test_full_size_batch64_as_benched(bq):
+    """The benchmark's 64-domain FP32 batch (21.3 M cells) at full size, in
+    the schedule the autotuner picks for it (3 lanes, 16-step graph replays,
+    64-thread line coupling): every member equals its solo run bit for bit,
+    and the smallest solitary-wave and beach members match the FP64 oracle."""
+    specs = S.batch_mix(64, seed=190904154)
+    steps = 32
+    print("batch64: %d cells" % sum(s["params"]["nx"] * s["params"]["ny"] for s in specs), flush=True)
+    doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
+    b = bq.Batch(doms, lanes=3)
+    b.set_tune(dict(lanes=3, graph_steps=16, reduce_block=64, reduce_segments=1, swizzle=1))
+    b.step(steps)
+    b.sync()
+    batched = []
+    for d in doms:
+        i = d.sync()
+        assert i.status == 0 and i.n == steps
+        batched.append([d.read(f) for f in FIELDS])
+    b.close()
+    for d in doms:
+        d.close()
+    for k, s in enumerate(specs):
+        g = bq.domain_from_spec(s, precision=bq.FP32)
+        g.step(steps)
+        assert g.sync().status == 0
+        for f, r in zip(FIELDS, batched[k]):
+            assert np.array_equal(g.read(f), r), (s["name"], f)
+        g.close()
+    def cells(k):
+        return specs[k]["params"]["nx"] * specs[k]["params"]["ny"]
+
+    sol = [k for k in range(len(specs)) if "solitary" in specs[k]["name"]]
+    beach = [k for k in range(len(specs)) if k not in sol]
+    for k in (min(sol, key=cells), min(beach, key=cells)):
+        spec = specs[k]
+        o = OracleDomain(spec["params"], spec["depth_c"])
+        assert o.set_state(spec["eta"], spec["P"], spec["Q"]) == 0
+        assert o.step(steps) == 0
+        sc = scales(spec)
+        errs = {f: rel(batched[k][n], o.read(f), sc[f]) for n, f in enumerate(FIELDS)}
+        print(spec["name"], " ".join(f"{f} {e:.2e}" for f, e in errs.items()), flush=True)
+        assert errs["eta"] <= 1e-4
+
+
 def _compare_maps(o, g, spec, scale):
     """run-up record (NaN pattern and values) and local CFL map.  The CFL
     speed holds sqrt(g h): on cells with a film of rounding-level depth the
