@@ -503,14 +503,37 @@ __device__ __forceinline__ void locate(const int* map, int nd, int idx, int& dom
 // k_dt: Delta t and weights of the step (one block per domain)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void commit(DevState* st) {
-  if (st->pending) {
-    st->t = st->t_next;
-    st->dt3 = st->dt2;
-    st->dt2 = st->dt1;
-    st->dt1 = st->dt;
-    st->n += 1;
-    st->pending = 0;
+// whole-state copies through the global address space: one batch of loads
+// or stores (a generic pointer would make them flat accesses, which also
+// wait on the LDS counter)
+__device__ __forceinline__ DevState load_state(const DevState* st) {
+  constexpr int NW = (int)(sizeof(DevState) / 8);
+  static_assert(sizeof(DevState) % 8 == 0, "state is whole 8-byte words");
+  const gp<const unsigned long long> src = gbl((const unsigned long long*)st);
+  unsigned long long w[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) w[k] = src[k];
+  DevState S;
+  __builtin_memcpy(&S, w, sizeof S);
+  return S;
+}
+__device__ __forceinline__ void store_state(DevState* st, const DevState& S) {
+  constexpr int NW = (int)(sizeof(DevState) / 8);
+  unsigned long long w[NW];
+  __builtin_memcpy(w, &S, sizeof S);
+  const gp<unsigned long long> dst = gbl((unsigned long long*)st);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) dst[k] = w[k];
+}
+
+__device__ __forceinline__ void commit(DevState& st) {
+  if (st.pending) {
+    st.t = st.t_next;
+    st.dt3 = st.dt2;
+    st.dt2 = st.dt1;
+    st.dt1 = st.dt;
+    st.n += 1;
+    st.pending = 0;
   }
 }
 
@@ -564,8 +587,11 @@ __device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP
   }
   __syncthreads();
   if (tid == 0) {
+    // lanes past the component count hold zeros: summing them would change
+    // nothing but the time
     double s[4] = {0, 0, 0, 0};
-    for (int q = 0; q < 64; ++q)
+    const int nq = nw < 64 ? nw : 64;
+    for (int q = 0; q < nq; ++q)
       for (int c = 0; c < 4; ++c) s[c] += red[c][q];
     gw[0] = s[0]; gP[0] = s[1]; gw[1] = s[2]; gP[1] = s[3];
   }
@@ -581,6 +607,15 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
   DevState* st = D.st;
   __shared__ int go;
   __shared__ double tn;
+  // The state and the step controls are loaded first, in one batch, so their
+  // latency overlaps the reduction below (the barrier in it keeps the state's
+  // loads here); the decision further down is then register arithmetic.
+  DevState S = load_state(st);
+  const double t_end = D.t_end, cfl = D.cfl, ema = D.ema_alpha, dt_init = D.dt_init, dt_max = D.dt_max,
+               dt_min = D.dt_min;
+  const int fixed_dt = D.fixed_dt, fstar_order = D.fstar_order;
+  __asm__ volatile("" ::"s"(t_end), "s"(cfl), "s"(ema), "s"(dt_init), "s"(dt_max), "s"(dt_min), "s"(fixed_dt),
+                   "s"(fstar_order));
   // CFL maximum of the current state: the finalize kernel's per-tile maxima
   // (a NaN there is already +inf) and the initial state's value
   double tmax = 0.0;
@@ -609,36 +644,38 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
     for (int w = 0; w < DT_THREADS / 64; ++w) tmax = fmax(tmax, wmax[w]);
   }
   if (threadIdx.x == 0) {
-    commit(st);
+    // one thread decides the step on the register copy of the state and
+    // stores it back in one batch
+    commit(S);
     go = 0;
-    st->halt = 1;
-    if (st->status == ST_OK) {
-      if (D.t_end > 0.0 && st->t >= D.t_end) {
-        st->status = ST_EDONE;
+    S.halt = 1;
+    if (S.status == ST_OK) {
+      if (t_end > 0.0 && S.t >= t_end) {
+        S.status = ST_EDONE;
       } else {
-        const double s = fmax(__longlong_as_double((long long)st->smax_bits), tmax);
+        const double s = fmax(__longlong_as_double((long long)S.smax_bits), tmax);
         if (!(s <= 1.79e308)) {
-          st->status = ST_ENONFINITE;
+          S.status = ST_ENONFINITE;
         } else {
-          const long long n = st->n;
+          const long long n = S.n;
           double dt;
           bool ok = true;
           if (dt_prescribed > 0.0) {
             dt = dt_prescribed;
-          } else if (D.fixed_dt) {
-            dt = D.dt_init;
+          } else if (fixed_dt) {
+            dt = dt_init;
           } else {
-            const double cand = s > 0.0 ? D.cfl / s : D.dt_max;
-            if (n == 0) dt = D.dt_init > 0.0 ? D.dt_init : cand;
-            else dt = cand <= st->dt1 ? cand : D.ema_alpha * cand + (1.0 - D.ema_alpha) * st->dt1;
-            dt = fmin(dt, D.dt_max);
-            if (dt < D.dt_min) {
-              st->status = ST_EDTMIN;
+            const double cand = s > 0.0 ? cfl / s : dt_max;
+            if (n == 0) dt = dt_init > 0.0 ? dt_init : cand;
+            else dt = cand <= S.dt1 ? cand : ema * cand + (1.0 - ema) * S.dt1;
+            dt = fmin(dt, dt_max);
+            if (dt < dt_min) {
+              S.status = ST_EDTMIN;
               ok = false;
             }
           }
           if (ok) {
-            const double h0 = dt, h1 = st->dt1, h2 = st->dt2;
+            const double h0 = dt, h1 = S.dt1, h2 = S.dt2;
             double a0 = h0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
             if (n == 1) {
               b0 = h0 / h1;
@@ -650,7 +687,7 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
               a0 = h0 / 6.0 * (r1 * (2.0 * h0 + 6.0 * h1 + 3.0 * h2) / s12 + 6.0);
               a1 = -h0 / 6.0 * (r1 * (2.0 * h0 + 3.0 * h1 + 3.0 * h2) / h2);
               a2 = h0 / 6.0 * ((h0 / h2) * (2.0 * h0 + 3.0 * h1) / s12);
-              if (D.fstar_order == 1) {
+              if (fstar_order == 1) {
                 b0 = r1;
                 b1 = -r1;
               } else {
@@ -678,22 +715,23 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
               g2 = -hh * (h0 + 2.0 * b) / (12.0 * a * (a + h0) * h2);
               g3 = hh * (h0 + 2.0 * a) / (12.0 * b * (b + h0) * h2);
             }
-            st->dt = dt;
-            st->alpha[0] = a0; st->alpha[1] = a1; st->alpha[2] = a2;
-            st->gamma[0] = g0; st->gamma[1] = g1; st->gamma[2] = g2; st->gamma[3] = g3;
-            st->beta[0] = b0; st->beta[1] = b1; st->beta[2] = b2;
-            st->t_next = st->t + dt;
-            st->smax_used = s;
-            st->slot = (int)(n % 3);
-            st->smax_bits = 0ull;
-            st->pending = 1;
-            st->halt = 0;
+            S.dt = dt;
+            S.alpha[0] = a0; S.alpha[1] = a1; S.alpha[2] = a2;
+            S.gamma[0] = g0; S.gamma[1] = g1; S.gamma[2] = g2; S.gamma[3] = g3;
+            S.beta[0] = b0; S.beta[1] = b1; S.beta[2] = b2;
+            S.t_next = S.t + dt;
+            S.smax_used = s;
+            S.slot = (int)(n % 3);
+            S.smax_bits = 0ull;
+            S.pending = 1;
+            S.halt = 0;
             go = 1;
-            tn = st->t_next;
+            tn = S.t_next;
           }
         }
       }
     }
+    store_state(st, S);
   }
   __syncthreads();
   if (go && west_driven(D.bc[0])) {
@@ -708,7 +746,7 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
 template <typename T>
 __global__ void k_commit(const DomDev<T>* __restrict__ doms, int nd) {
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d < nd) commit(doms[d].st);
+  if (d < nd) commit(*doms[d].st);
 }
 
 // ---------------------------------------------------------------------------
