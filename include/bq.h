@@ -223,9 +223,10 @@ int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
 /* Schedule of a batch: launch lanes, steps per hipGraph replay, threads per
  * block of the line-coupling kernel (64, 128 or 256), the XCD-aware tile
  * order of the stencil kernel (1 on, 0 off), and the line-coupling variant:
- * reduce_segments 1 = one thread per line running over its chunks, 4 = the
- * chunks of a line cut into 4 segments swept by 4 waves that exchange their
- * composed maps (reduce_block is then 256).  With reduce_segments 1 every
+ * reduce_segments 1 = one thread per line running over its chunks, 4 or 8 =
+ * the chunks of a line cut into that many segments swept by as many waves
+ * that exchange their composed maps (reduce_block is then ignored; give 256).
+ * With reduce_segments 1 every
  * schedule gives bitwise the same results; the segmented variant
  * reassociates the line-coupling products and differs at rounding level. */
 typedef struct bq_tune {

@@ -1312,25 +1312,23 @@ __global__ void __launch_bounds__(256) k_reduced(const DomDev<T>* __restrict__ d
   else reduce_line<T>(D.cy, D.nx, l - D.ny, gbl((const T*)D.chy), gbl((const T*)D.rsy), gbl(D.ify));
 }
 
-// The same recurrences with each line's chunks cut into NSEG segments, one
-// wave per segment (a block holds 64 lines x NSEG segments).  Both sweeps are
+// The same recurrences with each line's chunks cut into NS segments (4 or 8),
+// one wave per segment (a block holds 64 lines x NS segments).  Both sweeps are
 // affine recurrences (alpha_c = A_c alpha_{c-1} + B_c forward, with
 // A_c = m1 + m2 k2 and B_c = xh_e + m2 k1 xh_s; X_s(c) = tau_c X_s(c+1) +
 // sigma_c backward), so each segment first composes its maps, the segments
 // exchange them through LDS, and each then runs its part with the right
-// incoming value: twice the arithmetic, a quarter of the serial length.  The
+// incoming value: twice the arithmetic, 1/NS of the serial length.  The
 // results equal the serial sweep's up to rounding (the composition
 // reassociates the products).
-constexpr int NSEG = 4;
-
-template <typename T>
+template <typename T, int NS>
 __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg, bool active, const gp<const T> ch,
                                                 const gp<const T> rs, const gp<T> itf, T (*xa)[64], T (*xb)[64],
                                                 int lane) {
   // the loads of RB chunks are issued together ahead of their serial steps
   constexpr int RB = 8;
   const size_t CL = (size_t)C * L;
-  const int c0 = (int)(((long long)seg * C) / NSEG), c1 = (int)(((long long)(seg + 1) * C) / NSEG);
+  const int c0 = (int)(((long long)seg * C) / NS), c1 = (int)(((long long)(seg + 1) * C) / NS);
   const int n = active ? c1 - c0 : 0;
   // forward, pass 1: the segment's composite map alpha_out = A alpha_in + B
   T A = T(1), B = T(0);
@@ -1404,7 +1402,7 @@ __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg,
   xb[seg][lane] = Sv;
   __syncthreads();
   T xs_next = T(0);
-  for (int k = NSEG - 1; k > seg; --k) xs_next = xa[k][lane] * xs_next + xb[k][lane];
+  for (int k = NS - 1; k > seg; --k) xs_next = xa[k][lane] * xs_next + xb[k][lane];
   // backward, pass 2; the left-neighbour value of the next segment's first
   // chunk is written after the barrier (that segment reads the slot first)
   T held = T(0);
@@ -1443,11 +1441,11 @@ __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg,
   if (active && seg == 0) itf[line] = T(0);       // chunk 0 has no left neighbour
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64 * NSEG) k_reduced_seg(const DomDev<T>* __restrict__ doms,
-                                                          const int* __restrict__ line_map, int nd, int lines,
-                                                          int pass) {
-  __shared__ T xa[NSEG][64], xb[NSEG][64];
+template <typename T, int NS>
+__global__ void __launch_bounds__(64 * NS) k_reduced_seg(const DomDev<T>* __restrict__ doms,
+                                                        const int* __restrict__ line_map, int nd, int lines,
+                                                        int pass) {
+  __shared__ T xa[NS][64], xb[NS][64];
   const int lane = threadIdx.x & 63, seg = threadIdx.x >> 6;
   const int gid = blockIdx.x * 64 + lane;
   // every thread reaches the barriers; inactive ones carry identity maps
@@ -1462,7 +1460,7 @@ __global__ void __launch_bounds__(64 * NSEG) k_reduced_seg(const DomDev<T>* __re
   // the lanes of a wave may hold x-lines and y-lines
   const DomDev<T>& D = doms[dom];
   const bool xl = l < D.ny;
-  reduce_line_seg<T>(xl ? D.cx : D.cy, xl ? D.ny : D.nx, xl ? l : l - D.ny, seg, active,
+  reduce_line_seg<T, NS>(xl ? D.cx : D.cy, xl ? D.ny : D.nx, xl ? l : l - D.ny, seg, active,
                      gbl((const T*)(xl ? D.chx : D.chy)), gbl((const T*)(xl ? D.rsx : D.rsy)),
                      gbl(xl ? D.ifx : D.ify), xa, xb, lane);
 }

@@ -376,7 +376,7 @@ struct Launch {
   // kernel, XCD-aware tile order of the stencil kernel
   int rblock = 256;
   int swizzle = 1;
-  int segs = 1;                 // 1: one thread per line; NSEG: segmented sweeps
+  int segs = 1;                 // 1: one thread per line; 4 or 8: segmented sweeps
   hipGraphExec_t graph = nullptr;
   int graph_steps = 0;          // steps per replay (0 = none)
   int graph_built = 0;          // steps captured in `graph`
@@ -716,8 +716,10 @@ static int set_state_t(bq_domain* d, const double* eta, const double* P, const d
 template <typename T>
 static void launch_reduced(const Launch& L, hipStream_t s, int pass) {
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
-  if (L.segs > 1)
-    k_reduced_seg<T><<<cdiv(L.lines, 64), 64 * NSEG, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
+  if (L.segs == 8)
+    k_reduced_seg<T, 8><<<cdiv(L.lines, 64), 64 * 8, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
+  else if (L.segs == 4)
+    k_reduced_seg<T, 4><<<cdiv(L.lines, 64), 64 * 4, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
   else
     k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
 }
@@ -1166,8 +1168,8 @@ static int set_tune(bq_batch* b, const bq_tune* t) {
   if (t->reduce_block != 64 && t->reduce_block != 128 && t->reduce_block != 256)
     return fail(BQ_EINVAL, "reduce_block must be 64, 128 or 256");
   if (t->swizzle != 0 && t->swizzle != 1) return fail(BQ_EINVAL, "swizzle must be 0 or 1");
-  if (t->reduce_segments != 1 && t->reduce_segments != NSEG)
-    return fail(BQ_EINVAL, "reduce_segments must be 1 or %d", NSEG);
+  if (t->reduce_segments != 1 && t->reduce_segments != 4 && t->reduce_segments != 8)
+    return fail(BQ_EINVAL, "reduce_segments must be 1, 4 or 8");
   if (t->lanes != b->lanes_req) {
     b->lanes_req = t->lanes;
     const int rc = DISPATCH(b->precision, batch_build_t, b);
@@ -1179,8 +1181,9 @@ static int set_tune(bq_batch* b, const bq_tune* t) {
 }
 
 // Each candidate runs real steps of the method (every schedule gives the
-// same results bit for bit), so tuning costs no simulation work: warm-up
-// (which also captures the graph), then steps_per_trial timed steps.
+// same results, bit for bit without segments and up to rounding with them),
+// so tuning costs no simulation work: warm-up (which also captures the
+// graph), then steps_per_trial timed steps.
 template <typename T>
 static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   std::vector<bq_tune> cands;
@@ -1191,7 +1194,7 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   for (int lanes = 1; lanes <= max_lanes; ++lanes)
     for (int graph : {4, 16}) {
       for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 1, 0.0});
-      cands.push_back(bq_tune{lanes, graph, 64 * NSEG, 1, NSEG, 0.0});
+      for (int ns : {4, 8}) cands.push_back(bq_tune{lanes, graph, 256, 1, ns, 0.0});
     }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

@@ -504,17 +504,19 @@ def test_schedules_without_segments_are_bitwise_equal(bq):
         b.close()
 
 
+@pytest.mark.parametrize("segs", [4, 8])
 @pytest.mark.parametrize("case", ["long_lines", "rip_2d", "pc_hump_2d"])
-def test_fp64_parity_segmented_line_coupling(bq, case):
-    # the segmented sweeps (4 segments per line) against the oracle per step:
-    # 66-chunk x-lines, 2D y-lines, and the corrector's second pass
+def test_fp64_parity_segmented_line_coupling(bq, case, segs):
+    # the segmented sweeps (4 or 8 segments per line) against the oracle per
+    # step: 132-chunk x-lines and one-chunk y-lines, 2D lines, and the
+    # corrector's second pass
     spec = CASES[case]()
     o = OracleDomain(spec["params"], spec["depth_c"])
     assert o.set_state(spec["eta"], spec["P"], spec["Q"]) == 0
     g = bq.domain_from_spec(spec, precision=bq.FP64)
     b = bq.Batch([g])
-    b.set_tune({"lanes": 1, "graph_steps": 0, "reduce_block": 256, "swizzle": 1, "reduce_segments": 4})
-    assert b.tune["reduce_segments"] == 4
+    b.set_tune({"lanes": 1, "graph_steps": 0, "reduce_block": 256, "swizzle": 1, "reduce_segments": segs})
+    assert b.tune["reduce_segments"] == segs
     sc = scales(spec)
     worst = 0.0
     for k in range(10):
@@ -525,7 +527,7 @@ def test_fp64_parity_segmented_line_coupling(bq, case):
             e = rel(g.read(f), o.read(f), sc[f])
             worst = max(worst, e)
             assert e <= 1e-12, (case, (k + 1) * 10, f, e)
-    print(f"{case} segmented FP64 worst rel L2 {worst:.2e}")
+    print(f"{case} {segs} segments FP64 worst rel L2 {worst:.2e}")
     b.close()
 
 
