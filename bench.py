@@ -10,7 +10,8 @@ tridiagonal line solves, boundary ghosts.
 
 Prints one JSON line: Gcell-steps/s (interior cells x steps / s), the HBM
 roofline of the dominant kernel (algorithmic bytes / its mean duration, HIP
-events on the launch stream), the single-domain FP64 rates, and the CPU
+events on the launch stream), the single-domain FP64 rates, the error of
+each FP32 line against the FP64 path after the same steps, and the CPU
 oracle's rate on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -159,7 +160,32 @@ def single_line(bq, torch, args, wl, steps):
            "effective_hbm_frac": WORDS_STEP * wsize * c * steps / e / 1e9 / HBM_PEAK_GBS}
     del g, ds
     torch.cuda.synchronize()
+    if dt_ == "fp32":
+        out["fp32_error"] = fp32_error(bq, torch, sp, steps)
     return out
+
+
+def fp32_error(bq, torch, specs, steps):
+    """Error of the FP32 path stated against the FP64 path (whose parity with
+    the FP64 oracle, relative L2 <= 1e-12 per step, the GPU tests hold): both
+    advance the same initial states `steps` adaptive steps; per domain
+    ||eta32 - eta64|| / ||eta64||, worst and median over the domains."""
+    etas = {}
+    for dt_ in ("fp32", "fp64"):
+        ds, g = make_group(bq, specs, dt_, lanes=1)
+        g.step(steps)
+        g.wait()
+        etas[dt_] = [d.read("eta") for d in ds]
+        if g is not ds[0]:
+            g.close()
+        for d in ds:
+            d.close()
+        del g, ds
+        torch.cuda.synchronize()
+    errs = [float(np.linalg.norm(a - b) / max(float(np.linalg.norm(b)), 1e-300))
+            for a, b in zip(etas["fp32"], etas["fp64"])]
+    return {"reference": "fp64 path", "steps": steps, "domains": len(errs),
+            "eta_rel_l2_max": max(errs), "eta_rel_l2_median": float(np.median(errs))}
 
 
 def cpu_baseline(specs, budget_s):
@@ -362,6 +388,8 @@ def main():
         out["kernels_ms_lanes"] = kms2
     del group, doms
     torch.cuda.synchronize()
+    if dtype == "fp32":
+        out["fp32_error"] = fp32_error(bq, torch, specs, args.steps)
     out["copy_gbs"] = copy_bandwidth(torch)
     tr = roof["traffic"]
     if tr:
