@@ -140,6 +140,11 @@ typedef struct bq_batch bq_batch;
 int bq_abi_version(void);
 const char* bq_last_error(void);
 
+/* Streams, events and graph executables the library has created and not yet
+ * destroyed, in counts[0..2] (all domains and batches of the process).  For
+ * tests that freeing a batch or a domain releases what it made. */
+int bq_live_handles(int32_t* counts);
+
 /* Defaults: g 9.81, B 1/15, cfl 0.2, ema_alpha 0.1, dt_max 1, dt_min 1e-9,
  * theta 1.3, walls, fstar_order 2, FP64. */
 void bq_params_default(bq_params* p);

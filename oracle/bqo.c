@@ -360,6 +360,30 @@ static int is_wave(int bc) { return bc == BQO_SINE || bc == BQO_IRREGULAR; }
 /* west sides whose ghost cells are prescribed (wavemakers, time series) */
 static int is_driven(int bc) { return is_wave(bc) || bc == BQO_TIMESERIES; }
 
+/* d_x, d_y (central differences of the cell still-water depth) times
+ * `scale`, and the tridiagonal coefficients of Eq. (21) from them; scale 1
+ * is the method, anything else is a planted mistake for the pin tests */
+static void depth_gradient_and_coefficients(bqo_domain* d, double scale) {
+  const bqo_params* pin = &d->p;
+  const int nx = d->nx, ny = d->ny;
+  const double Bc = pin->B + 1.0 / 3.0;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      const double dd = d->dep[CI(d, i, j)];
+      const double dx_ = scale * (d->dep[CI(d, i + 1, j)] - d->dep[CI(d, i - 1, j)]) / (2.0 * pin->dx);
+      const double dy_ = scale * (d->dep[CI(d, i, j + 1)] - d->dep[CI(d, i, j - 1)]) / (2.0 * pin->dy);
+      d->ddx[II(d, i, j)] = dx_;
+      d->ddy[II(d, i, j)] = dy_;
+      /* Eq. (21) */
+      d->Ax[II(d, i, j)] = dd * dx_ / (6.0 * pin->dx) - Bc * dd * dd / (pin->dx * pin->dx);
+      d->Bx[II(d, i, j)] = 1.0 + 2.0 * Bc * dd * dd / (pin->dx * pin->dx);
+      d->Cx[II(d, i, j)] = -dd * dx_ / (6.0 * pin->dx) - Bc * dd * dd / (pin->dx * pin->dx);
+      d->Ay[II(d, i, j)] = dd * dy_ / (6.0 * pin->dy) - Bc * dd * dd / (pin->dy * pin->dy);
+      d->By[II(d, i, j)] = 1.0 + 2.0 * Bc * dd * dd / (pin->dy * pin->dy);
+      d->Cy[II(d, i, j)] = -dd * dy_ / (6.0 * pin->dy) - Bc * dd * dd / (pin->dy * pin->dy);
+    }
+}
+
 bqo_domain* bqo_create(const bqo_params* pin, const double* depth_c) {
   if (!pin || !depth_c || pin->nx < 3 || pin->ny < 3 || !(pin->dx > 0) || !(pin->dy > 0)) return NULL;
   for (int s = 1; s < 4; ++s)
@@ -437,22 +461,7 @@ bqo_domain* bqo_create(const bqo_params* pin, const double* depth_c) {
       d->bfy[CI(d, i, j)] = 0.5 * (b00 + b10);
       d->dep[CI(d, i, j)] = fmax(0.0 - d->bbar[CI(d, i, j)], 0.0);
     }
-  const double Bc = pin->B + 1.0 / 3.0;
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nx; ++i) {
-      const double dd = d->dep[CI(d, i, j)];
-      const double dx_ = (d->dep[CI(d, i + 1, j)] - d->dep[CI(d, i - 1, j)]) / (2.0 * pin->dx);
-      const double dy_ = (d->dep[CI(d, i, j + 1)] - d->dep[CI(d, i, j - 1)]) / (2.0 * pin->dy);
-      d->ddx[II(d, i, j)] = dx_;
-      d->ddy[II(d, i, j)] = dy_;
-      /* Eq. (21) */
-      d->Ax[II(d, i, j)] = dd * dx_ / (6.0 * pin->dx) - Bc * dd * dd / (pin->dx * pin->dx);
-      d->Bx[II(d, i, j)] = 1.0 + 2.0 * Bc * dd * dd / (pin->dx * pin->dx);
-      d->Cx[II(d, i, j)] = -dd * dx_ / (6.0 * pin->dx) - Bc * dd * dd / (pin->dx * pin->dx);
-      d->Ay[II(d, i, j)] = dd * dy_ / (6.0 * pin->dy) - Bc * dd * dd / (pin->dy * pin->dy);
-      d->By[II(d, i, j)] = 1.0 + 2.0 * Bc * dd * dd / (pin->dy * pin->dy);
-      d->Cy[II(d, i, j)] = -dd * dy_ / (6.0 * pin->dy) - Bc * dd * dd / (pin->dy * pin->dy);
-    }
+  depth_gradient_and_coefficients(d, 1.0);
   /* wavemaker wave numbers at the mean depth of the first interior column */
   double dwm = 0.0;
   for (int j = 0; j < ny; ++j) dwm += d->dep[CI(d, 0, j)];
@@ -776,6 +785,31 @@ static double gstar(const bqo_domain* d, const double* P, int i, int j) {
   const double pxy = (P[CI(d, i + 1, j + 1)] - P[CI(d, i + 1, j - 1)] - P[CI(d, i - 1, j + 1)] + P[CI(d, i - 1, j - 1)]) /
                      (4.0 * dx * dy);
   return dd * dX * py / 6.0 + dd * dY * px / 6.0 + (d->p.B + 1.0 / 3.0) * dd * dd * pxy;
+}
+
+/* Operators of the current state at the interior cells, for the pin tests:
+ * 0 U*^n as the row of Eq. (19) (= Eq. 9 with the coefficients of Eq. 21),
+ * 1 V*^n (Eq. 20 / 10), 2 F*(Q^n) (Eq. 14), 3 G*(P^n) (Eq. 15) */
+int bqo_operator(bqo_domain* d, int32_t which, double* out) {
+  if (which < 0 || which > 3) return BQO_EINVAL;
+  const double* Pn = d->P[d->n % 3];
+  const double* Qn = d->Q[d->n % 3];
+  for (int j = 0; j < d->ny; ++j)
+    for (int i = 0; i < d->nx; ++i) {
+      const size_t q = II(d, i, j);
+      double v;
+      if (which == 0) v = d->Ax[q] * Pn[CI(d, i - 1, j)] + d->Bx[q] * Pn[CI(d, i, j)] + d->Cx[q] * Pn[CI(d, i + 1, j)];
+      else if (which == 1) v = d->Ay[q] * Qn[CI(d, i, j - 1)] + d->By[q] * Qn[CI(d, i, j)] + d->Cy[q] * Qn[CI(d, i, j + 1)];
+      else if (which == 2) v = fstar(d, Qn, i, j);
+      else v = gstar(d, Pn, i, j);
+      out[q] = v;
+    }
+  return BQO_OK;
+}
+
+int bqo_plant_depth_gradient_scale(bqo_domain* d, double scale) {
+  depth_gradient_and_coefficients(d, scale);
+  return BQO_OK;
 }
 
 /* ------------------------------------------------------------------------ */

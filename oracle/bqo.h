@@ -103,6 +103,14 @@ int bqo_info_get(bqo_domain* d, bqo_info* out);
 int bqo_read(bqo_domain* d, int32_t which, double* out);
 /* spatial operator at the current state: E, F, G (Eq. 11-13), interior */
 int bqo_rhs(bqo_domain* d, double* E, double* F, double* G);
+/* operators of the current state, interior: which 0 U*^n (Eq. 9 as the row
+ * of Eq. 19 with the coefficients of Eq. 21), 1 V*^n (Eq. 10 / 20),
+ * 2 F*(Q^n) (Eq. 14), 3 G*(P^n) (Eq. 15) */
+int bqo_operator(bqo_domain* d, int32_t which, double* out);
+/* PLANTED MISTAKE for the pin tests only: multiply the depth gradient
+ * d_x, d_y wherever it enters (Eq. 12-15 and the dd/(6 dalpha) terms of
+ * Eq. 21) by `scale`; 1 restores the method */
+int bqo_plant_depth_gradient_scale(bqo_domain* d, double scale);
 /* west ghost values at time t (wavemaker or time series): out = eta and P
  * of ghost cell -1, then of ghost cell -2 */
 int bqo_west_ghosts(bqo_domain* d, double t, double out[4]);

@@ -79,6 +79,8 @@ def lib():
         L.bqo_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
         L.bqo_rhs.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.bqo_wave_numbers.argtypes = [ctypes.c_void_p, dp]
+        L.bqo_operator.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
+        L.bqo_plant_depth_gradient_scale.argtypes = [ctypes.c_void_p, ctypes.c_double]
         L.bqo_west_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
         L.bqo_ab3_alpha.argtypes = [ctypes.c_double] * 3 + [dp]
         L.bqo_am_weights.argtypes = [ctypes.c_int64] + [ctypes.c_double] * 3 + [dp]
@@ -289,6 +291,19 @@ class OracleDomain:
         E, F, G = (np.zeros((self.ny, self.nx)) for _ in range(3))
         lib().bqo_rhs(self._h, _ptr(E), _ptr(F), _ptr(G))
         return E, F, G
+
+    def operator(self, which: str) -> np.ndarray:
+        """U* (Eq. 9 as the row of Eq. 19), V* (Eq. 10), Fstar (Eq. 14) or
+        Gstar (Eq. 15) of the current state, interior"""
+        idx = {"U*": 0, "V*": 1, "Fstar": 2, "Gstar": 3}[which]
+        out = np.zeros((self.ny, self.nx))
+        if lib().bqo_operator(self._h, idx, _ptr(out)) != OK:
+            raise ValueError(which)
+        return out
+
+    def plant_depth_gradient_scale(self, scale: float):
+        """test-only planted mistake: scale d_x, d_y wherever they enter"""
+        lib().bqo_plant_depth_gradient_scale(self._h, float(scale))
 
     def wave_numbers(self) -> np.ndarray:
         out = np.zeros(max(1, len(self._amp)))

@@ -63,7 +63,7 @@ class Tune(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["bq_abi_version", "bq_last_error", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
+EXPORTS = ["bq_abi_version", "bq_last_error", "bq_live_handles", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
            "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
            "bq_batch_create", "bq_batch_set", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
            "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps",
@@ -85,6 +85,7 @@ def load(path: str | None = None):
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
     L.bq_abi_version.restype = ctypes.c_int
     L.bq_last_error.restype = ctypes.c_char_p
+    L.bq_live_handles.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     L.bq_params_default.argtypes = [ctypes.POINTER(Params)]
     L.bq_params_default.restype = None
     L.bq_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
@@ -386,6 +387,13 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def live_handles() -> dict:
+    """library-created streams, events and graph executables still alive"""
+    c = (ctypes.c_int32 * 3)()
+    _check(load().bq_live_handles(c))
+    return {"streams": c[0], "events": c[1], "graphs": c[2]}
 
 
 def domain_from_spec(spec: dict, precision: int = FP64, stream=None) -> Domain:

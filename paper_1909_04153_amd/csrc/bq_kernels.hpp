@@ -170,8 +170,12 @@ template <> __device__ __forceinline__ float frcp<float>(float x) { return __bui
 // a / b: correctly rounded in FP64, reciprocal-multiply in FP32
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// The hardware log takes a subnormal input as 0 (giving +inf here, and a
+// NaN once multiplied by the zero velocity of a film that thin): depths are
+// raised to the smallest normal value first, which leaves h^(-1/3) finite
+// (< 5e12) for every h > 0.
 template <> __device__ __forceinline__ float frcbrt<float>(float x) {
-  return __builtin_amdgcn_exp2f(-0.33333333f * __builtin_amdgcn_logf(x));
+  return __builtin_amdgcn_exp2f(-0.33333333f * __builtin_amdgcn_logf(__builtin_fmaxf(x, 1.17549435e-38f)));
 }
 
 // generalised minmod of three values: the one nearest zero when all three
@@ -1088,7 +1092,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   __syncthreads();
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
-  const T B = D.B, Bc = D.Bc, gn2 = D.gn2, cf = D.cf;
+  const T B = D.B, gn2 = D.gn2, cf = D.cf;
   const T a0 = (T)(CORR ? st->gamma[0] : st->alpha[0]);
   T* const wn = uni(CORR ? D.w[par ^ 1] : (D.corrector ? D.w[2] : D.w[par ^ 1]));
   const T* const wbase = uni((const T*)D.w[par]);   // w^n (the corrector's base)

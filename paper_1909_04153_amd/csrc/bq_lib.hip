@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "bq.h"
@@ -62,6 +63,38 @@ static int fail(int code, const char* fmt, ...) {
 
 static size_t rup(size_t v, size_t a) { return (v + a - 1) / a * a; }
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Streams, events and graph executables the library creates, counted while
+// alive (bq_live_handles), so a test can check that freeing a batch or a
+// domain releases everything it made.
+static std::atomic<int> g_live[3];   // streams, events, graph execs
+static hipError_t stream_new(hipStream_t* s) {
+  const hipError_t e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+  if (e == hipSuccess) ++g_live[0];
+  return e;
+}
+static void stream_del(hipStream_t& s) {
+  if (s && hipStreamDestroy(s) == hipSuccess) --g_live[0];
+  s = nullptr;
+}
+static hipError_t event_new(hipEvent_t* ev, bool timing) {
+  const hipError_t e = timing ? hipEventCreate(ev) : hipEventCreateWithFlags(ev, hipEventDisableTiming);
+  if (e == hipSuccess) ++g_live[1];
+  return e;
+}
+static void event_del(hipEvent_t& ev) {
+  if (ev && hipEventDestroy(ev) == hipSuccess) --g_live[1];
+  ev = nullptr;
+}
+static hipError_t graph_new(hipGraphExec_t* x, hipGraph_t g) {
+  const hipError_t e = hipGraphInstantiate(x, g, nullptr, nullptr, 0);
+  if (e == hipSuccess) ++g_live[2];
+  return e;
+}
+static void graph_del(hipGraphExec_t& x) {
+  if (x && hipGraphExecDestroy(x) == hipSuccess) --g_live[2];
+  x = nullptr;
+}
 
 // ---------------------------------------------------------------------------
 // set-up kernels
@@ -753,17 +786,15 @@ static int run_steps(Launch& L, hipStream_t s, int n_steps, int graph_steps) {
   int left = n_steps;
   // graphs cannot be captured on the legacy null stream
   if (graph_steps > 0 && s != nullptr && n_steps >= graph_steps) {
-    if (L.graph && L.graph_built != graph_steps) {
-      HIPCHK(hipGraphExecDestroy(L.graph));
-      L.graph = nullptr;
-    }
+    if (L.graph && L.graph_built != graph_steps) graph_del(L.graph);
     if (!L.graph) {
       hipGraph_t g;
       HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < graph_steps; ++k) enqueue_step<T>(L, s, 0.0);
       HIPCHK(hipStreamEndCapture(s, &g));
-      HIPCHK(hipGraphInstantiate(&L.graph, g, nullptr, nullptr, 0));
-      HIPCHK(hipGraphDestroy(g));
+      const hipError_t ie = graph_new(&L.graph, g);
+      (void)hipGraphDestroy(g);
+      HIPCHK(ie);
       L.graph_built = graph_steps;
     }
     while (left >= graph_steps) {
@@ -781,8 +812,12 @@ template <typename T>
 static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
-  hipEvent_t ev[8];
-  for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&ev[k]));
+  hipEvent_t ev[8] = {};
+  for (int k = 0; k < 8; ++k)
+    if (event_new(&ev[k], true) != hipSuccess) {
+      for (hipEvent_t& e : ev) event_del(e);
+      return fail(BQ_EDEVICE, "hipEventCreate");
+    }
   double acc[4] = {0, 0, 0, 0};
   int rc = BQ_OK;
   const int last = L.any_pc ? 7 : 4;
@@ -813,7 +848,7 @@ static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
     }
   }
   enqueue_commit<T>(L, s);
-  for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[k]);
+  for (hipEvent_t& e : ev) event_del(e);
   if (rc) return rc;
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -925,8 +960,7 @@ static int load_t(bq_domain* d, const void* host, size_t bytes) {
 
 template <typename T>
 static void drop_graph(Launch& L) {
-  if (L.graph) (void)hipGraphExecDestroy(L.graph);
-  L.graph = nullptr;
+  graph_del(L.graph);
   L.graph_built = 0;
 }
 
@@ -1033,10 +1067,10 @@ static int batch_build_t(bq_batch* b) {
     if (rc) return rc;
     // the lane streams are created together, one after the other
     for (int l = 0; l < MAX_LANES; ++l)
-      if (!b->lane[l]) HIPCHK(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
-    if (!b->ev_fork) HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+      if (!b->lane[l]) HIPCHK(stream_new(&b->lane[l]));
+    if (!b->ev_fork) HIPCHK(event_new(&b->ev_fork, false));
     for (int l = 0; l < MAX_LANES; ++l)
-      if (!b->ev_join[l]) HIPCHK(hipEventCreateWithFlags(&b->ev_join[l], hipEventDisableTiming));
+      if (!b->ev_join[l]) HIPCHK(event_new(&b->ev_join[l], false));
   }
   HIPCHK(hipStreamSynchronize(b->stream));
   return BQ_OK;
@@ -1077,9 +1111,14 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const int nl = b->lanes;
   hipStream_t* ss = b->lane;
-  hipEvent_t ev[MAX_LANES][8];
+  hipEvent_t ev[MAX_LANES][8] = {};
   for (int l = 0; l < nl; ++l)
-    for (int k = 0; k < 8; ++k) HIPCHK(hipEventCreate(&ev[l][k]));
+    for (int k = 0; k < 8; ++k)
+      if (event_new(&ev[l][k], true) != hipSuccess) {
+        for (auto& row : ev)
+          for (hipEvent_t& e : row) event_del(e);
+        return fail(BQ_EDEVICE, "hipEventCreate");
+      }
   double acc[4] = {0, 0, 0, 0};
   bool pc = false;
   for (int l = 0; l < nl; ++l) pc |= b->G[l].any_pc != 0;
@@ -1126,8 +1165,8 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   }
   for (int l = 0; l < nl; ++l) enqueue_commit<T>(b->G[l], ss[l]);
   const int rj = join_lanes(b);
-  for (int l = 0; l < nl; ++l)
-    for (int k = 0; k < 8; ++k) (void)hipEventDestroy(ev[l][k]);
+  for (auto& row : ev)
+    for (hipEvent_t& e : row) event_del(e);
   if (rc) return rc;
   if (rj) return rj;
   HIPCHK(hipGetLastError());
@@ -1157,8 +1196,7 @@ static void apply_schedule(bq_batch* b, int rblock, int swizzle, int segs) {
     L->swizzle = swizzle;
     L->segs = segs;
     // graphs hold the launch parameters they were captured with
-    if (L->graph) (void)hipGraphExecDestroy(L->graph);
-    L->graph = nullptr;
+    graph_del(L->graph);
   }
 }
 
@@ -1196,9 +1234,11 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
       for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 1, 0.0});
       for (int ns : {4, 8}) cands.push_back(bq_tune{lanes, graph, 256, 1, ns, 0.0});
     }
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (event_new(&e0, true) != hipSuccess || event_new(&e1, true) != hipSuccess) {
+    event_del(e0);
+    return fail(BQ_EDEVICE, "hipEventCreate");
+  }
   int rc = BQ_OK;
   auto trial = [&](bq_tune& c) -> int {
     int r = set_tune(b, &c);
@@ -1220,8 +1260,8 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   // settling) cancels instead of favouring the first candidates
   for (size_t k = 0; k < cands.size() && rc == BQ_OK; ++k) rc = trial(cands[k]);
   for (size_t k = cands.size(); k-- > 0 && rc == BQ_OK;) rc = trial(cands[k]);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  event_del(e0);
+  event_del(e1);
   if (rc) return rc;
   if (getenv("BQ_TUNE_LOG"))
     for (const bq_tune& c : cands)
@@ -1245,6 +1285,12 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
 extern "C" {
 
 int bq_abi_version(void) { return BQ_ABI_VERSION; }
+
+int bq_live_handles(int32_t* counts) {
+  if (!counts) return fail(BQ_EINVAL, "NULL argument");
+  for (int k = 0; k < 3; ++k) counts[k] = g_live[k].load();
+  return BQ_OK;
+}
 
 const char* bq_last_error(void) { return g_err; }
 
@@ -1320,7 +1366,7 @@ int bq_domain_create(const bq_params* p, const double* depth_c, void* dev_worksp
 
 int bq_domain_free(bq_domain* d) {
   if (!d) return fail(BQ_EINVAL, "NULL domain");
-  if (d->L.graph) (void)hipGraphExecDestroy(d->L.graph);
+  graph_del(d->L.graph);
   delete d;
   return BQ_OK;
 }
@@ -1456,13 +1502,12 @@ int bq_batch_free(bq_batch* b) {
   (void)hipStreamSynchronize(b->stream);
   for (hipStream_t ls : b->lane)
     if (ls) (void)hipStreamSynchronize(ls);
-  if (b->L.graph) (void)hipGraphExecDestroy(b->L.graph);
-  for (int l = 0; l < 2; ++l)
-    if (b->G[l].graph) (void)hipGraphExecDestroy(b->G[l].graph);
-  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
-  for (int l = 0; l < 2; ++l) {
-    if (b->ev_join[l]) (void)hipEventDestroy(b->ev_join[l]);
-    if (b->lane[l]) (void)hipStreamDestroy(b->lane[l]);
+  graph_del(b->L.graph);
+  event_del(b->ev_fork);
+  for (int l = 0; l < MAX_LANES; ++l) {
+    graph_del(b->G[l].graph);
+    event_del(b->ev_join[l]);
+    stream_del(b->lane[l]);
   }
   if (b->mem) (void)hipFree(b->mem);
   delete b;
