@@ -21,10 +21,22 @@
  *   KP07 face flux (Sec. 3.1, reading) ............ pinned: physical flux of a
  *       uniform state, hydrostatic lake-at-rest flux, dry|dry = 0, mirror
  *       symmetry.
+ *   operators of Eq. 9-10, 12-15 .................. pinned: second-order
+ *       convergence of U*, V*, F*, G* and of the dispersive parts of F, G
+ *       (bed-slope terms included) to their continuous expressions on
+ *       smooth analytic fields; swapped or dropped d_x, d_y terms fail it;
+ *       linear shoaling up a 1:30 slope follows the energy flux.  The
+ *       four-corner cross differences are taken as the difference of two
+ *       one-sided differences, so they vanish exactly on fields uniform in
+ *       either direction: pinned by bit-for-bit transposition symmetry of
+ *       the step.
+ *   energy sum (diagnostic) ........................ pinned: closed forms.
  *   full step (Eq. 5-15, 19-22, 42-47) ............ pinned: lake at rest on an
  *       uneven bed, closed-basin mass, Madsen-Sorensen linear dispersion,
  *       solitary-wave propagation, third-order temporal convergence on a
- *       y-uniform case, Ritter dam break in the NLSW limit (d = 0).
+ *       y-uniform case, Ritter dam break in the NLSW limit (d = 0);
+ *       single 2D modes grow at the spectral radius of the step's Fourier
+ *       symbol (linear stability of Eq. 16-17 and of the linear reading).
  *   friction, Manning and quadratic (Sec. 5.3-5.4 reading) ... pinned: decay
  *       of a uniform current against the closed form P0 / (1 + k P0 t).
  *   time-series boundary (Sec. 3.3 reading) ....... pinned: exact linear
@@ -720,7 +732,7 @@ static void compute_rhs(const bqo_domain* d, const double* P, const double* Q, d
 #define ETA(a, b) ((w[CI(d, i + (a), j + (b))] - d->bbar[CI(d, i + (a), j + (b))]) - d->dep[CI(d, i + (a), j + (b))])
         const double exx = (ETA(1, 0) - 2.0 * ETA(0, 0) + ETA(-1, 0)) / (dx * dx);
         const double eyy = (ETA(0, 1) - 2.0 * ETA(0, 0) + ETA(0, -1)) / (dy * dy);
-        const double exy = (ETA(1, 1) - ETA(1, -1) - ETA(-1, 1) + ETA(-1, -1)) / (4.0 * dx * dy);
+        const double exy = ((ETA(1, 1) - ETA(1, -1)) - (ETA(-1, 1) - ETA(-1, -1))) / (4.0 * dx * dy);
         const double exxx = (ETA(2, 0) - 2.0 * ETA(1, 0) + 2.0 * ETA(-1, 0) - ETA(-2, 0)) / (2.0 * dx * dx * dx);
         const double eyyy = (ETA(0, 2) - 2.0 * ETA(0, 1) + 2.0 * ETA(0, -1) - ETA(0, -2)) / (2.0 * dy * dy * dy);
         const double exyy = ((ETA(1, 1) - 2.0 * ETA(1, 0) + ETA(1, -1)) - (ETA(-1, 1) - 2.0 * ETA(-1, 0) + ETA(-1, -1))) /
@@ -772,7 +784,7 @@ static double fstar(const bqo_domain* d, const double* Q, int i, int j) {
   const double dx = d->p.dx, dy = d->p.dy;
   const double qy = (Q[CI(d, i, j + 1)] - Q[CI(d, i, j - 1)]) / (2.0 * dy);
   const double qx = (Q[CI(d, i + 1, j)] - Q[CI(d, i - 1, j)]) / (2.0 * dx);
-  const double qxy = (Q[CI(d, i + 1, j + 1)] - Q[CI(d, i + 1, j - 1)] - Q[CI(d, i - 1, j + 1)] + Q[CI(d, i - 1, j - 1)]) /
+  const double qxy = ((Q[CI(d, i + 1, j + 1)] - Q[CI(d, i + 1, j - 1)]) - (Q[CI(d, i - 1, j + 1)] - Q[CI(d, i - 1, j - 1)])) /
                      (4.0 * dx * dy);
   return dd * dX * qy / 6.0 + dd * dY * qx / 6.0 + (d->p.B + 1.0 / 3.0) * dd * dd * qxy;
 }
@@ -782,7 +794,7 @@ static double gstar(const bqo_domain* d, const double* P, int i, int j) {
   const double dx = d->p.dx, dy = d->p.dy;
   const double py = (P[CI(d, i, j + 1)] - P[CI(d, i, j - 1)]) / (2.0 * dy);
   const double px = (P[CI(d, i + 1, j)] - P[CI(d, i - 1, j)]) / (2.0 * dx);
-  const double pxy = (P[CI(d, i + 1, j + 1)] - P[CI(d, i + 1, j - 1)] - P[CI(d, i - 1, j + 1)] + P[CI(d, i - 1, j - 1)]) /
+  const double pxy = ((P[CI(d, i + 1, j + 1)] - P[CI(d, i + 1, j - 1)]) - (P[CI(d, i - 1, j + 1)] - P[CI(d, i - 1, j - 1)])) /
                      (4.0 * dx * dy);
   return dd * dX * py / 6.0 + dd * dY * px / 6.0 + (d->p.B + 1.0 / 3.0) * dd * dd * pxy;
 }

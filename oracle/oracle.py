@@ -19,18 +19,36 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "bqo.c")
 _LIB = os.path.join(_HERE, "libbqo.so")
+# the same source compiled with FMA contraction: a measuring instrument for
+# how far a different (equally valid) rounding order moves the results, not
+# a second oracle
+_LIB_FMA = os.path.join(_HERE, "libbqo_fma.so")
 
 WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
 OK, EINVAL, ENONFINITE, EDTMIN, EDONE = 0, -1, -4, -5, -7
 
 
+def host_has_fma() -> bool:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return any(line.startswith("flags") and " fma" in line for line in fh)
+    except OSError:
+        return False
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain FP64, no FMA contraction)."""
+    """Compile the oracle with gcc (plain FP64, no FMA contraction), and the
+    FMA-contracted build of the same source where the host has FMA."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
                "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.check_call(cmd)
         os.replace(_LIB + ".tmp", _LIB)
+    if host_has_fma() and (force or not os.path.exists(_LIB_FMA)):
+        cmd = ["gcc", "-O2", "-ffp-contract=fast", "-mfma", "-fno-fast-math", "-std=c99", "-fPIC", "-shared",
+               "-o", _LIB_FMA + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB_FMA + ".tmp", _LIB_FMA)
     return _LIB
 
 
@@ -60,6 +78,17 @@ class _Info(ctypes.Structure):
 
 
 _lib = None
+_lib_fma = None
+
+
+def lib_fma():
+    """the FMA-contracted build (see _LIB_FMA)"""
+    global _lib_fma
+    if _lib_fma is None:
+        if not os.path.exists(_LIB_FMA):
+            build()
+        _lib_fma = _bind(ctypes.CDLL(_LIB_FMA))
+    return _lib_fma
 
 
 def lib():
@@ -67,36 +96,40 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        dp = ctypes.POINTER(ctypes.c_double)
-        L.bqo_create.restype = ctypes.c_void_p
-        L.bqo_create.argtypes = [ctypes.POINTER(_Params), dp]
-        L.bqo_free.argtypes = [ctypes.c_void_p]
-        L.bqo_set_state.argtypes = [ctypes.c_void_p, dp, dp, dp]
-        L.bqo_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
-        L.bqo_step_dt.argtypes = [ctypes.c_void_p, ctypes.c_double]
-        L.bqo_info_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Info)]
-        L.bqo_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
-        L.bqo_rhs.argtypes = [ctypes.c_void_p, dp, dp, dp]
-        L.bqo_wave_numbers.argtypes = [ctypes.c_void_p, dp]
-        L.bqo_operator.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
-        L.bqo_plant_depth_gradient_scale.argtypes = [ctypes.c_void_p, ctypes.c_double]
-        L.bqo_west_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
-        L.bqo_ab3_alpha.argtypes = [ctypes.c_double] * 3 + [dp]
-        L.bqo_am_weights.argtypes = [ctypes.c_int64] + [ctypes.c_double] * 3 + [dp]
-        L.bqo_fd_weights.argtypes = [ctypes.c_double] * 2 + [dp]
-        L.bqo_step_weights.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_double] * 3 + [dp, dp]
-        L.bqo_lazy_ema.restype = ctypes.c_double
-        L.bqo_lazy_ema.argtypes = [ctypes.c_double] * 3
-        L.bqo_thomas.argtypes = [ctypes.c_int32, dp, dp, dp, dp, dp]
-        L.bqo_solve_line.argtypes = [ctypes.c_int32, dp, dp, dp, dp, dp]
-        L.bqo_minmod.restype = ctypes.c_double
-        L.bqo_minmod.argtypes = [ctypes.c_double] * 3
-        L.bqo_ms_wavenumber.restype = ctypes.c_double
-        L.bqo_ms_wavenumber.argtypes = [ctypes.c_double] * 4
-        L.bqo_face_flux_const.argtypes = [ctypes.c_double] * 9 + [dp]
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+def _bind(L):
+    """argument and result types of the oracle's exported functions"""
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.bqo_create.restype = ctypes.c_void_p
+    L.bqo_create.argtypes = [ctypes.POINTER(_Params), dp]
+    L.bqo_free.argtypes = [ctypes.c_void_p]
+    L.bqo_set_state.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    L.bqo_step.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    L.bqo_step_dt.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    L.bqo_info_get.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Info)]
+    L.bqo_read.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
+    L.bqo_rhs.argtypes = [ctypes.c_void_p, dp, dp, dp]
+    L.bqo_wave_numbers.argtypes = [ctypes.c_void_p, dp]
+    L.bqo_operator.argtypes = [ctypes.c_void_p, ctypes.c_int32, dp]
+    L.bqo_plant_depth_gradient_scale.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    L.bqo_west_ghosts.argtypes = [ctypes.c_void_p, ctypes.c_double, dp]
+    L.bqo_ab3_alpha.argtypes = [ctypes.c_double] * 3 + [dp]
+    L.bqo_am_weights.argtypes = [ctypes.c_int64] + [ctypes.c_double] * 3 + [dp]
+    L.bqo_fd_weights.argtypes = [ctypes.c_double] * 2 + [dp]
+    L.bqo_step_weights.argtypes = [ctypes.c_int64, ctypes.c_int32] + [ctypes.c_double] * 3 + [dp, dp]
+    L.bqo_lazy_ema.restype = ctypes.c_double
+    L.bqo_lazy_ema.argtypes = [ctypes.c_double] * 3
+    L.bqo_thomas.argtypes = [ctypes.c_int32, dp, dp, dp, dp, dp]
+    L.bqo_solve_line.argtypes = [ctypes.c_int32, dp, dp, dp, dp, dp]
+    L.bqo_minmod.restype = ctypes.c_double
+    L.bqo_minmod.argtypes = [ctypes.c_double] * 3
+    L.bqo_ms_wavenumber.restype = ctypes.c_double
+    L.bqo_ms_wavenumber.argtypes = [ctypes.c_double] * 4
+    L.bqo_face_flux_const.argtypes = [ctypes.c_double] * 9 + [dp]
+    return L
 
 
 def _ptr(a: np.ndarray):
@@ -198,7 +231,8 @@ class OracleDomain:
     (ny+1, nx+1) still-water depth at cell corners.
     """
 
-    def __init__(self, params: dict, depth_c: np.ndarray):
+    def __init__(self, params: dict, depth_c: np.ndarray, fma: bool = False):
+        self._L = lib_fma() if fma else lib()
         p = _Params()
         p.nx, p.ny = int(params["nx"]), int(params["ny"])
         p.dx, p.dy = float(params["dx"]), float(params["dy"])
@@ -241,13 +275,13 @@ class OracleDomain:
         assert dc.shape == (p.ny + 1, p.nx + 1), dc.shape
         self._p = p
         self.nx, self.ny = p.nx, p.ny
-        self._h = lib().bqo_create(ctypes.byref(p), _ptr(dc))
+        self._h = self._L.bqo_create(ctypes.byref(p), _ptr(dc))
         if not self._h:
             raise ValueError("bqo_create rejected the parameters")
 
     def close(self):
         if self._h:
-            lib().bqo_free(self._h)
+            self._L.bqo_free(self._h)
             self._h = None
 
     def __del__(self):
@@ -258,17 +292,17 @@ class OracleDomain:
 
     def set_state(self, eta, P, Q) -> int:
         eta, P, Q = (_f64(v).reshape(self.ny, self.nx) for v in (eta, P, Q))
-        return lib().bqo_set_state(self._h, _ptr(eta), _ptr(P), _ptr(Q))
+        return self._L.bqo_set_state(self._h, _ptr(eta), _ptr(P), _ptr(Q))
 
     def step(self, n: int = 1) -> int:
-        return lib().bqo_step(self._h, int(n))
+        return self._L.bqo_step(self._h, int(n))
 
     def step_dt(self, dt: float) -> int:
-        return lib().bqo_step_dt(self._h, float(dt))
+        return self._L.bqo_step_dt(self._h, float(dt))
 
     def info(self) -> OracleInfo:
         i = _Info()
-        lib().bqo_info_get(self._h, ctypes.byref(i))
+        self._L.bqo_info_get(self._h, ctypes.byref(i))
         return OracleInfo(i.t, i.n, i.dt_last, i.dt_prev1, i.dt_prev2, i.smax, i.mass, i.energy, i.status)
 
     def read(self, which: str) -> np.ndarray:
@@ -276,20 +310,20 @@ class OracleDomain:
         inundated); cfl (local CFL number of Eq. 22 with the last step)"""
         idx = {"eta": 0, "P": 1, "Q": 2, "w": 3, "runup": 4, "cfl": 5}[which]
         out = np.zeros((self.ny, self.nx))
-        if lib().bqo_read(self._h, idx, _ptr(out)) != OK:
+        if self._L.bqo_read(self._h, idx, _ptr(out)) != OK:
             raise ValueError(f"bqo_read({which}) rejected")
         return out
 
     def west_ghosts(self, t: float) -> np.ndarray:
         """(eta, P) of west ghost cell -1, then of ghost cell -2, at time t"""
         out = np.zeros(4)
-        if lib().bqo_west_ghosts(self._h, float(t), _ptr(out)) != OK:
+        if self._L.bqo_west_ghosts(self._h, float(t), _ptr(out)) != OK:
             raise ValueError("the west side is not a prescribed boundary")
         return out
 
     def rhs(self):
         E, F, G = (np.zeros((self.ny, self.nx)) for _ in range(3))
-        lib().bqo_rhs(self._h, _ptr(E), _ptr(F), _ptr(G))
+        self._L.bqo_rhs(self._h, _ptr(E), _ptr(F), _ptr(G))
         return E, F, G
 
     def operator(self, which: str) -> np.ndarray:
@@ -297,15 +331,15 @@ class OracleDomain:
         Gstar (Eq. 15) of the current state, interior"""
         idx = {"U*": 0, "V*": 1, "Fstar": 2, "Gstar": 3}[which]
         out = np.zeros((self.ny, self.nx))
-        if lib().bqo_operator(self._h, idx, _ptr(out)) != OK:
+        if self._L.bqo_operator(self._h, idx, _ptr(out)) != OK:
             raise ValueError(which)
         return out
 
     def plant_depth_gradient_scale(self, scale: float):
         """test-only planted mistake: scale d_x, d_y wherever they enter"""
-        lib().bqo_plant_depth_gradient_scale(self._h, float(scale))
+        self._L.bqo_plant_depth_gradient_scale(self._h, float(scale))
 
     def wave_numbers(self) -> np.ndarray:
         out = np.zeros(max(1, len(self._amp)))
-        lib().bqo_wave_numbers(self._h, _ptr(out))
+        self._L.bqo_wave_numbers(self._h, _ptr(out))
         return out[: len(self._amp)]

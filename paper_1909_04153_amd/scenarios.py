@@ -187,6 +187,71 @@ def conical_island(nx=601, ny=601, dx=0.05, depth=0.32, rel_height=0.18, r_top=1
                 center=(xc, yc), shore_radius=r_top + (island_h - depth) / island_slope)
 
 
+def airy_wavenumber(omega, h):
+    """Wave number of linear (Airy) theory, omega^2 = g k tanh(k h), by Newton
+    iteration on a table of depths interpolated to the given ones (used only
+    to lay a plausible wave field over an initial state; the solver's own
+    relation is not used here)."""
+    h = np.maximum(np.asarray(h, dtype=np.float64), 1e-3)
+    tab = np.geomspace(1e-3, max(float(np.max(h)), 2e-3), 4096)
+    k = omega / np.sqrt(G * tab)
+    for _ in range(40):
+        t = np.tanh(k * tab)
+        f = G * k * t - omega * omega
+        df = G * t + G * k * tab * (1.0 - t * t)
+        k = k - f / df
+    return np.interp(h, tab, k)
+
+
+def spun_up(spec, h_taper=(0.3, 0.1), ramp_off=True):
+    """The scenario with its west wavemaker's wave train already in the
+    domain at t = 0: eta = A sum_m a_m sin(phi_m - theta_m), theta_m the
+    integral along x of the local Airy wave number of component m, flux
+    P = (omega_m / k_m) eta_m (waves travelling east), Q = 0.  The envelope A
+    falls from 1 to 0 (sin^2) where the still-water depth drops from
+    h_taper[0] to h_taper[1] (relative to the offshore depth), so the train
+    stops short of the shoreline.  ramp_off: no start-up ramp, so the
+    wavemaker's values continue the field at the boundary."""
+    out = dict(spec)
+    p = dict(spec["params"])
+    if ramp_off:
+        p["wave_ramp"] = 0.0
+    out["params"] = p
+    nx, ny, dx = p["nx"], p["ny"], p["dx"]
+    dc = spec["depth_c"]
+    dcell = 0.25 * (dc[:-1, :-1] + dc[1:, :-1] + dc[:-1, 1:] + dc[1:, 1:])
+    h0 = float(np.max(dcell[:, 0]))
+    z = np.clip((dcell / h0 - h_taper[1]) / (h_taper[0] - h_taper[1]), 0.0, 1.0)
+    # the envelope also stays 0 beyond the first cell that falls below the
+    # taper's lower end, so no wave is laid behind a bar or on land
+    blocked = np.cumsum(dcell / h0 <= h_taper[1], axis=1) > 0
+    A = np.where(blocked, 0.0, np.sin(0.5 * math.pi * z) ** 2)
+    eta = np.zeros((ny, nx))
+    P = np.zeros((ny, nx))
+    amps, oms = p.get("wave_amp", []), p.get("wave_omega", [])
+    phs = p.get("wave_phase", [0.0] * len(amps))
+    for a, om, ph in zip(amps, oms, phs):
+        k = airy_wavenumber(om, dcell)
+        theta = np.cumsum(k, axis=1) * dx - 0.5 * k * dx   # integral to the cell centre
+        e = a * A * np.sin(ph - theta)
+        eta += e
+        P += (om / k) * e
+    out["eta"], out["P"], out["Q"] = eta, P, np.zeros_like(eta)
+    out["name"] = spec["name"] + "_spun_up"
+    return out
+
+
+def transposed_solitary(nx=64, ny=1536, dx=0.05, depth=1.0, amp=0.1, y0=8.0, **kw):
+    """C1's solitary wave travelling north along a channel of ny cells: the
+    y-lines carry the wave (many chunks per line)."""
+    p = base_params(nx, ny, dx, **kw)
+    depth_c = np.full((ny + 1, nx + 1), float(depth))
+    _, Y = cell_coords(nx, ny, dx, p["dy"])
+    eta, Q = solitary_profile(Y, y0, amp, depth)
+    return dict(name=f"solitary_north_{nx}x{ny}", params=p, depth_c=depth_c, eta=eta, P=np.zeros_like(eta),
+                Q=Q)
+
+
 def rip_beach_scaled(nx, ny, seed=190904153, **kw):
     """rip_beach geometry scaled to an nx x ny grid covering the same 1024 m
     cross-shore extent (for parity tests at small sizes)."""

@@ -1,14 +1,19 @@
 """Parity of the HIP path (through the C ABI) with the CPU oracle.
 
-FP64: relative L2 error per field <= 1e-12 after every compared step.  FP32:
-eta within 1e-4 relative L2 after 1000 steps on non-breaking cases.
+FP64: relative L2 error per field <= 1e-12 after every compared step, and
+the largest pointwise difference <= 10 x that bar times the field's natural
+scale.  FP32: eta within 1e-4 relative L2 after 1000 steps on non-breaking
+cases.
 
 The relative error divides by max(||ref||, 0.1 s sqrt(N)), s the field's
 natural scale in the case (wave amplitude for eta, amplitude times the
 long-wave speed for P and Q): while a field is far below its natural size
 (the first steps behind a ramped wavemaker, a standing wave's flux passing
-through zero in time) the comparison is against 10 % of that size, not
-against the roundoff of the oracle's own FP64 cancellations.
+through zero in time) the comparison is against 10 % of that size.  The
+floor is measured, not assumed: the oracle compiled with FMA contraction
+differs from the plain build by 1.06e-12 on the central-slopes standing wave
+under a 1 % floor (the bar itself) and by 1.2e-13 under 10 %
+(tests/test_oracle_rounding.py).
 """
 import math
 
@@ -46,6 +51,11 @@ def rel(a, b, scale=0.0):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 0.1 * scale * math.sqrt(b.size), 1e-300))
 
 
+def maxrel(a, b, scale):
+    """largest pointwise difference over the field's natural scale"""
+    return float(np.max(np.abs(a - b))) / scale
+
+
 def pair(bq, spec, precision):
     o = OracleDomain(spec["params"], spec["depth_c"])
     assert o.set_state(spec["eta"], spec["P"], spec["Q"]) == 0
@@ -57,7 +67,7 @@ def run_compare(bq, spec, steps, every, tol, precision=None, fields=FIELDS):
     precision = bq.FP64 if precision is None else precision
     o, g = pair(bq, spec, precision)
     sc = scales(spec)
-    worst = 0.0
+    worst = worst_max = 0.0
     done = 0
     while done < steps:
         k = min(every, steps - done)
@@ -69,9 +79,12 @@ def run_compare(bq, spec, steps, every, tol, precision=None, fields=FIELDS):
         assert gi.n == oi.n == done
         assert abs(gi.t - oi.t) <= 1e-12 * oi.t
         for f in fields:
-            e = rel(g.read(f), o.read(f), sc[f])
-            worst = max(worst, e)
-            assert e <= tol, f"{spec.get('name')} step {done} field {f}: rel L2 {e:.3e} > {tol:.1e}"
+            a, b = g.read(f), o.read(f)
+            e, m = rel(a, b, sc[f]), maxrel(a, b, sc[f])
+            worst, worst_max = max(worst, e), max(worst_max, m)
+            assert e <= tol, f"{spec.get('name')} step {done} field {f}: rel L2 {e:.3e} > {tol:.1e} (max {m:.2e})"
+            assert m <= 10 * tol, f"{spec.get('name')} step {done} field {f}: max {m:.3e} > {10 * tol:.1e} (L2 {e:.2e})"
+    print(f"{spec.get('name')}: worst rel L2 {worst:.2e}, worst max/scale {worst_max:.2e}")
     return worst, o, g
 
 
@@ -84,6 +97,10 @@ def test_fp64_solitary_flat_full_config(bq):
     gi, oi = g.sync(), o.info()
     assert abs(gi.mass - oi.mass) <= 1e-12 * oi.mass
     assert abs(gi.dt_last - oi.dt_last) <= 1e-12 * oi.dt_last
+    # the FP64 energy diagnostic (a fixed-order tree on the GPU, row-major
+    # order in the oracle)
+    print(f"solitary 200x20 energy GPU {gi.energy:.15e} oracle {oi.energy:.15e}")
+    assert oi.energy > 0 and abs(gi.energy - oi.energy) <= 1e-12 * oi.energy
 
 
 CASES = {
@@ -161,8 +178,10 @@ def test_fp32_eta_after_1000_steps(bq, case):
     assert g.sync().status == 0
     sc = scales(spec)
     errs = {f: rel(g.read(f), o.read(f), sc[f]) for f in FIELDS}
-    print(f"{case} FP32 after 1000 steps: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
-    assert errs["eta"] <= 1e-4
+    mx = maxrel(g.read("eta"), o.read("eta"), sc["eta"])
+    print(f"{case} FP32 after 1000 steps: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) +
+          f"; eta max/scale {mx:.2e}")
+    assert errs["eta"] <= 1e-4 and mx <= 1e-3
 
 
 def test_fp32_solitary_config_reported(bq):
@@ -196,6 +215,74 @@ def test_fp32_full_size_rip_beach_first_steps(bq):
         e = rel(g.read(f), o.read(f), sc[f])
         print(f"rip 2048^2 FP32 2 steps {f} {e:.2e}")
         assert e <= 1e-4
+
+
+def test_fp64_full_size_beach_active_waves(bq):
+    """1024 x 256 beach (dx 0.1 m, 0.5 m deep, 1:20 to dry land, sine source
+    T = 2 s, a = 0.02 m, Manning 0.015) with the wave train already in the
+    domain, tapered to zero 0.1 m before the shoreline, so the front runs up
+    the dry beach within the compared steps: 300 steps against the oracle,
+    every 10th, plus mass and energy."""
+    spec = S.spun_up(S.sloping_beach(), h_taper=(0.12, 0.01))
+    worst, o, g = run_compare(bq, spec, 300, 10, 1e-12)
+    gi, oi = g.sync(), o.info()
+    print(f"beach 1024x256 active FP64: mass {abs(gi.mass - oi.mass) / oi.mass:.1e}, "
+          f"energy {abs(gi.energy - oi.energy) / oi.energy:.1e} (relative differences)")
+    assert abs(gi.mass - oi.mass) <= 1e-12 * oi.mass
+    assert abs(gi.energy - oi.energy) <= 1e-12 * oi.energy
+    # the run reached land: some cells dry at rest are wet now
+    dc = spec["depth_c"]
+    land = 0.25 * (dc[:-1, :-1] + dc[1:, :-1] + dc[:-1, 1:] + dc[1:, 1:]) < 0
+    assert np.any(o.read("eta")[land] > 1e-5)
+
+
+def test_fp64_long_y_lines_active(bq):
+    """A solitary wave running north along a 64 x 1536 channel: y-lines of
+    192 chunks carry the wave (FP64, 200 steps, every 20th)."""
+    spec = S.transposed_solitary(nx=64, ny=1536)
+    run_compare(bq, spec, 200, 20, 1e-12)
+
+
+def test_fp32_full_size_rip_beach_active_waves(bq):
+    """2048 x 2048 rip-channel beach (FP32) with the 64-component JONSWAP
+    train already over the offshore flat and slope: 50 steps against the
+    oracle (eta within 1e-4)."""
+    spec = S.spun_up(S.rip_beach(cfl=0.125, fstar_order=1), h_taper=(0.4, 0.25))
+    print("rip 2048^2 spun up: |eta| max %.3f m" % float(np.max(np.abs(spec["eta"]))), flush=True)
+    o, g = pair(bq, spec, bq.FP32)
+    g.step(50)
+    assert o.step(50) == 0
+    assert g.sync().status == 0
+    sc = scales(spec)
+    errs = {f: rel(g.read(f), o.read(f), sc[f]) for f in FIELDS}
+    mx = maxrel(g.read("eta"), o.read("eta"), sc["eta"])
+    print("rip 2048^2 active FP32 after 50 steps: " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) +
+          f"; eta max/scale {mx:.2e}")
+    assert errs["eta"] <= 1e-4 and mx <= 1e-3
+
+
+def test_fp32_batch_members_1000_steps(bq):
+    """Two members of the benchmark's 64-domain batch at their full size (the
+    smallest solitary-wave and beach members, 256 x 320 each): 1000 FP32
+    steps against the oracle (eta within 1e-4)."""
+    specs = S.batch_mix(64, seed=190904154)
+
+    def cells(s):
+        return s["params"]["nx"] * s["params"]["ny"]
+
+    sol = min((s for s in specs if "solitary" in s["name"]), key=cells)
+    beach = min((s for s in specs if "solitary" not in s["name"]), key=cells)
+    for spec in (sol, beach):
+        o, g = pair(bq, spec, bq.FP32)
+        g.step(1000)
+        assert o.step(1000) == 0
+        assert g.sync().status == 0
+        sc = scales(spec)
+        errs = {f: rel(g.read(f), o.read(f), sc[f]) for f in FIELDS}
+        mx = maxrel(g.read("eta"), o.read("eta"), sc["eta"])
+        print(f"{spec['name']} FP32 after 1000 steps (t = {o.info().t:.2f} s): " +
+              " ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f"; eta max/scale {mx:.2e}", flush=True)
+        assert errs["eta"] <= 1e-4 and mx <= 1e-3
 
 
 def test_status_latching(bq):
@@ -524,9 +611,10 @@ def test_fp64_parity_segmented_line_coupling(bq, case, segs):
         b.step(10)
         b.sync()
         for f in FIELDS:
-            e = rel(g.read(f), o.read(f), sc[f])
+            a, r = g.read(f), o.read(f)
+            e, m = rel(a, r, sc[f]), maxrel(a, r, sc[f])
             worst = max(worst, e)
-            assert e <= 1e-12, (case, (k + 1) * 10, f, e)
+            assert e <= 1e-12 and m <= 1e-11, (case, (k + 1) * 10, f, e, m)
     print(f"{case} {segs} segments FP64 worst rel L2 {worst:.2e}")
     b.close()
 
