@@ -35,7 +35,8 @@
  * bq_domain_create (for instance a torch uint8 tensor on the GPU) and must
  * keep it alive until bq_domain_free.  The library allocates nothing on the
  * device for a domain beyond that workspace; a batch allocates its own small
- * descriptor tables and creates the streams and events of its lanes.  Host
+ * descriptor tables (bq_batch_set_static takes a static array instead) and
+ * creates the streams and events of its lanes.  Host
  * pointers passed in are only read during the call.
  *
  * Errors.  Every call returns 0 (BQ_OK) or a negative bq_status; nothing
@@ -54,8 +55,13 @@
 extern "C" {
 #endif
 
-#define BQ_ABI_VERSION 4
+#define BQ_ABI_VERSION 5
 #define BQ_MAX_WAVES 256
+/* Size of the per-GPU static array that holds the device tables of a batch
+ * set up by bq_batch_set_static (8 MiB: the tables take 4 bytes per tile of
+ * 64 x 16 (FP32) or 64 x 8 (FP64) cells and per grid line, plus about 1 KB
+ * per member, twice over with lanes). */
+#define BQ_STATIC_TABLE_BYTES (8u << 20)
 
 /* BQ_TIMESERIES: both west ghost columns take eta and P interpolated
  * linearly in time from the samples ts_eta, ts_P (held at the first / last
@@ -196,6 +202,23 @@ int bq_load(bq_domain* d, const void* host, size_t bytes);
  * batch's stream or be idle. */
 int bq_batch_create(bq_domain* const* doms, int32_t n, void* hip_stream, bq_batch** out);
 int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n);
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * a serving loop that admits and retires members between steps, hosts that
+ * forbid hipMalloc): bq_batch_set without any device allocation or release.
+ * The batch's tables (member descriptors, tile and line work maps) go into a
+ * static array of BQ_STATIC_TABLE_BYTES on the current device instead of
+ * memory the batch allocates; a member list needing more returns BQ_EINVAL
+ * and leaves the batch as it was.  Call it with the batch's device current.
+ * There is one such array per device, shared by every batch on it: the
+ * call waits for the work queued by the batch that used the array before,
+ * and from then on that batch's steps, profiles and schedule changes return
+ * BQ_ESTATE until it sets its members again (either call).  Calls for two
+ * batches of one device that overlap in time (from two host threads) race.
+ * The batch's lane streams exist from bq_batch_create on; the step graphs
+ * are re-captured by the next bq_batch_step.  Results are those of
+ * bq_batch_set with the same members, bit for bit. */
+int bq_batch_set_static(bq_batch* b, bq_domain* const* doms, int32_t n);
 int bq_batch_step(bq_batch* b, int32_t n_steps);
 int bq_batch_sync(bq_batch* b);
 int bq_batch_free(bq_batch* b);

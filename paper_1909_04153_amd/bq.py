@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbq.so")
 
 WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
-ABI_VERSION = 4
+ABI_VERSION = 5
+STATIC_TABLE_BYTES = 8 << 20
 FP64, FP32 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDTMIN, ESTATE, EDONE = 0, -1, -2, -3, -4, -5, -6, -7
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENONFINITE: "ENONFINITE",
@@ -65,7 +66,7 @@ class Tune(ctypes.Structure):
 
 EXPORTS = ["bq_abi_version", "bq_last_error", "bq_live_handles", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
            "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
-           "bq_batch_create", "bq_batch_set", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
+           "bq_batch_create", "bq_batch_set", "bq_batch_set_static", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
            "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps",
            "bq_batch_set_lanes", "bq_batch_lanes", "bq_batch_autotune", "bq_batch_set_tune", "bq_batch_get_tune"]
 KERNELS = ("k_dt", "k_rhs", "k_reduced", "k_final")
@@ -100,6 +101,7 @@ def load(path: str | None = None):
     L.bq_load.argtypes = [vp, vp, ctypes.c_size_t]
     L.bq_batch_create.argtypes = [ctypes.POINTER(vp), ip, vp, ctypes.POINTER(vp)]
     L.bq_batch_set.argtypes = [vp, ctypes.POINTER(vp), ip]
+    L.bq_batch_set_static.argtypes = [vp, ctypes.POINTER(vp), ip]
     L.bq_batch_step.argtypes = [vp, ip]
     L.bq_batch_sync.argtypes = [vp]
     L.bq_batch_free.argtypes = [vp]
@@ -303,10 +305,14 @@ class Batch:
     def lanes(self) -> int:
         return int(load().bq_batch_lanes(self._h))
 
-    def set(self, domains):
-        self.domains = list(domains)
-        arr = (ctypes.c_void_p * len(self.domains))(*[d.handle for d in self.domains])
-        _check(load().bq_batch_set(self._h, arr, len(self.domains)))
+    def set(self, domains, static: bool = False):
+        """replace the members; static=True keeps the batch's device tables
+        in the library's per-device static array (no device allocation)"""
+        doms = list(domains)
+        arr = (ctypes.c_void_p * len(doms))(*[d.handle for d in doms])
+        fn = load().bq_batch_set_static if static else load().bq_batch_set
+        _check(fn(self._h, arr, len(doms)))
+        self.domains = doms
 
     def step(self, n: int = 1):
         _check(load().bq_batch_step(self._h, int(n)))

@@ -11,6 +11,7 @@
 #include <new>
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "bq.h"
@@ -455,7 +456,47 @@ struct bq_batch {
   hipEvent_t ev_fork = nullptr, ev_join[MAX_LANES] = {};
   int graph_steps = 16;
   int rblock = 256, swizzle = 1, segs = 1;  // schedule copied into the launches
+  int static_dev = -1;          // >= 0: tables in that device's static array (bq_batch_set_static)
 };
+
+// ---------------------------------------------------------------------------
+// static table memory (bq_batch_set_static)
+// ---------------------------------------------------------------------------
+// One fixed array per GPU holds the device tables of the batch that last
+// called bq_batch_set_static on it, so that call allocates no device memory.
+// In host code `scratch` only names the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) unsigned char scratch[BQ_STATIC_TABLE_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_static_mu;
+static char* g_static_ptr[MAX_DEVICES];        // device address of `scratch` per device
+static bq_batch* g_static_owner[MAX_DEVICES];  // batch whose tables it holds
+
+// address of the current device's array (looked up on the first use there)
+static int static_tables(int* dev_out, char** ptr_out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(BQ_EDEVICE, "device %d out of range for static tables", dev);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(BQ_EDEVICE, "hipGetSymbolAddress returned NULL");
+    g_static_ptr[dev] = (char*)p;
+  }
+  *dev_out = dev;
+  *ptr_out = g_static_ptr[dev];
+  return BQ_OK;
+}
+
+// a batch on static tables may run only while it still owns them
+static int static_owner_ok(const bq_batch* b) {
+  if (b->static_dev < 0) return BQ_OK;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_owner[b->static_dev] != b)
+    return fail(BQ_ESTATE, "another batch has taken this device's static tables; call bq_batch_set_static again");
+  return BQ_OK;
+}
 
 // layout of a domain in its workspace
 struct Layout {
@@ -977,8 +1018,11 @@ static size_t launch_bytes(const std::vector<bq_domain*>& doms) {
   return rup(sizeof(DomDev<T>) * doms.size(), 256) + rup(sizeof(int) * tiles, 256) + rup(sizeof(int) * lines, 256);
 }
 
+// defer_graph: leave a stale graph executable to the next step (which
+// destroys and re-captures it) instead of destroying it here
 template <typename T>
-static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, hipStream_t s) {
+static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, hipStream_t s,
+                       bool defer_graph = false) {
   const int nd = (int)doms.size();
   std::vector<DomDev<T>> tab(nd);
   std::vector<int> tmap, lmap;
@@ -992,7 +1036,8 @@ static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, 
   HIPCHK(hipMemcpyAsync(m, tab.data(), sizeof(DomDev<T>) * nd, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(m + tb, tmap.data(), sizeof(int) * tmap.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(m + tb + mb, lmap.data(), sizeof(int) * lmap.size(), hipMemcpyHostToDevice, s));
-  drop_graph<T>(L);
+  if (defer_graph) L.graph_built = 0;
+  else drop_graph<T>(L);
   L.table = m;
   L.tile_map = (int*)(m + tb);
   L.line_map = (int*)(m + tb + mb);
@@ -1042,37 +1087,56 @@ static int batch_build_t(bq_batch* b) {
   const size_t s0 = launch_bytes<T>(b->doms);
   size_t sg[MAX_LANES] = {}, need = s0;
   for (int g = 0; g < nl && nl > 1; ++g) need += (sg[g] = launch_bytes<T>(part[g]));
-  if (need > b->mem_bytes) {
-    if (b->mem) HIPCHK(hipFree(b->mem));
-    b->mem = nullptr;
-    HIPCHK(hipMalloc(&b->mem, need));
-    b->mem_bytes = need;
+  // tables in the device's static array (no allocation; its owner was set
+  // by bq_batch_set_static) or in the batch's own device memory
+  const bool stat = b->static_dev >= 0;
+  char* m = nullptr;
+  if (stat) {
+    if (need > (size_t)BQ_STATIC_TABLE_BYTES)
+      return fail(BQ_EINVAL, "the batch's tables need %zu bytes, more than the %zu of the static array", need,
+                  (size_t)BQ_STATIC_TABLE_BYTES);
+    m = g_static_ptr[b->static_dev];
+  } else {
+    if (need > b->mem_bytes) {
+      if (b->mem) HIPCHK(hipFree(b->mem));
+      b->mem = nullptr;
+      HIPCHK(hipMalloc(&b->mem, need));
+      b->mem_bytes = need;
+    }
+    m = (char*)b->mem;
   }
-  char* m = (char*)b->mem;
-  int rc = fill_launch<T>(b->L, m, b->doms, b->stream);
+  int rc = fill_launch<T>(b->L, m, b->doms, b->stream, stat);
   if (rc) return rc;
   b->L.rblock = b->rblock;
   b->L.swizzle = b->swizzle;
   b->L.segs = b->segs;
-  for (int g = 0; g < MAX_LANES; ++g) drop_graph<T>(b->G[g]);
+  for (int g = 0; g < MAX_LANES; ++g) {
+    if (stat) b->G[g].graph_built = 0;
+    else drop_graph<T>(b->G[g]);
+  }
   if (nl > 1) {
     size_t off = s0;
     for (int g = 0; g < nl && !rc; ++g) {
-      rc = fill_launch<T>(b->G[g], m + off, part[g], b->stream);
+      rc = fill_launch<T>(b->G[g], m + off, part[g], b->stream, stat);
       off += sg[g];
       b->G[g].rblock = b->rblock;
       b->G[g].swizzle = b->swizzle;
       b->G[g].segs = b->segs;
     }
     if (rc) return rc;
-    // the lane streams are created together, one after the other
-    for (int l = 0; l < MAX_LANES; ++l)
-      if (!b->lane[l]) HIPCHK(stream_new(&b->lane[l]));
-    if (!b->ev_fork) HIPCHK(event_new(&b->ev_fork, false));
-    for (int l = 0; l < MAX_LANES; ++l)
-      if (!b->ev_join[l]) HIPCHK(event_new(&b->ev_join[l], false));
   }
   HIPCHK(hipStreamSynchronize(b->stream));
+  return BQ_OK;
+}
+
+// the lane streams and their events, created together, one after the other,
+// when the batch is created (later member changes create nothing)
+static int make_lanes(bq_batch* b) {
+  for (int l = 0; l < MAX_LANES; ++l)
+    if (!b->lane[l]) HIPCHK(stream_new(&b->lane[l]));
+  if (!b->ev_fork) HIPCHK(event_new(&b->ev_fork, false));
+  for (int l = 0; l < MAX_LANES; ++l)
+    if (!b->ev_join[l]) HIPCHK(event_new(&b->ev_join[l], false));
   return BQ_OK;
 }
 
@@ -1417,6 +1481,8 @@ int bq_profile_steps(bq_domain* d, int32_t n_steps, double* ms_out) {
 
 int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out) {
   if (!b || !ms_out || n_steps < 0) return fail(BQ_EINVAL, "bad argument");
+  const int rc = static_owner_ok(b);
+  if (rc) return rc;
   return DISPATCH(b->precision, batch_profile_t, b, n_steps, ms_out);
 }
 
@@ -1431,30 +1497,91 @@ int bq_batch_create(bq_domain* const* doms, int32_t n, void* hip_stream, bq_batc
   bq_batch* b = new (std::nothrow) bq_batch();
   if (!b) return fail(BQ_EINVAL, "out of host memory");
   b->stream = (hipStream_t)hip_stream;
-  const int rc = bq_batch_set(b, doms, n);
+  int rc = make_lanes(b);
+  if (!rc) rc = bq_batch_set(b, doms, n);
   if (rc) {
-    delete b;
+    bq_batch_free(b);
     return rc;
   }
   *out = b;
   return BQ_OK;
 }
 
-int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n) {
-  if (!b || n < 1 || !doms) return fail(BQ_EINVAL, "a batch needs at least one domain");
+static int check_members(bq_domain* const* doms, int32_t n) {
+  if (n < 1 || !doms) return fail(BQ_EINVAL, "a batch needs at least one domain");
+  if (!doms[0]) return fail(BQ_EINVAL, "NULL domain in batch");
   const int prec = doms[0]->precision;
   for (int k = 0; k < n; ++k) {
     if (!doms[k]) return fail(BQ_EINVAL, "NULL domain in batch");
     if (doms[k]->precision != prec) return fail(BQ_EINVAL, "batch members must share one precision");
   }
+  return BQ_OK;
+}
+
+// give up the static tables (if this batch holds them)
+static void release_static(bq_batch* b) {
+  if (b->static_dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_owner[b->static_dev] == b) g_static_owner[b->static_dev] = nullptr;
+  b->static_dev = -1;
+}
+
+int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n) {
+  if (!b) return fail(BQ_EINVAL, "NULL batch");
+  const int rc = check_members(doms, n);
+  if (rc) return rc;
+  if (b->static_dev >= 0) {
+    // queued steps may still read the static tables
+    HIPCHK(hipStreamSynchronize(b->stream));
+    release_static(b);
+  }
   b->doms.assign(doms, doms + n);
-  b->precision = prec;
-  return DISPATCH(prec, batch_build_t, b);
+  b->precision = doms[0]->precision;
+  return DISPATCH(b->precision, batch_build_t, b);
+}
+
+int bq_batch_set_static(bq_batch* b, bq_domain* const* doms, int32_t n) {
+  if (!b) return fail(BQ_EINVAL, "NULL batch");
+  int rc = check_members(doms, n);
+  if (rc) return rc;
+  // the one-lane tables plus those of the lane groups (a partition of the
+  // same members: at most as many bytes again, plus the groups' rounding)
+  const std::vector<bq_domain*> dv(doms, doms + n);
+  const size_t one = doms[0]->precision == BQ_FP32 ? launch_bytes<float>(dv) : launch_bytes<double>(dv);
+  const size_t bound = 2 * one + (size_t)MAX_LANES * 3 * 256;
+  if (bound > (size_t)BQ_STATIC_TABLE_BYTES)
+    return fail(BQ_EINVAL, "%d domains need up to %zu bytes of tables, more than the %zu of the static array", n, bound,
+                (size_t)BQ_STATIC_TABLE_BYTES);
+  int dev = -1;
+  char* ptr = nullptr;
+  rc = static_tables(&dev, &ptr);
+  if (rc) return rc;
+  (void)ptr;
+  {
+    // the batch that held the array last must have finished reading it;
+    // from here on its steps are refused until it sets its members again
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    bq_batch* prev = g_static_owner[dev];
+    if (prev && prev != b) {
+      HIPCHK(hipStreamSynchronize(prev->stream));
+      for (hipStream_t ls : prev->lane)
+        if (ls) HIPCHK(hipStreamSynchronize(ls));
+    }
+    g_static_owner[dev] = b;
+  }
+  b->static_dev = dev;
+  b->doms.assign(doms, doms + n);
+  b->precision = doms[0]->precision;
+  rc = DISPATCH(b->precision, batch_build_t, b);
+  if (rc) release_static(b);
+  return rc;
 }
 
 int bq_batch_step(bq_batch* b, int32_t n_steps) {
   if (!b) return fail(BQ_EINVAL, "NULL batch");
   if (n_steps < 0) return fail(BQ_EINVAL, "n_steps < 0");
+  const int rc = static_owner_ok(b);
+  if (rc) return rc;
   return DISPATCH(b->precision, batch_run_t, b, n_steps);
 }
 
@@ -1469,6 +1596,8 @@ int bq_batch_sync(bq_batch* b) {
 int bq_batch_set_lanes(bq_batch* b, int32_t lanes) {
   if (!b || lanes < 1 || lanes > MAX_LANES) return fail(BQ_EINVAL, "lanes must be 1 .. %d", MAX_LANES);
   if (lanes == b->lanes_req) return BQ_OK;
+  const int rc = static_owner_ok(b);
+  if (rc) return rc;
   b->lanes_req = lanes;
   return DISPATCH(b->precision, batch_build_t, b);
 }
@@ -1483,11 +1612,15 @@ int bq_batch_set_graph_steps(bq_batch* b, int32_t steps) {
 
 int bq_batch_autotune(bq_batch* b, int32_t steps_per_trial, bq_tune* out) {
   if (!b || !out || steps_per_trial < 1) return fail(BQ_EINVAL, "bad argument");
+  const int rc = static_owner_ok(b);
+  if (rc) return rc;
   return DISPATCH(b->precision, batch_autotune_t, b, steps_per_trial, out);
 }
 
 int bq_batch_set_tune(bq_batch* b, const bq_tune* t) {
   if (!b || !t) return fail(BQ_EINVAL, "NULL argument");
+  const int rc = static_owner_ok(b);
+  if (rc) return rc;
   return set_tune(b, t);
 }
 
@@ -1509,6 +1642,7 @@ int bq_batch_free(bq_batch* b) {
     event_del(b->ev_join[l]);
     stream_del(b->lane[l]);
   }
+  release_static(b);
   if (b->mem) (void)hipFree(b->mem);
   delete b;
   return BQ_OK;
