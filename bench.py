@@ -245,17 +245,26 @@ def cpu_baseline_all_cores(specs, budget_s, cores):
     return sum(c / e for c, e in res if e > 0)
 
 
-def copy_bandwidth(torch, mib=1024, reps=5):
-    """device-to-device copy of `mib` MiB: (read + write) bytes / time"""
+def copy_bandwidth(torch, bq=None, mib=1024, reps=5):
+    """device-to-device copy of `mib` MiB, (read + write) bytes / time: the
+    library's hand-written copy kernel (16 bytes per lane) when `bq` is
+    given, else torch's copy"""
     n = mib << 20
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
     b = torch.ones(n, dtype=torch.uint8, device="cuda")
-    a.copy_(b)
+
+    def copy():
+        if bq is not None:
+            bq.stream_copy(a, b)
+        else:
+            a.copy_(b)
+
+    copy()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
-        a.copy_(b)
+        copy()
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
@@ -263,9 +272,41 @@ def copy_bandwidth(torch, mib=1024, reps=5):
     return 2.0 * n / (ms * 1e-3) / 1e9
 
 
+def fp32_error_run(bq, torch, spec, t_end, checkpoints=4):
+    """FP32 against FP64 over a whole run: both paths advance the same
+    initial state to t_end (each with its own adaptive Delta t); eta relative
+    L2 and largest pointwise difference over the wave amplitude at
+    `checkpoints` evenly spaced times (the nearest step at or after each)"""
+    amp = max(float(np.max(np.abs(spec["eta"]))), float(np.sum(np.abs(spec["params"].get("wave_amp", [])))))
+    marks = [t_end * (k + 1) / checkpoints for k in range(checkpoints)]
+    res = {}
+    for dt_, prec in (("fp32", bq.FP32), ("fp64", bq.FP64)):
+        d = bq.domain_from_spec(spec, precision=prec)
+        d.set_graph_steps(16)
+        snaps, steps = [], 0
+        t0 = time.perf_counter()
+        for tm in marks:
+            while d.sync().t < tm:
+                d.step(16)
+            i = d.sync()
+            assert i.status == bq.OK, (dt_, i)
+            snaps.append((i.t, i.n, d.read("eta")))
+        res[dt_] = (snaps, time.perf_counter() - t0)
+        d.close()
+        torch.cuda.synchronize()
+    rows = []
+    for (t32, n32, e32), (t64, n64, e64) in zip(res["fp32"][0], res["fp64"][0]):
+        rows.append({"t32": t32, "t64": t64, "steps32": n32, "steps64": n64,
+                     "eta_rel_l2": float(np.linalg.norm(e32 - e64) / max(float(np.linalg.norm(e64)), 1e-300)),
+                     "eta_max_over_amp": float(np.max(np.abs(e32 - e64))) / amp})
+    return {"reference": "fp64 path", "t_end": t_end, "checkpoints": rows,
+            "wall_s": {"fp32": res["fp32"][1], "fp64": res["fp64"][1]}}
+
+
 def serve_run(bq, seconds):
-    """a short Poisson request stream (mixed sizes 128..1024, 2..12 s simulated
-    each) through the continuous-batching loop"""
+    """a reduced Poisson request stream (48 requests, sides 128..1024, 2..12 s
+    simulated each) through the continuous-batching loop; the configured
+    stream (200 requests, 128..2048, 60..600 s) runs with --serve-c5"""
     from paper_1909_04153_amd import scenarios as S
     from paper_1909_04153_amd import serve
 
@@ -290,8 +331,67 @@ def serve_run(bq, seconds):
     out = stats.summary(skip_before=0.1 * t)
     out["cell_steps_per_s"] = out["cell_steps_per_s"] / 1e9 if out["cell_steps_per_s"] else None
     out["unit_throughput"] = "Gcell-steps/s"
+    out["stream"] = "reduced: 48 requests, sides 128..1024, 2..12 s simulated, first 10 % of arrivals excluded"
     out["hbm_budget_bytes"] = budget
     out["peak_resident_bytes"] = srv.peak_used
+    return out
+
+
+def serve_c5(bq, torch, rho, n_req=200, max_wall=1100.0, chunk=16, warmup_s=10.0, seed=190904155):
+    """The configured serving stream: n_req Poisson arrivals of C2-type
+    beaches and C3-type rip beaches, square sides log-uniform on
+    [128, 2048], 60..600 s simulated each, offered load rho times the
+    capacity (measured first: the cell-steps/s of a batch of 16 requests of
+    the stream's own mix), HBM admission on a 200 GiB budget, up to 64
+    resident; p50/p99 time to solution over the requests arriving after the
+    first warmup_s seconds (unfinished ones count with the time they had
+    waited: censored, and p99 is then a lower bound)."""
+    from paper_1909_04153_amd import scenarios as S
+    from paper_1909_04153_amd import serve
+
+    t_gen = time.perf_counter()
+    print(f"serving stream: generating {n_req} requests", file=sys.stderr, flush=True)
+    probe = S.request_stream(n=n_req, seed=seed, rho=1.0, capacity_cells_per_s=1.0)
+    # capacity: a batch of 16 requests of the mix, 200 steps (FP32, 2 lanes)
+    sample = [s for _, s in probe[:16]]
+    doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in sample]
+    b = bq.Batch(doms)
+    b.set_graph_steps(chunk)
+    b.step(32)
+    b.sync()
+    cells = sum(d.nx * d.ny for d in doms)
+    t0 = time.perf_counter()
+    b.step(200)
+    b.sync()
+    cap = cells * 200 / (time.perf_counter() - t0)
+    print(f"serving stream: capacity {cap / 1e9:.1f} Gcell-steps/s on a batch of 16 requests", file=sys.stderr,
+          flush=True)
+    b.close()
+    for d in doms:
+        d.close()
+    del doms, b, sample
+    torch.cuda.synchronize()
+    # the stream itself: the same requests, the interarrival times (drawn
+    # for rho 1 at a capacity of 1 cell-step/s) scaled to rho at the
+    # measured capacity
+    stream = [(t / (rho * cap), sp) for t, sp in probe]
+    del probe
+    work = [S.request_work(s) for _, s in stream]
+    reqs = [serve.Request(k, s, arrival=t) for k, (t, s) in enumerate(stream)]
+    gen_s = time.perf_counter() - t_gen
+    budget = 200 << 30
+    srv = serve.Server(budget, max_slots=64, precision=bq.FP32, chunk_steps=chunk)
+    stats = srv.run(reqs, max_wall=max_wall, progress=lambda m: print(m, file=sys.stderr, flush=True))
+    out = stats.summary(skip_before=warmup_s)
+    out["cell_steps_per_s"] = out["cell_steps_per_s"] / 1e9 if out["cell_steps_per_s"] else None
+    span = stream[-1][0]
+    out.update({"rho": rho, "unit_throughput": "Gcell-steps/s", "capacity_gcs": cap / 1e9,
+                "arrival_span_s": span, "offered_gcs": sum(work) / span / 1e9,
+                "estimated_work_gcs": sum(work) / 1e9,
+                "warmup_excluded_s": warmup_s, "hbm_budget_bytes": budget, "max_slots": 64,
+                "peak_resident_bytes": srv.peak_used, "chunk_steps": chunk, "generation_s": gen_s,
+                "stream": f"{n_req} requests, sides 128..2048 log-uniform, 60..600 s simulated, "
+                          "half beaches (CFL 0.2), half rip beaches (CFL 0.125), seed %d" % seed})
     return out
 
 
@@ -315,6 +415,10 @@ def main():
                     help="run the request loop for about this long and report p50/p99 (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of this many MiB (5 times), for counter calibration")
+    ap.add_argument("--serve-c5", type=float, default=0.0, metavar="RHO",
+                    help="only run the configured serving stream (200 requests, 128..2048, 60..600 s) at this "
+                         "offered load and print its JSON line")
+    ap.add_argument("--serve-max-wall", type=float, default=1100.0)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -337,6 +441,10 @@ def main():
     from paper_1909_04153_amd import bq
 
     bq.load()
+    if args.serve_c5 > 0:
+        print(json.dumps({"metric": "p50/p99 time to solution", "serving_c5": serve_c5(
+            bq, torch, args.serve_c5, max_wall=args.serve_max_wall)}), flush=True)
+        return
     specs, dtype = workload(args.workload)
     cells = sum(s["params"]["nx"] * s["params"]["ny"] for s in specs)
     # a single-domain workload runs as a batch of one, so that its schedule
@@ -391,6 +499,12 @@ def main():
     if dtype == "fp32":
         out["fp32_error"] = fp32_error(bq, torch, specs, args.steps)
     out["copy_gbs"] = copy_bandwidth(torch)
+    # the achievable HBM rate: the library's hand-written copy kernel
+    out["copy_gbs_hip"] = copy_bandwidth(torch, bq)
+    if achieved:
+        roof["achievable_peak"] = out["copy_gbs_hip"]
+        roof["frac_of_achievable"] = achieved / out["copy_gbs_hip"]
+    out["effective_frac_of_achievable"] = out["effective_hbm_frac"] * HBM_PEAK_GBS / out["copy_gbs_hip"]
     tr = roof["traffic"]
     if tr:
         roof["traffic_gbs"] = tr / (kms[dom_k] * 1e-3) / 1e9
@@ -418,6 +532,15 @@ def main():
         for wl in ("beach1024x256_fp64", "solitary200x20"):
             fp64[wl] = single_line(bq, torch, args, wl, max(20, args.steps))
         out["fp64_plain"] = fp64
+        # FP32 against FP64 over whole runs: the 1024 x 256 beach over its
+        # 20 s (wave through the wet/dry shoreline), and the 2048^2 rip beach
+        # over 30 s from a state with the JONSWAP train already in the domain
+        from paper_1909_04153_amd import scenarios as S
+
+        out["fp32_error_runs"] = {
+            "beach1024x256_20s": fp32_error_run(bq, torch, S.sloping_beach(), 20.0),
+            "rip2048_spun_up_30s": fp32_error_run(
+                bq, torch, S.spun_up(S.rip_beach(cfl=0.125, fstar_order=1), h_taper=(0.4, 0.25)), 30.0)}
     if args.serve_seconds > 0:
         out["serving"] = serve_run(bq, args.serve_seconds)
     if not args.no_cpu_baseline:

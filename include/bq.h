@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define BQ_ABI_VERSION 5
+#define BQ_ABI_VERSION 6
 #define BQ_MAX_WAVES 256
 /* Size of the per-GPU static array that holds the device tables of a batch
  * set up by bq_batch_set_static (8 MiB: the tables take 4 bytes per tile of
@@ -146,6 +146,12 @@ typedef struct bq_batch bq_batch;
 int bq_abi_version(void);
 const char* bq_last_error(void);
 
+/* A plain device-to-device copy of `bytes` (a multiple of 16, both buffers
+ * 16-byte aligned), one 16-byte vector per lane, enqueued on hip_stream: the
+ * achievable HBM bandwidth that the step's kernels are measured against
+ * (read + write bytes over its duration). */
+int bq_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
 /* Streams, events and graph executables the library has created and not yet
  * destroyed, in counts[0..2] (all domains and batches of the process).  For
  * tests that freeing a batch or a domain releases what it made. */
@@ -221,6 +227,14 @@ int bq_batch_set(bq_batch* b, bq_domain* const* doms, int32_t n);
 int bq_batch_set_static(bq_batch* b, bq_domain* const* doms, int32_t n);
 int bq_batch_step(bq_batch* b, int32_t n_steps);
 int bq_batch_sync(bq_batch* b);
+
+/* Latched status of every member after the work queued so far, for a loop
+ * that polls many members (serving): one small kernel and one copy for the
+ * whole batch instead of a bq_sync per member.  status[k] is member k's
+ * bq_status (BQ_EDONE once its time reached t_end), steps[k] its step count
+ * and t[k] its time (Sec. 3.2.2: the sum of its own Delta t); steps and t
+ * may be NULL; arrays hold the member count.  Waits for the batch's stream. */
+int bq_batch_status(bq_batch* b, int32_t* status, int64_t* steps, double* t);
 int bq_batch_free(bq_batch* b);
 
 /* Launch lanes of a batch (1 to 4; default 2, at most the member count).
@@ -250,28 +264,38 @@ int bq_batch_profile_steps(bq_batch* b, int32_t n_steps, double* ms_out);
 
 /* Schedule of a batch: launch lanes, steps per hipGraph replay, threads per
  * block of the line-coupling kernel (64, 128 or 256), the XCD-aware tile
- * order of the stencil kernel (1 on, 0 off), and the line-coupling variant:
- * reduce_segments 1 = one thread per line running over its chunks, 4 or 8 =
+ * order of the stencil kernel (1 on, 0 off), the line-coupling variant
+ * (reduce_segments 1 = one thread per line running over its chunks, 4 or 8 =
  * the chunks of a line cut into that many segments swept by as many waves
- * that exchange their composed maps (reduce_block is then ignored; give 256).
- * With reduce_segments 1 every
- * schedule gives bitwise the same results; the segmented variant
- * reassociates the line-coupling products and differs at rounding level. */
+ * that exchange their composed maps; reduce_block is then ignored, give
+ * 256), and the tile shape shared by the members (the chunking of the
+ * tridiagonal solves of Eq. 19-20; the workspace is laid out for every
+ * candidate, so members change shape between steps in place).  With
+ * reduce_segments 1 every schedule of one tile shape gives bitwise the same
+ * results; the segmented variant reassociates the line-coupling products,
+ * and another tile shape chunks the line solves differently: both differ
+ * at rounding level. */
 typedef struct bq_tune {
   int32_t lanes;
   int32_t graph_steps;
   int32_t reduce_block;
   int32_t swizzle;
   int32_t reduce_segments;
+  int32_t tile_y;          /* tile height = y-chunk length of the line solves */
+  int32_t chunk_x;         /* x-chunk length of the line solves (tiles are 64
+                              cells wide); FP32 takes 16 x 16, 16 x 32, 8 x 16,
+                              8 x 32, FP64 8 x 16, 8 x 32, 4 x 16 (tile_y x
+                              chunk_x; both 0 in bq_batch_set_tune: keep) */
   double ms_per_step;      /* bq_batch_autotune: measured time of one step */
 } bq_tune;
 
 /* Autotuner: times steps_per_trial steps of the batch under each candidate
  * schedule (lanes 1-4 x graph replays of 4 or 16 steps x line coupling by
  * one thread per line in blocks of 64 or 256, or segmented; XCD-aware tile
- * order on) twice, in forward then reverse order,
+ * order on; the current tile shape) twice, in forward then reverse order,
  * keeps the one of the lowest mean time (among those within 0.5 % of it,
- * the one with the longest graph replays) and returns it.  The
+ * the one with the longest graph replays), then times every tile shape
+ * under that schedule the same way and returns the fastest.  The
  * trial steps are real steps (the domains advance by them).  bq_batch_set_tune applies a schedule, for
  * instance one cached from an earlier autotune of a batch of the same shape;
  * bq_batch_get_tune reports the current one (ms_per_step 0). */

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbq.so")
 
 WALL, SINE, SPONGE, IRREGULAR, TIMESERIES = 0, 1, 2, 3, 4
-ABI_VERSION = 5
+ABI_VERSION = 6
 STATIC_TABLE_BYTES = 8 << 20
 FP64, FP32 = 0, 1
 OK, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EDTMIN, ESTATE, EDONE = 0, -1, -2, -3, -4, -5, -6, -7
@@ -58,15 +58,16 @@ class Info(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("lanes", ctypes.c_int32), ("graph_steps", ctypes.c_int32), ("reduce_block", ctypes.c_int32),
-                ("swizzle", ctypes.c_int32), ("reduce_segments", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
+                ("swizzle", ctypes.c_int32), ("reduce_segments", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("chunk_x", ctypes.c_int32), ("ms_per_step", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-EXPORTS = ["bq_abi_version", "bq_last_error", "bq_live_handles", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
+EXPORTS = ["bq_abi_version", "bq_last_error", "bq_stream_copy", "bq_live_handles", "bq_params_default", "bq_workspace_bytes", "bq_domain_create",
            "bq_domain_free", "bq_set_state", "bq_step", "bq_step_dt", "bq_sync", "bq_read", "bq_save", "bq_load",
-           "bq_batch_create", "bq_batch_set", "bq_batch_set_static", "bq_batch_step", "bq_batch_sync", "bq_batch_free",
+           "bq_batch_create", "bq_batch_set", "bq_batch_set_static", "bq_batch_step", "bq_batch_status", "bq_batch_sync", "bq_batch_free",
            "bq_set_graph_steps", "bq_batch_set_graph_steps", "bq_profile_steps", "bq_batch_profile_steps",
            "bq_batch_set_lanes", "bq_batch_lanes", "bq_batch_autotune", "bq_batch_set_tune", "bq_batch_get_tune"]
 KERNELS = ("k_dt", "k_rhs", "k_reduced", "k_final")
@@ -87,6 +88,7 @@ def load(path: str | None = None):
     L.bq_abi_version.restype = ctypes.c_int
     L.bq_last_error.restype = ctypes.c_char_p
     L.bq_live_handles.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    L.bq_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.bq_params_default.argtypes = [ctypes.POINTER(Params)]
     L.bq_params_default.restype = None
     L.bq_workspace_bytes.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
@@ -104,6 +106,8 @@ def load(path: str | None = None):
     L.bq_batch_set_static.argtypes = [vp, ctypes.POINTER(vp), ip]
     L.bq_batch_step.argtypes = [vp, ip]
     L.bq_batch_sync.argtypes = [vp]
+    L.bq_batch_status.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_double)]
     L.bq_batch_free.argtypes = [vp]
     L.bq_set_graph_steps.argtypes = [vp, ip]
     L.bq_batch_set_graph_steps.argtypes = [vp, ip]
@@ -320,6 +324,16 @@ class Batch:
     def sync(self):
         _check(load().bq_batch_sync(self._h))
 
+    def status(self):
+        """(status, steps, t) arrays over the members, one readback"""
+        n = len(self.domains)
+        st = np.zeros(n, dtype=np.int32)
+        steps = np.zeros(n, dtype=np.int64)
+        t = np.zeros(n)
+        _check(load().bq_batch_status(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      steps.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dptr(t)))
+        return st, steps, t
+
     def wait(self):
         self.sync()
 
@@ -339,7 +353,7 @@ class Batch:
 
     def set_tune(self, tune: dict):
         t = Tune(int(tune["lanes"]), int(tune["graph_steps"]), int(tune["reduce_block"]), int(tune["swizzle"]),
-                 int(tune.get("reduce_segments", 1)), 0.0)
+                 int(tune.get("reduce_segments", 1)), int(tune.get("tile_y", 0)), int(tune.get("chunk_x", 0)), 0.0)
         _check(load().bq_batch_set_tune(self._h, ctypes.byref(t)))
 
     def shape_key(self) -> str:
@@ -393,6 +407,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def stream_copy(dst, src, stream=None):
+    """the library's plain device copy of torch tensor src into dst (same
+    byte size, 16-byte aligned), on `stream` (default: torch's current)"""
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("dst and src differ in size")
+    _check(load().bq_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n,
+                                 ctypes.c_void_p(s.cuda_stream)))
 
 
 def live_handles() -> dict:

@@ -1539,13 +1539,15 @@ struct alignas(16) FinSmem {
 // finalizes the corrector of the domains that run it.
 template <typename T, int TY, int MX, int MODE>
 __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
-                                             int nd) {
+                                             int nd, int swizzle) {
   using S = FinSmem<T, TY, MX>;
   constexpr int CXN = S::CXN, BX = S::BX, TXP = S::TXP;
   constexpr int CPT = (TX * TY) / NT;
   __shared__ S sm;
   int dom, tile;
-  locate(tile_map, nd, blockIdx.x, dom, tile);
+  // swizzle = 1: XCD-aware tile order, as in the stencil kernel (the corner
+  // halo of a tile is then mostly in its XCD's L2)
+  locate(tile_map, nd, swizzle ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x, dom, tile);
   const DomDev<T>& D = doms[dom];
   DevState* st = D.st;
   if (st->halt) return;

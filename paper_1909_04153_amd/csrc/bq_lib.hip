@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <atomic>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "bq.h"
@@ -20,31 +21,51 @@
 using namespace bqk;
 
 // ---------------------------------------------------------------------------
-// tile configuration per precision
+// tile shapes per precision
 // ---------------------------------------------------------------------------
-// Tile height (= y-chunk length) and x-chunk length of the line solves;
-// the chunk lengths are build-time tunables (BQ_MX_F32 / BQ_MX_F64, a
-// divisor of the 64-cell tile width).  Both take 16-cell x-chunks: the
-// finalize kernel's x solves then run half as long (in FP32 on a whole wave,
-// 16 rows x 4 chunks); the line coupling gets twice the chunks, which the
-// segmented variant absorbs (measured against 32 in FP32: k_final -12 %,
-// k_rhs -3 %, C3 domain +6 %, 64-domain batch unchanged; in FP64: 200 x 20
-// domain +9 %, 1024 x 256 +1 %).
-#ifndef BQ_MX_F32
-#define BQ_MX_F32 16
-#endif
-#ifndef BQ_MX_F64
-#define BQ_MX_F64 16
-#endif
+// A tile is 64 cells wide and TY tall (TY = the y-chunk length of the line
+// solves); x-lines are cut into chunks of MX cells (a divisor of 64).  The
+// shape is a runtime choice of a domain (and of a batch, whose members share
+// it), among the candidates below, the first being the default; the
+// workspace is laid out for all of them (fields padded for the tallest tile,
+// chunk and tile tables for the shortest chunks), so a domain changes shape
+// between steps without moving its state.
+struct Shape {
+  int ty, mx;
+};
 template <typename T> struct Cfg;
 template <> struct Cfg<float> {
-  static constexpr int TY = 16;
-  static constexpr int MX = BQ_MX_F32;
+  static constexpr int NS = 4, TYMAX = 16, TYMIN = 8, MXMIN = 16;
+  static constexpr Shape shape(int k) {
+    return k == 0 ? Shape{16, 16} : k == 1 ? Shape{16, 32} : k == 2 ? Shape{8, 16} : Shape{8, 32};
+  }
 };
 template <> struct Cfg<double> {
-  static constexpr int TY = 8;
-  static constexpr int MX = BQ_MX_F64;
+  static constexpr int NS = 3, TYMAX = 8, TYMIN = 4, MXMIN = 16;
+  static constexpr Shape shape(int k) { return k == 0 ? Shape{8, 16} : k == 1 ? Shape{8, 32} : Shape{4, 16}; }
 };
+template <typename T>
+static bool shape_ok(int ty, int mx) {
+  for (int k = 0; k < Cfg<T>::NS; ++k)
+    if (Cfg<T>::shape(k).ty == ty && Cfg<T>::shape(k).mx == mx) return true;
+  return false;
+}
+template <int V>
+using IC = std::integral_constant<int, V>;
+// f(IC<TY>, IC<MX>) for the shape (ty, mx), which shape_ok<T> has accepted
+template <typename T, typename F>
+static void shape_dispatch(int ty, int mx, F&& f) {
+  if constexpr (sizeof(T) == 4) {
+    if (ty == 16 && mx == 16) f(IC<16>{}, IC<16>{});
+    else if (ty == 16) f(IC<16>{}, IC<32>{});
+    else if (mx == 16) f(IC<8>{}, IC<16>{});
+    else f(IC<8>{}, IC<32>{});
+  } else {
+    if (ty == 8 && mx == 16) f(IC<8>{}, IC<16>{});
+    else if (ty == 8) f(IC<8>{}, IC<32>{});
+    else f(IC<4>{}, IC<16>{});
+  }
+}
 
 static thread_local char g_err[512] = "";
 
@@ -395,6 +416,35 @@ __global__ void __launch_bounds__(NDIAG) k_diag_final(const DomDev<T>* Dp) {
   }
 }
 
+// Plain device copy, one 16-byte vector per lane: the HBM bandwidth
+// reference the step's kernels are measured against (bq_stream_copy).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_stream_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst, size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// Before a change of tile shape: fold the per-tile CFL maxima of the old
+// tiling (written by the finalize kernel for the next step's Delta t) into
+// the state's maximum, then clear every slot, so the next Delta t sees the
+// same maximum under the new tiling.
+template <typename T>
+__global__ void __launch_bounds__(256) k_fold_tiles(const DomDev<T>* Dp, int ntiles_old, int ntiles_max) {
+  const DomDev<T>& D = *Dp;
+  double m = 0.0;
+  for (int k = threadIdx.x; k < ntiles_old; k += 256) m = fmax(m, D.smax_tile[k]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  __shared__ double red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double mm = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    const double s0 = __longlong_as_double((long long)D.st->smax_bits);
+    D.st->smax_bits = (unsigned long long)__double_as_longlong(fmax(s0, mm));
+  }
+  for (int k = threadIdx.x; k < ntiles_max; k += 256) D.smax_tile[k] = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // host objects
 // ---------------------------------------------------------------------------
@@ -404,7 +454,9 @@ struct Launch {
   void* table = nullptr;        // DomDev<T>[nd]
   int* tile_map = nullptr;      // per tile: domain << MAP_SHIFT | tile (batches; NULL for one domain)
   int* line_map = nullptr;      // per line: domain << MAP_SHIFT | line
+  void* status = nullptr;       // StatusRec[nd]: staging of bq_batch_status (batches)
   int nd = 0, tiles = 0, lines = 0;
+  int ty = 0, mx = 0;           // tile shape shared by the members
   int any_pc = 0;               // some member runs the corrector pass
   // schedule (tuned per batch): threads per block of the line-coupling
   // kernel, XCD-aware tile order of the stencil kernel
@@ -457,6 +509,7 @@ struct bq_batch {
   int graph_steps = 16;
   int rblock = 256, swizzle = 1, segs = 1;  // schedule copied into the launches
   int static_dev = -1;          // >= 0: tables in that device's static array (bq_batch_set_static)
+  int ty = 0, mx = 0;           // tile shape of the members (0: the first member's)
 };
 
 // ---------------------------------------------------------------------------
@@ -505,7 +558,9 @@ struct Layout {
   size_t off_Dc, off_Dbar, off_xhP, off_xhQ;
   size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
   size_t ghosted, interior, total;
-  int pitch, xoff, ipitch, cpitch, cx, cy, tiles_x, tiles_y, TY, MX;
+  // sizes for every tile shape: chunks per line (shortest chunks), tiles
+  // (shortest tiles)
+  int pitch, xoff, ipitch, cpitch, cx, cy, tiles_x, tiles_max;
 };
 
 template <typename T>
@@ -513,15 +568,14 @@ static Layout layout_for(const bq_params* p) {
   Layout L{};
   const int nx = p->nx, ny = p->ny;
   const int A = 256 / (int)sizeof(T);
-  L.TY = Cfg<T>::TY;
-  L.MX = Cfg<T>::MX;
-  L.cx = cdiv(nx, L.MX);
-  L.cy = cdiv(ny, L.TY);
+  L.cx = cdiv(nx, Cfg<T>::MXMIN);
+  L.cy = cdiv(ny, Cfg<T>::TYMIN);
   L.tiles_x = cdiv(nx, TX);
-  L.tiles_y = cdiv(ny, L.TY);
-  // fields are padded to whole tiles plus the stencil halo, so the stencil
-  // kernel reads every tile without clamping its indices
-  const int NX = L.tiles_x * TX, NY = L.tiles_y * L.TY;
+  L.tiles_max = L.tiles_x * cdiv(ny, Cfg<T>::TYMIN);
+  // fields are padded to whole tiles of the tallest shape plus the stencil
+  // halo, so the stencil kernel reads every tile of every shape without
+  // clamping its indices
+  const int NX = L.tiles_x * TX, NY = cdiv(ny, Cfg<T>::TYMAX) * Cfg<T>::TYMAX;
   L.xoff = A;
   L.pitch = (int)rup((size_t)A + NX + 2, (size_t)A);
   L.ipitch = NX;
@@ -544,7 +598,7 @@ static Layout layout_for(const bq_params* p) {
   L.off_G = take(3 * L.interior);
   // per-tile CFL maxima and diagnostic partial sums (zeroed by set_state,
   // part of the checkpoint)
-  L.off_part = take(sizeof(double) * ((size_t)L.tiles_x * L.tiles_y + 2 * NDIAG));
+  L.off_part = take(sizeof(double) * ((size_t)L.tiles_max + 2 * NDIAG));
   L.off_wmax = take(p->runup_delta > 0.0 ? L.interior : 0);   // run-up record (checkpointed)
   L.off_Dc = take((size_t)(NY + 5) * L.cpitch * sizeof(T));
   L.off_Dbar = take(L.interior);
@@ -611,6 +665,19 @@ DomDev<float>& desc<float>(bq_domain* d) { return d->df; }
 template <>
 DomDev<double>& desc<double>(bq_domain* d) { return d->dd; }
 
+// static data of the chunked line solves for the domain's current shape:
+// the chunk spikes' end values, then the interface-recurrence coefficients
+template <typename T>
+static void setup_chunks(const DomDev<T>& D, const DomDev<T>* Dd, hipStream_t s) {
+  shape_dispatch<T>(D.my, D.mx, [&](auto tyc, auto mxc) {
+    constexpr int TY = decltype(tyc)::value, MX = decltype(mxc)::value;
+    k_setup_spikes<T, MX><<<cdiv(D.ny * D.cx, 64), 64, 0, s>>>(Dd, 0);
+    k_setup_spikes<T, TY><<<cdiv(D.nx * D.cy, 64), 64, 0, s>>>(Dd, 1);
+  });
+  k_setup_reduced<T><<<cdiv(D.ny, 64), 64, 0, s>>>(Dd, 0);
+  k_setup_reduced<T><<<cdiv(D.nx, 64), 64, 0, s>>>(Dd, 1);
+}
+
 template <typename T>
 static int create_t(bq_domain* d, const double* depth_c) {
   const bq_params* p = &d->p;
@@ -625,12 +692,13 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.xoff = Ly.xoff;
   D.ipitch = Ly.ipitch;
   D.cpitch = Ly.cpitch;
-  D.cx = Ly.cx;
-  D.cy = Ly.cy;
-  D.mx = Ly.MX;
-  D.my = Ly.TY;
+  const Shape sh0 = Cfg<T>::shape(0);
+  D.cx = cdiv(p->nx, sh0.mx);
+  D.cy = cdiv(p->ny, sh0.ty);
+  D.mx = sh0.mx;
+  D.my = sh0.ty;
   D.tiles_x = Ly.tiles_x;
-  D.tiles_y = Ly.tiles_y;
+  D.tiles_y = cdiv(p->ny, sh0.ty);
   for (int s = 0; s < 4; ++s) {
     D.bc[s] = p->bc[s];
     D.sponge_w[s] = (T)p->sponge_width[s];
@@ -705,7 +773,7 @@ static int create_t(bq_domain* d, const double* depth_c) {
   D.ifx = (T*)(b + Ly.off_ifx);
   D.ify = (T*)(b + Ly.off_ify);
   D.smax_tile = (double*)(b + Ly.off_part);
-  D.diag_part = D.smax_tile + (size_t)Ly.tiles_x * Ly.tiles_y;
+  D.diag_part = D.smax_tile + (size_t)Ly.tiles_max;
   D.wave = (double*)(b + Ly.off_wave);
   D.wmax = D.runup ? (T*)(b + Ly.off_wmax) : nullptr;
   D.io = (double*)(b + Ly.off_io);
@@ -720,8 +788,10 @@ static int create_t(bq_domain* d, const double* depth_c) {
   d->L.tile_map = d->L.line_map = nullptr;
   d->L.nd = 1;
   d->L.any_pc = D.corrector;
-  d->L.tiles = Ly.tiles_x * Ly.tiles_y;
+  d->L.tiles = D.tiles_x * D.tiles_y;
   d->L.lines = p->nx + p->ny;
+  d->L.ty = sh0.ty;
+  d->L.mx = sh0.mx;
   if (D.n_waves > 0) {
     std::vector<double> wv(4 * (size_t)D.n_waves, 0.0);
     for (int m = 0; m < D.n_waves; ++m) {
@@ -739,10 +809,7 @@ static int create_t(bq_domain* d, const double* depth_c) {
   const int ncorn = (p->nx + 5) * (p->ny + 5);
   k_setup_corners<T><<<cdiv(ncorn, 256), 256, 0, s>>>(Dd);
   k_setup_cells<T><<<cdiv(p->nx * p->ny, 256), 256, 0, s>>>(Dd);
-  k_setup_spikes<T, Cfg<T>::MX><<<cdiv(p->ny * Ly.cx, 64), 64, 0, s>>>(Dd, 0);
-  k_setup_spikes<T, Cfg<T>::TY><<<cdiv(p->nx * Ly.cy, 64), 64, 0, s>>>(Dd, 1);
-  k_setup_reduced<T><<<cdiv(p->ny, 64), 64, 0, s>>>(Dd, 0);
-  k_setup_reduced<T><<<cdiv(p->nx, 64), 64, 0, s>>>(Dd, 1);
+  setup_chunks<T>(D, Dd, s);
   if (D.n_waves > 0) k_setup_waves<T><<<1, 64, 0, s>>>(Dd, p->B);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(s));
@@ -783,6 +850,36 @@ static int set_state_t(bq_domain* d, const double* eta, const double* P, const d
   return BQ_OK;
 }
 
+// Change a domain's tile shape between steps (the domain must be idle): the
+// state stays where it is; the descriptor, the chunk tables and the per-tile
+// maxima follow the new tiling.  Results continue up to the rounding of the
+// line solves' different chunking.
+template <typename T>
+static int set_shape_t(bq_domain* d, int ty, int mx) {
+  DomDev<T>& D = desc<T>(d);
+  if (D.my == ty && D.mx == mx) return BQ_OK;
+  if (!shape_ok<T>(ty, mx)) return fail(BQ_EINVAL, "tile shape %d x %d is not a candidate for this precision", ty, mx);
+  const Layout Ly = layout_for<T>(&d->p);
+  hipStream_t s = d->stream;
+  const DomDev<T>* Dd = (const DomDev<T>*)d->ddev;
+  k_fold_tiles<T><<<1, 256, 0, s>>>(Dd, D.tiles_x * D.tiles_y, Ly.tiles_max);
+  D.mx = mx;
+  D.my = ty;
+  D.cx = cdiv(D.nx, mx);
+  D.cy = cdiv(D.ny, ty);
+  D.tiles_y = cdiv(D.ny, ty);
+  HIPCHK(hipMemcpyAsync(d->ddev, &D, sizeof(D), hipMemcpyHostToDevice, s));
+  setup_chunks<T>(D, Dd, s);
+  HIPCHK(hipGetLastError());
+  graph_del(d->L.graph);
+  d->L.graph_built = 0;
+  d->L.tiles = D.tiles_x * D.tiles_y;
+  d->L.ty = ty;
+  d->L.mx = mx;
+  HIPCHK(hipStreamSynchronize(s));
+  return BQ_OK;
+}
+
 // ---------------------------------------------------------------------------
 // stepping
 // ---------------------------------------------------------------------------
@@ -798,21 +895,43 @@ static void launch_reduced(const Launch& L, hipStream_t s, int pass) {
     k_reduced<T><<<cdiv(L.lines, L.rblock), L.rblock, 0, s>>>(tab, L.line_map, L.nd, L.lines, pass);
 }
 
+// the stencil/update kernel (pass 0: AB3 step, 1: corrector) and the
+// finalize kernel (mode as in k_final) in the launch's tile shape
+template <typename T>
+static void launch_rhs(const Launch& L, hipStream_t s, int pass) {
+  shape_dispatch<T>(L.ty, L.mx, [&](auto tyc, auto mxc) {
+    constexpr int TY = decltype(tyc)::value, MX = decltype(mxc)::value;
+    const DomDev<T>* tab = (const DomDev<T>*)L.table;
+    if (pass == 0) k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+    else k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+  });
+}
+
+template <typename T>
+static void launch_final(const Launch& L, hipStream_t s, int mode) {
+  shape_dispatch<T>(L.ty, L.mx, [&](auto tyc, auto mxc) {
+    constexpr int TY = decltype(tyc)::value, MX = decltype(mxc)::value;
+    const DomDev<T>* tab = (const DomDev<T>*)L.table;
+    if (mode == 0) k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+    else if (mode == 1) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+    else k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+  });
+}
+
 template <typename T>
 static void enqueue_step(const Launch& L, hipStream_t s, double dt_prescribed) {
-  constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
   k_dt<T><<<L.nd, DT_THREADS, 0, s>>>(tab, dt_prescribed);
-  k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+  launch_rhs<T>(L, s, 0);
   launch_reduced<T>(L, s, 0);
   if (!L.any_pc) {
-    k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    launch_final<T>(L, s, 0);
   } else {
-    k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    launch_final<T>(L, s, 1);
     // corrector pass of the domains that run it (the others return at once)
-    k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+    launch_rhs<T>(L, s, 1);
     launch_reduced<T>(L, s, 1);
-    k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    launch_final<T>(L, s, 2);
   }
 }
 
@@ -851,7 +970,6 @@ static int run_steps(Launch& L, hipStream_t s, int n_steps, int graph_steps) {
 
 template <typename T>
 static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
-  constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const DomDev<T>* tab = (const DomDev<T>*)L.table;
   hipEvent_t ev[8] = {};
   for (int k = 0; k < 8; ++k)
@@ -866,19 +984,18 @@ static int profile_t(Launch& L, hipStream_t s, int n_steps, double* ms_out) {
     if (hipEventRecord(ev[0], s) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventRecord"); break; }
     k_dt<T><<<L.nd, DT_THREADS, 0, s>>>(tab, 0.0);
     (void)hipEventRecord(ev[1], s);
-    k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+    launch_rhs<T>(L, s, 0);
     (void)hipEventRecord(ev[2], s);
     launch_reduced<T>(L, s, 0);
     (void)hipEventRecord(ev[3], s);
-    if (L.any_pc) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
-    else k_final<T, TY, MX, 0><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+    launch_final<T>(L, s, L.any_pc ? 1 : 0);
     (void)hipEventRecord(ev[4], s);
     if (L.any_pc) {
-      k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd, L.swizzle);
+      launch_rhs<T>(L, s, 1);
       (void)hipEventRecord(ev[5], s);
       launch_reduced<T>(L, s, 1);
       (void)hipEventRecord(ev[6], s);
-      k_final<T, TY, MX, 2><<<L.tiles, NT, 0, s>>>(tab, L.tile_map, L.nd);
+      launch_final<T>(L, s, 2);
       (void)hipEventRecord(ev[7], s);
     }
     if (hipEventSynchronize(ev[last]) != hipSuccess) { rc = fail(BQ_EDEVICE, "hipEventSynchronize"); break; }
@@ -991,6 +1108,11 @@ static int load_t(bq_domain* d, const void* host, size_t bytes) {
   HIPCHK(hipMemcpyAsync(d->st, o + sizeof(hd), sizeof(DevState), hipMemcpyHostToDevice, d->stream));
   HIPCHK(hipMemcpyAsync(d->ws + Ly.off_w, o + sizeof(hd) + sizeof(DevState), hd.field_bytes, hipMemcpyHostToDevice,
                         d->stream));
+  // the per-tile CFL maxima were written under the saving domain's tiling:
+  // fold every slot into the state's maximum (the same value for the next
+  // Delta t under any tiling)
+  k_fold_tiles<T><<<1, 256, 0, d->stream>>>((const DomDev<T>*)d->ddev, Ly.tiles_max, Ly.tiles_max);
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(d->stream));
   return BQ_OK;
 }
@@ -1005,8 +1127,24 @@ static void drop_graph(Launch& L) {
   L.graph_built = 0;
 }
 
+// one member's committed time, step count and latched status, as gathered
+// by bq_batch_status
+struct StatusRec {
+  double t;
+  long long n;
+  int status, pad;
+};
+
+template <typename T>
+__global__ void k_batch_status(const DomDev<T>* __restrict__ doms, int nd, StatusRec* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nd) return;
+  const DevState* st = doms[k].st;
+  out[k] = StatusRec{st->t, st->n, st->status, 0};
+}
+
 // bytes of the device tables of one member list: DomDev<T>[nd], tile map,
-// line map
+// line map, status staging
 template <typename T>
 static size_t launch_bytes(const std::vector<bq_domain*>& doms) {
   size_t tiles = 0, lines = 0;
@@ -1015,7 +1153,8 @@ static size_t launch_bytes(const std::vector<bq_domain*>& doms) {
     tiles += (size_t)D.tiles_x * D.tiles_y;
     lines += (size_t)D.nx + D.ny;
   }
-  return rup(sizeof(DomDev<T>) * doms.size(), 256) + rup(sizeof(int) * tiles, 256) + rup(sizeof(int) * lines, 256);
+  return rup(sizeof(DomDev<T>) * doms.size(), 256) + rup(sizeof(int) * tiles, 256) + rup(sizeof(int) * lines, 256) +
+         rup(sizeof(StatusRec) * doms.size(), 256);
 }
 
 // defer_graph: leave a stale graph executable to the next step (which
@@ -1032,7 +1171,8 @@ static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, 
     for (int t = 0; t < nt; ++t) tmap.push_back((k << MAP_SHIFT) | t);
     for (int l = 0; l < nl; ++l) lmap.push_back((k << MAP_SHIFT) | l);
   }
-  const size_t tb = rup(sizeof(DomDev<T>) * nd, 256), mb = rup(sizeof(int) * tmap.size(), 256);
+  const size_t tb = rup(sizeof(DomDev<T>) * nd, 256), mb = rup(sizeof(int) * tmap.size(), 256),
+               lb = rup(sizeof(int) * lmap.size(), 256);
   HIPCHK(hipMemcpyAsync(m, tab.data(), sizeof(DomDev<T>) * nd, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(m + tb, tmap.data(), sizeof(int) * tmap.size(), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(m + tb + mb, lmap.data(), sizeof(int) * lmap.size(), hipMemcpyHostToDevice, s));
@@ -1041,11 +1181,14 @@ static int fill_launch(Launch& L, char* m, const std::vector<bq_domain*>& doms, 
   L.table = m;
   L.tile_map = (int*)(m + tb);
   L.line_map = (int*)(m + tb + mb);
+  L.status = m + tb + mb + lb;
   L.nd = nd;
   L.tiles = (int)tmap.size();
   L.lines = (int)lmap.size();
   L.any_pc = 0;
   for (int k = 0; k < nd; ++k) L.any_pc |= tab[k].corrector;
+  L.ty = tab[0].my;
+  L.mx = tab[0].mx;
   return BQ_OK;
 }
 
@@ -1062,6 +1205,16 @@ static int batch_build_t(bq_batch* b) {
   HIPCHK(hipStreamSynchronize(b->stream));
   for (hipStream_t ls : b->lane)
     if (ls) HIPCHK(hipStreamSynchronize(ls));
+  // every member takes the batch's tile shape (the first member's until a
+  // schedule sets one)
+  if (b->ty == 0) {
+    b->ty = desc<T>(b->doms[0]).my;
+    b->mx = desc<T>(b->doms[0]).mx;
+  }
+  for (bq_domain* d : b->doms) {
+    const int rc = set_shape_t<T>(d, b->ty, b->mx);
+    if (rc) return rc;
+  }
   b->lanes = b->lanes_req < nd ? b->lanes_req : nd;
   const int nl = b->lanes;
   std::vector<bq_domain*> part[MAX_LANES];
@@ -1172,7 +1325,6 @@ static int batch_run_t(bq_batch* b, int n_steps) {
 template <typename T>
 static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   if (b->lanes == 1) return profile_t<T>(b->L, b->stream, n_steps, ms_out);
-  constexpr int TY = Cfg<T>::TY, MX = Cfg<T>::MX;
   const int nl = b->lanes;
   hipStream_t* ss = b->lane;
   hipEvent_t ev[MAX_LANES][8] = {};
@@ -1198,10 +1350,7 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
     for (int pass = 0; pass < (last == 7 ? 2 : 1); ++pass) {
       const int e0 = pass == 0 ? 1 : 4;
       for (int l = 0; l < nl; ++l) {
-        const Launch& L = b->G[l];
-        const DomDev<T>* tb0 = (const DomDev<T>*)L.table;
-        if (pass == 0) k_rhs<T, TY, MX, false><<<L.tiles, NT, 0, ss[l]>>>(tb0, L.tile_map, L.nd, L.swizzle);
-        else k_rhs<T, TY, MX, true><<<L.tiles, NT, 0, ss[l]>>>(tb0, L.tile_map, L.nd, L.swizzle);
+        launch_rhs<T>(b->G[l], ss[l], pass);
         (void)hipEventRecord(ev[l][e0 + 1], ss[l]);
       }
       for (int l = 0; l < nl; ++l) {
@@ -1211,10 +1360,7 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
       }
       for (int l = 0; l < nl; ++l) {
         const Launch& L = b->G[l];
-        const DomDev<T>* tb = (const DomDev<T>*)L.table;
-        if (pass == 1) k_final<T, TY, MX, 2><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
-        else if (L.any_pc) k_final<T, TY, MX, 1><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
-        else k_final<T, TY, MX, 0><<<L.tiles, NT, 0, ss[l]>>>(tb, L.tile_map, L.nd);
+        launch_final<T>(L, ss[l], pass == 1 ? 2 : (L.any_pc ? 1 : 0));
         (void)hipEventRecord(ev[l][e0 + 3], ss[l]);
       }
     }
@@ -1236,6 +1382,22 @@ static int batch_profile_t(bq_batch* b, int n_steps, double* ms_out) {
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(b->stream));
   for (int k = 0; k < 4; ++k) ms_out[k] = n_steps > 0 ? acc[k] / n_steps : 0.0;
+  return BQ_OK;
+}
+
+template <typename T>
+static int batch_status_t(bq_batch* b, int32_t* status, int64_t* steps, double* t) {
+  const int nd = b->L.nd;
+  k_batch_status<T><<<cdiv(nd, 64), 64, 0, b->stream>>>((const DomDev<T>*)b->L.table, nd, (StatusRec*)b->L.status);
+  HIPCHK(hipGetLastError());
+  std::vector<StatusRec> h(nd);
+  HIPCHK(hipMemcpyAsync(h.data(), b->L.status, sizeof(StatusRec) * nd, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  for (int k = 0; k < nd; ++k) {
+    status[k] = h[k].status;
+    if (steps) steps[k] = h[k].n;
+    if (t) t[k] = h[k].t;
+  }
   return BQ_OK;
 }
 
@@ -1272,8 +1434,16 @@ static int set_tune(bq_batch* b, const bq_tune* t) {
   if (t->swizzle != 0 && t->swizzle != 1) return fail(BQ_EINVAL, "swizzle must be 0 or 1");
   if (t->reduce_segments != 1 && t->reduce_segments != 4 && t->reduce_segments != 8)
     return fail(BQ_EINVAL, "reduce_segments must be 1, 4 or 8");
-  if (t->lanes != b->lanes_req) {
+  const bool shape = (t->tile_y || t->chunk_x) && (t->tile_y != b->ty || t->chunk_x != b->mx);
+  if (shape && !(b->precision == BQ_FP32 ? shape_ok<float>(t->tile_y, t->chunk_x)
+                                         : shape_ok<double>(t->tile_y, t->chunk_x)))
+    return fail(BQ_EINVAL, "tile shape %d x %d is not a candidate for this precision", t->tile_y, t->chunk_x);
+  if (t->lanes != b->lanes_req || shape) {
     b->lanes_req = t->lanes;
+    if (shape) {
+      b->ty = t->tile_y;
+      b->mx = t->chunk_x;
+    }
     const int rc = DISPATCH(b->precision, batch_build_t, b);
     if (rc) return rc;
   }
@@ -1293,10 +1463,11 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   // The XCD-aware tile order is not searched: it cuts the stencil kernel's
   // HBM traffic by a third (measured) while its effect on a whole step is
   // below the trials' timing noise, so a search would pick it by chance.
+  const int ty0 = b->ty, mx0 = b->mx;
   for (int lanes = 1; lanes <= max_lanes; ++lanes)
     for (int graph : {4, 16}) {
-      for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 1, 0.0});
-      for (int ns : {4, 8}) cands.push_back(bq_tune{lanes, graph, 256, 1, ns, 0.0});
+      for (int rb : {64, 256}) cands.push_back(bq_tune{lanes, graph, rb, 1, 1, ty0, mx0, 0.0});
+      for (int ns : {4, 8}) cands.push_back(bq_tune{lanes, graph, 256, 1, ns, ty0, mx0, 0.0});
     }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (event_new(&e0, true) != hipSuccess || event_new(&e1, true) != hipSuccess) {
@@ -1322,33 +1493,69 @@ static int batch_autotune_t(bq_batch* b, int steps, bq_tune* out) {
   // every candidate twice, in forward then reverse order, scored by the mean:
   // a drift of the clocks over the tuning run (boost after idle, then
   // settling) cancels instead of favouring the first candidates
-  for (size_t k = 0; k < cands.size() && rc == BQ_OK; ++k) rc = trial(cands[k]);
-  for (size_t k = cands.size(); k-- > 0 && rc == BQ_OK;) rc = trial(cands[k]);
+  auto search = [&](std::vector<bq_tune>& cs, int& best) -> int {
+    int r = BQ_OK;
+    for (size_t k = 0; k < cs.size() && r == BQ_OK; ++k) r = trial(cs[k]);
+    for (size_t k = cs.size(); k-- > 0 && r == BQ_OK;) r = trial(cs[k]);
+    if (r) return r;
+    if (getenv("BQ_TUNE_LOG"))
+      for (const bq_tune& c : cs)
+        fprintf(stderr, "bq tune: lanes %d graph %d reduce_block %d segments %d swizzle %d tile %dx64 chunk %d: "
+                "%.4f ms/step\n", c.lanes, c.graph_steps, c.reduce_block, c.reduce_segments, c.swizzle, c.tile_y,
+                c.chunk_x, c.ms_per_step);
+    best = 0;
+    for (size_t k = 1; k < cs.size(); ++k)
+      if (cs[k].ms_per_step < cs[best].ms_per_step) best = (int)k;
+    // candidates within half a percent of the fastest are ties at the
+    // trials' resolution: take the one with the longest graph replays among
+    // them (fewest host launches over a long run)
+    const double tie = 1.005 * cs[best].ms_per_step;
+    for (size_t k = 0; k < cs.size(); ++k)
+      if (cs[k].ms_per_step <= tie && cs[k].graph_steps > cs[best].graph_steps) best = (int)k;
+    return BQ_OK;
+  };
+  // stage 1: the schedule in the current tile shape; stage 2: the tile
+  // shapes under the best schedule (the shape changes the layout of the
+  // line solves, the schedule only the launches)
+  int best = 0;
+  rc = search(cands, best);
+  bq_tune pick = cands[best];
+  if (!rc) {
+    std::vector<bq_tune> shapes;
+    for (int k = 0; k < Cfg<T>::NS; ++k) {
+      bq_tune c = pick;
+      c.tile_y = Cfg<T>::shape(k).ty;
+      c.chunk_x = Cfg<T>::shape(k).mx;
+      c.ms_per_step = 0.0;
+      shapes.push_back(c);
+    }
+    rc = search(shapes, best);
+    pick = shapes[best];
+  }
   event_del(e0);
   event_del(e1);
   if (rc) return rc;
-  if (getenv("BQ_TUNE_LOG"))
-    for (const bq_tune& c : cands)
-      fprintf(stderr, "bq tune: lanes %d graph %d reduce_block %d segments %d swizzle %d: %.4f ms/step\n",
-              c.lanes, c.graph_steps, c.reduce_block, c.reduce_segments, c.swizzle, c.ms_per_step);
-  int best = 0;
-  for (size_t k = 1; k < cands.size(); ++k)
-    if (cands[k].ms_per_step < cands[best].ms_per_step) best = (int)k;
-  // candidates within half a percent of the fastest are ties at the trials'
-  // resolution: take the one with the longest graph replays among them
-  // (fewest host launches over a long run)
-  const double tie = 1.005 * cands[best].ms_per_step;
-  for (size_t k = 0; k < cands.size(); ++k)
-    if (cands[k].ms_per_step <= tie && cands[k].graph_steps > cands[best].graph_steps) best = (int)k;
-  rc = set_tune(b, &cands[best]);
+  rc = set_tune(b, &pick);
   if (rc) return rc;
-  *out = cands[best];
+  *out = pick;
   return BQ_OK;
 }
 
 extern "C" {
 
 int bq_abi_version(void) { return BQ_ABI_VERSION; }
+
+int bq_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src) return fail(BQ_EINVAL, "NULL argument");
+  if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
+    return fail(BQ_EINVAL, "bq_stream_copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+  const size_t n = bytes / 16;
+  if (n == 0) return BQ_OK;
+  if (n / 256 >= (size_t)INT32_MAX) return fail(BQ_EINVAL, "copy too large");
+  k_stream_copy<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>((const u32x4*)src, (u32x4*)dst, n);
+  HIPCHK(hipGetLastError());
+  return BQ_OK;
+}
 
 int bq_live_handles(int32_t* counts) {
   if (!counts) return fail(BQ_EINVAL, "NULL argument");
@@ -1545,10 +1752,11 @@ int bq_batch_set_static(bq_batch* b, bq_domain* const* doms, int32_t n) {
   int rc = check_members(doms, n);
   if (rc) return rc;
   // the one-lane tables plus those of the lane groups (a partition of the
-  // same members: at most as many bytes again, plus the groups' rounding)
+  // same members: at most as many bytes again, plus the groups' rounding of
+  // their four regions)
   const std::vector<bq_domain*> dv(doms, doms + n);
   const size_t one = doms[0]->precision == BQ_FP32 ? launch_bytes<float>(dv) : launch_bytes<double>(dv);
-  const size_t bound = 2 * one + (size_t)MAX_LANES * 3 * 256;
+  const size_t bound = 2 * one + (size_t)MAX_LANES * 4 * 256;
   if (bound > (size_t)BQ_STATIC_TABLE_BYTES)
     return fail(BQ_EINVAL, "%d domains need up to %zu bytes of tables, more than the %zu of the static array", n, bound,
                 (size_t)BQ_STATIC_TABLE_BYTES);
@@ -1583,6 +1791,13 @@ int bq_batch_step(bq_batch* b, int32_t n_steps) {
   const int rc = static_owner_ok(b);
   if (rc) return rc;
   return DISPATCH(b->precision, batch_run_t, b, n_steps);
+}
+
+int bq_batch_status(bq_batch* b, int32_t* status, int64_t* steps, double* t) {
+  if (!b || !status) return fail(BQ_EINVAL, "NULL argument");
+  const int rc = static_owner_ok(b);
+  if (rc) return rc;
+  return DISPATCH(b->precision, batch_status_t, b, status, steps, t);
 }
 
 int bq_batch_sync(bq_batch* b) {
@@ -1626,7 +1841,7 @@ int bq_batch_set_tune(bq_batch* b, const bq_tune* t) {
 
 int bq_batch_get_tune(const bq_batch* b, bq_tune* out) {
   if (!b || !out) return fail(BQ_EINVAL, "NULL argument");
-  *out = bq_tune{b->lanes, b->graph_steps, b->rblock, b->swizzle, b->segs, 0.0};
+  *out = bq_tune{b->lanes, b->graph_steps, b->rblock, b->swizzle, b->segs, b->ty, b->mx, 0.0};
   return BQ_OK;
 }
 

@@ -18,6 +18,7 @@ usable criterion in run-up cases: the kinetic term (P^2 + Q^2) / 2h of thin
 films at the wet/dry front grows without any instability.
 
     python -m paper_1909_04153_amd.robustness [--nx 601] [--t-end 20] [--fp64]
+        [--scenario conical|shelf] [--corrector] [--cfl C]
 """
 from __future__ import annotations
 
@@ -126,16 +127,22 @@ def largest_stable_fixed_dt(spec, t_end, lo, hi, precision=bq.FP32, rel_tol=0.03
 
 
 def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0), log=None, corrector=False,
-          cfl=None):
-    """The conical-island comparison at nx x nx cells over the same 30 m basin
-    (optionally with the Adams-Moulton corrector, and another CFL target)."""
-    dx = 30.0 / (nx - 1) if nx != 601 else 0.05
+          cfl=None, scenario="conical"):
+    """The fixed-versus-adaptive comparison on the conical-island basin (Sec.
+    5.1) at nx x nx cells over the same 30 m, or (scenario "shelf") on the
+    breaking solitary wave over a shelf with an island (Sec. 5.2) at
+    nx x nx/5 cells over the same 40 m x 8 m; optionally with the
+    Adams-Moulton corrector and another CFL target."""
     kw = {}
     if corrector:
         kw.update(corrector=1, fstar_order=2)
     if cfl is not None:
         kw.update(cfl=float(cfl))
-    spec = S.conical_island(nx=nx, ny=nx, dx=dx, **kw)
+    if scenario == "shelf":
+        spec = S.shelf_breaking(nx=nx, ny=nx // 5, dx=40.0 / nx, **kw)
+    else:
+        dx = 30.0 / (nx - 1) if nx != 601 else 0.05
+        spec = S.conical_island(nx=nx, ny=nx, dx=dx, **kw)
     t0 = time.perf_counter()
     ad = run(spec, t_end, precision, snapshots=snapshots)
     t_ad = time.perf_counter() - t0
@@ -176,10 +183,13 @@ def main():
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--corrector", action="store_true", help="AB3 predictor + Adams-Moulton corrector")
     ap.add_argument("--cfl", type=float, default=None, help="CFL target of the adaptive run")
+    ap.add_argument("--scenario", choices=("conical", "shelf"), default="conical")
+    ap.add_argument("--snapshots", default="4,7,10,14", help="times of the local CFL maps, comma separated")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     res = study(a.nx, a.t_end, bq.FP64 if a.fp64 else bq.FP32, log=lambda m: print(m, flush=True),
-                corrector=a.corrector, cfl=a.cfl)
+                corrector=a.corrector, cfl=a.cfl, scenario=a.scenario,
+                snapshots=tuple(float(v) for v in a.snapshots.split(",") if v))
     txt = json.dumps(res)
     print(txt, flush=True)
     if a.out:

@@ -252,6 +252,32 @@ def transposed_solitary(nx=64, ny=1536, dx=0.05, depth=1.0, amp=0.1, y0=8.0, **k
                 Q=Q)
 
 
+def shelf_breaking(nx=400, ny=80, dx=0.1, h_off=0.78, x_toe=10.0, slope=1.0 / 15.0, h_shelf=0.05,
+                   rel_height=0.5, x0=5.0, island_x=28.0, island_r=1.0, island_h=0.25, island_slope=0.25,
+                   manning=0.0, **kw):
+    """Stand-in for the breaking solitary wave over a shelf (Sec. 5.2, the
+    Lynett et al. 2019 experiment, whose gauge data are not available): a
+    flat offshore region of depth h_off, a 1:15 slope up to a shallow shelf
+    of still-water depth h_shelf that runs to the east wall, a conical island
+    on the shelf (top above still water), and a solitary wave of height
+    rel_height * h_off starting at x0, so that it steepens and breaks on the
+    slope and crosses the shelf as a bore; sponge west, walls elsewhere.
+    2D dispersive case: CFL 0.125, linear F* extrapolation."""
+    kw.setdefault("cfl", 0.125)
+    kw.setdefault("fstar_order", 1)
+    p = base_params(nx, ny, dx, bc=(SPONGE, WALL, WALL, WALL), sponge_width=(3.0, 0.0, 0.0, 0.0),
+                    sponge_sigma=2.0, manning_n=manning, runup_delta=slope * dx / 3.0, **kw)
+    Xc, Yc = corner_coords(nx, ny, dx, p["dy"])
+    b = np.minimum(-h_shelf, -h_off + np.maximum(Xc - x_toe, 0.0) * slope)
+    yc = 0.5 * ny * p["dy"]
+    r = np.hypot(Xc - island_x, Yc - yc)
+    b = np.maximum(b, -h_shelf + island_h - np.maximum(r - island_r, 0.0) * island_slope)
+    X, _ = cell_coords(nx, ny, dx, p["dy"])
+    eta, P = solitary_profile(X, x0, rel_height * h_off, h_off)
+    return dict(name=f"shelf_breaking_{nx}x{ny}", params=p, depth_c=-b, eta=eta, P=P, Q=np.zeros_like(eta),
+                center=(island_x, yc), shore_radius=island_r + (island_h - h_shelf) / island_slope)
+
+
 def rip_beach_scaled(nx, ny, seed=190904153, **kw):
     """rip_beach geometry scaled to an nx x ny grid covering the same 1024 m
     cross-shore extent (for parity tests at small sizes)."""
@@ -293,11 +319,25 @@ def batch_mix(n=64, seed=190904154, nx_choices=None, ny_choices=None):
     return out
 
 
+def request_work(spec):
+    """Rough cell-steps of a request: cells x (t_end / Delta t), Delta t from
+    the CFL number and the offshore long-wave speed."""
+    p = spec["params"]
+    h = float(np.max(spec["depth_c"]))
+    dt = p["cfl"] * min(p["dx"], p["dy"]) / math.sqrt(G * h)
+    return p["nx"] * p["ny"] * p["t_end"] / dt
+
+
 def request_stream(n=200, seed=190904155, rho=0.8, capacity_cells_per_s=2.0e10, sides=None,
                    sim_seconds=(60.0, 600.0)):
     """Poisson arrivals of scenario requests of mixed size; returns a list of
-    (arrival_time_s, spec) sorted by arrival.  The arrival rate is set so the
-    offered load is rho times the stated capacity (cell-steps per second)."""
+    (arrival_time_s, spec) sorted by arrival.  Square sides log-uniform on
+    [128, 2048] (multiples of 64), simulated durations uniform on
+    sim_seconds, half plane beaches under a sine wavemaker (CFL 0.2), half
+    rip-channel beaches under JONSWAP waves (2D: CFL 0.125, linear F*
+    extrapolation), each with a seed of its own.  The arrival rate is set so
+    that the offered load (request_work per second) is rho times the stated
+    capacity in cell-steps per second."""
     rng = np.random.default_rng(seed)
     if sides is None:
         lo, hi = math.log(128), math.log(2048)
@@ -310,14 +350,12 @@ def request_stream(n=200, seed=190904155, rho=0.8, capacity_cells_per_s=2.0e10, 
         if rng.uniform() < 0.5:
             s = beach_of_size(side, side, dx=0.1, t_end=dur)
         else:
-            s = rip_beach_scaled(side, side, seed=int(rng.integers(1 << 30)), t_end=dur)
+            s = rip_beach_scaled(side, side, seed=int(rng.integers(1 << 30)), t_end=dur, cfl=0.125,
+                                 fstar_order=1)
         s["params"]["t_end"] = dur
         s["name"] = f"req{k}_{s['name']}"
         reqs.append(s)
-        # rough work estimate: cells x steps at CFL 0.2 and the offshore celerity
-        h = float(np.max(s["depth_c"]))
-        dt = 0.2 * s["params"]["dx"] / math.sqrt(G * h) / 2.0
-        work.append(side * side * dur / dt)
+        work.append(request_work(s))
     lam = rho * capacity_cells_per_s / float(np.mean(work))
     t = 0.0
     out = []

@@ -32,7 +32,8 @@ def _specs():
     return out
 
 
-def test_served_results_equal_solo_runs(mods):
+@pytest.mark.parametrize("static_tables", [True, False])
+def test_served_results_equal_solo_runs(mods, static_tables):
     bq, serve = mods
     specs = _specs()
     solo = []
@@ -46,7 +47,8 @@ def test_served_results_equal_solo_runs(mods):
         solo.append((i.n, [d.read(f) for f in ("eta", "P", "Q")]))
         d.close()
     budget = sum(bq.workspace_bytes(s["params"], bq.FP32) for s in specs[:2]) + 1024
-    srv = serve.Server(budget, max_slots=3, precision=bq.FP32, chunk_steps=8, keep_results=True)
+    srv = serve.Server(budget, max_slots=3, precision=bq.FP32, chunk_steps=8, keep_results=True,
+                       static_tables=static_tables)
     reqs = [serve.Request(k, s, arrival=0.02 * k) for k, s in enumerate(specs)]
     stats = srv.run(reqs, max_wall=120.0)
     assert srv.peak_used <= budget
@@ -56,3 +58,25 @@ def test_served_results_equal_solo_runs(mods):
             assert np.array_equal(r.result[f], x), (r.rid, f)
     summ = stats.summary()
     assert summ["completed"] == len(specs) and summ["p99_s"] >= summ["p50_s"] > 0
+
+
+def test_batch_status_matches_member_sync(mods):
+    # one readback for the whole batch gives each member's status, step
+    # count and time as its own bq_sync does, including a member that
+    # reached t_end (EDONE) while the others continue
+    bq, _ = mods
+    specs = _specs()
+    specs[1]["params"]["t_end"] = 0.05
+    for k in (0, 3):
+        specs[k]["params"]["t_end"] = 30.0
+    doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
+    b = bq.Batch(doms)
+    for static in (False, True):
+        b.set(doms, static=static)
+        b.step(40)
+        st, n, t = b.status()
+        for k, d in enumerate(doms):
+            i = d.sync()
+            assert (st[k], n[k], t[k]) == (i.status, i.n, i.t), (static, k)
+        assert st[1] == bq.EDONE and all(st[k] == bq.OK for k in (0, 2, 3))
+    b.close()
