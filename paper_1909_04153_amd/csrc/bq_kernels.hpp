@@ -134,6 +134,12 @@ __device__ __forceinline__ P* uni(P* p) {
   return (P*)(((unsigned long long)hi << 32) | lo);
 }
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uni(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 // materialise a value in a register at this point (the compiler may not sink
 // its computation to a later use)
 template <typename T>
@@ -153,6 +159,51 @@ template <typename T>
 __device__ __forceinline__ void stu(T* base, unsigned off, T v) {
   const gp<char> b = (gp<char>)(char*)base;
   *(gp<T>)(b + (unsigned)(off * (unsigned)sizeof(T))) = v;
+}
+// N consecutive elements of a field at a block-uniform base, as one vector
+// access (off is a multiple of N and the bases are 256-byte aligned)
+template <typename T, int N>
+struct alignas(sizeof(T) * N) Vec {
+  T v[N];
+};
+template <typename T, int N>
+struct VecRaw;
+template <>
+struct VecRaw<float, 1> {
+  typedef float t;
+};
+template <>
+struct VecRaw<float, 2> {
+  typedef float t __attribute__((ext_vector_type(2)));
+};
+template <>
+struct VecRaw<float, 4> {
+  typedef float t __attribute__((ext_vector_type(4)));
+};
+template <>
+struct VecRaw<double, 1> {
+  typedef double t;
+};
+template <>
+struct VecRaw<double, 2> {
+  typedef double t __attribute__((ext_vector_type(2)));
+};
+template <int N, typename T>
+__device__ __forceinline__ Vec<T, N> ldv(const T* base, unsigned off) {
+  using R = typename VecRaw<T, N>::t;
+  const gp<const char> b = (gp<const char>)(const char*)base;
+  const R x = *(gp<const R>)(b + (unsigned)(off * (unsigned)sizeof(T)));
+  Vec<T, N> r;
+  __builtin_memcpy(&r, &x, sizeof r);
+  return r;
+}
+template <int N, typename T>
+__device__ __forceinline__ void stv(T* base, unsigned off, const Vec<T, N>& v) {
+  using R = typename VecRaw<T, N>::t;
+  R x;
+  __builtin_memcpy(&x, &v, sizeof x);
+  const gp<char> b = (gp<char>)(char*)base;
+  *(gp<R>)(b + (unsigned)(off * (unsigned)sizeof(T))) = x;
 }
 
 // Square root, reciprocal and cube root.  FP64 uses the correctly rounded
@@ -766,23 +817,29 @@ struct alignas(16) RhsSmem {
   // LDS row pitch of the radius-2 tiles: 5 mod 64 words, so the x-segment
   // threads (stride 4 within a row, 4 rows per wave) hit 64 distinct banks
   static constexpr int LW = WX + 1;
-  static constexpr int AXP = TX + 1;                  // row pitch of ax (same reason)
+  static constexpr int AXP = TX + 1;                  // row pitch of ay (same reason)
+  // the corner tile is staged in pairs from corner i0 - 2, one corner past
+  // the CXN used; its row pitch is 9 mod 64 words for the face passes
+  static constexpr int CP = CXN + 4;
+  // the weighted P/Q history is kept on radius-1 rows in the columns of the
+  // radius-2 tile (its pairs load like the radius-2 rows)
+  static constexpr int PW = WX + 1;
   T w[WY * LW];
   T p[WY * LW];
   T q[WY * LW];
   T db[WY * LW];                                      // cell still-water depth
   union {
     struct {
-      T pt[BY * BX];                                  // sum_k beta_k P^{n-k} (until the F* terms are formed)
-      T qt[BY * BX];
+      T pt[BY * PW];                                  // sum_k beta_k P^{n-k} (until the F* terms are formed)
+      T qt[BY * PW];
     } h;
-    T ax[3][TY * AXP];                                // x-direction parts of E, F, G per cell
+    T ay[3][TY * AXP];                                // y-direction parts of E, F, G per cell
     struct {
       T u[TY * TXP];
       T v[TY * TXP];
     } s;
   } x;
-  T dc[CYN * CXN];
+  T dc[CYN * CP];
 };
 
 // CORR = false: the AB3 step of Eq. (42)-(43) from level n (the predictor
@@ -795,9 +852,11 @@ template <typename T, int TY, int MX, bool CORR>
 __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                            int nd, int swizzle) {
   using S = RhsSmem<T, TY, MX>;
-  constexpr int WX = S::WX, LW = S::LW, AXP = S::AXP, BX = S::BX, CXN = S::CXN, TXP = S::TXP;
+  constexpr int WX = S::WX, LW = S::LW, AXP = S::AXP, CXN = S::CXN, CP = S::CP, PW = S::PW, TXP = S::TXP;
   constexpr int CPT = (TX * TY) / NT;                 // cells per thread
   static_assert((TX * TY) % NT == 0, "tile must be a multiple of the block");
+  using V = Vec<T, CPT>;
+  using V2 = Vec<T, 2>;
   __shared__ S sm;
   int dom, tile;
   // swizzle = 1: XCD-aware tile order (each XCD walks a contiguous run)
@@ -808,91 +867,79 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   if (CORR && !D.corrector) return;
   const int i0 = (tile % D.tiles_x) * TX, j0 = (tile / D.tiles_x) * TY;
   const int nx = D.nx, ny = D.ny, tid = threadIdx.x;
+  // The step's scalars are read (and made wave-uniform) before any field
+  // load is issued: the state is read through vector loads, whose waits are
+  // in issue order and would otherwise also wait for the field loads.
   const int slot = uni(st->slot), par = uni((int)(st->n & 1));
   const int s1 = slot == 0 ? 2 : slot - 1, s2 = slot == 2 ? 0 : slot + 1;
-  const T beta0 = CORR ? T(1) : (T)st->beta[0];
-  const T beta1 = CORR ? T(-1) : (T)st->beta[1];
-  const T beta2 = CORR ? T(0) : (T)st->beta[2];
-  const bool hist = CORR || st->beta[0] != 0.0 || st->beta[1] != 0.0 || st->beta[2] != 0.0;
+  const double sb0 = uni(st->beta[0]), sb1 = uni(st->beta[1]), sb2 = uni(st->beta[2]);
+  const double sa0 = uni(CORR ? st->gamma[0] : st->alpha[0]), sa1 = uni(CORR ? st->gamma[1] : st->alpha[1]);
+  const double sa2 = uni(CORR ? st->gamma[2] : st->alpha[2]), sa3 = CORR ? uni(st->gamma[3]) : 0.0;
+  const T beta0 = CORR ? T(1) : (T)sb0;
+  const T beta1 = CORR ? T(-1) : (T)sb1;
+  const T beta2 = CORR ? T(0) : (T)sb2;
+  const bool hist = CORR || sb0 != 0.0 || sb1 != 0.0 || sb2 != 0.0;
   const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
-  // Cells of a thread in the per-cell phases: column cY, rows rY0 .. rY0+CPT-1
-  // (consecutive rows, so the vertical stencils of a thread's cells overlap).
-  const int cY = tid % TX, rY0 = (tid / TX) * CPT;
-  static_assert((NT / TX) * CPT == TY, "per-cell mapping covers the tile");
-  const unsigned oI = (unsigned)((j0 + rY0) * ipitch + i0 + cY);          // interior fields
-  const unsigned oG = (unsigned)((j0 + rY0 + 2) * pitch + xoff + i0 + cY);  // ghosted fields
+  // Cells of a thread in the per-cell phases: row vr, columns vc .. vc+CPT-1
+  // (consecutive columns: one vector access per field, and the x-face pass
+  // below takes the same cells, so its results stay in registers).
+  constexpr int SPR = TX / CPT;
+  static_assert(SPR * TY == NT, "one row segment per thread");
+  const int vr = tid / SPR, vc = (tid - vr * SPR) * CPT;
+  const unsigned oI = (unsigned)((j0 + vr) * ipitch + i0 + vc);          // interior fields
+  const unsigned oG = (unsigned)((j0 + vr + 2) * pitch + xoff + i0 + vc);  // ghosted fields
 
   // ---- phase 0: issue every load of the tile before the first LDS store ----
-  // Each LDS tile of width Wd is read RG = NT / Wd rows per round: thread
-  // (r0, c) = (tid / Wd, tid % Wd) loads rows r0 + RG k, so the LDS index is
+  // The halo tiles are read in pairs of cells (8 or 16 bytes per lane): a
+  // radius-2 row is NP pairs from cell i0 - 2, a corner row NPC pairs from
+  // corner i0 - 2; thread (r0, c) loads rows r0 + RG k, so the LDS index is
   // a per-thread base plus a constant.  The threads beyond RG whole rows and
   // the rows past the tile in the last round repeat a row of the tile (same
   // values to the same LDS words), so every round is branch-free.  The
   // workspace pads every field to whole tiles plus the halo, so no index is
   // clamped to the domain: values outside it only reach cells outside it.
-  constexpr int RGW = NT / WX, KW = (S::WY + RGW - 1) / RGW;
-  constexpr int RGC = NT / CXN, KC = (S::CYN + RGC - 1) / RGC;
-  constexpr int RGB = NT / BX, KB = (S::BY + RGB - 1) / RGB;
-  const int rW = min(tid / WX, RGW - 1), cW = tid - (tid / WX) * WX;
-  const int rC = min(tid / CXN, RGC - 1), cC = tid - (tid / CXN) * CXN;
-  const int rB = min(tid / BX, RGB - 1), cB = tid - (tid / BX) * BX;
-  auto rowW = [&](int k) { return k < KW - 1 ? rW + RGW * k : min(rW + RGW * k, S::WY - 1); };
+  constexpr int NP = WX / 2, RGP = NT / NP;
+  constexpr int KW = (S::WY + RGP - 1) / RGP, KB = (S::BY + RGP - 1) / RGP;
+  constexpr int NPC = (CXN + 1) / 2, RGC = NT / NPC, KC = (S::CYN + RGC - 1) / RGC;
+  const int rP = min(tid / NP, RGP - 1), cP = 2 * (tid - (tid / NP) * NP);
+  const int rC = min(tid / NPC, RGC - 1), cC = 2 * (tid - (tid / NPC) * NPC);
+  auto rowW = [&](int k) { return k < KW - 1 ? rP + RGP * k : min(rP + RGP * k, S::WY - 1); };
+  auto rowB = [&](int k) { return k < KB - 1 ? rP + RGP * k : min(rP + RGP * k, S::BY - 1); };
   auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
-  auto rowB = [&](int k) { return k < KB - 1 ? rB + RGB * k : min(rB + RGB * k, S::BY - 1); };
-  // E, F, G history of this thread's cells (consumed in phase 2)
-  // combined as the AB3 history terms alpha_1 X^{n-1} + alpha_2 X^{n-2}
-  // (Eq. 42) right away, so three values per cell stay live, not six; the
-  // corrector's terms are gamma_1 X^n + gamma_2 X^{n-1} + gamma_3 X^{n-2}
-  const T a1 = (T)(CORR ? st->gamma[1] : st->alpha[1]), a2 = (T)(CORR ? st->gamma[2] : st->alpha[2]);
-  T hE[CPT], hF[CPT], hG[CPT];
-  {
-    const int l1 = CORR ? slot : s1, l2 = CORR ? s1 : s2;
-    const T* E1 = uni((const T*)D.E[l1]);
-    const T* E2 = uni((const T*)D.E[l2]);
-    const T* F1 = uni((const T*)D.F[l1]);
-    const T* F2 = uni((const T*)D.F[l2]);
-    const T* G1 = uni((const T*)D.G[l1]);
-    const T* G2 = uni((const T*)D.G[l2]);
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const unsigned o = oI + (unsigned)(q * ipitch);
-      hE[q] = a1 * ldu(E1, o) + a2 * ldu(E2, o);
-      hF[q] = a1 * ldu(F1, o) + a2 * ldu(F2, o);
-      hG[q] = a1 * ldu(G1, o) + a2 * ldu(G2, o);
-    }
-    if (CORR) {
-      const T a3 = (T)st->gamma[3];
-      const T* E3 = uni((const T*)D.E[s2]);
-      const T* F3 = uni((const T*)D.F[s2]);
-      const T* G3 = uni((const T*)D.G[s2]);
-#pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const unsigned o = oI + (unsigned)(q * ipitch);
-        hE[q] += a3 * ldu(E3, o);
-        hF[q] += a3 * ldu(F3, o);
-        hG[q] += a3 * ldu(G3, o);
-      }
-    }
-  }
-  T rw[KW], rp[KW], rq[KW], rc[KC], h1p[KB], h2p[KB], h1q[KB], h2q[KB];
+  // the history fields' addresses first (a wait for a descriptor read
+  // would also wait for every field load issued before it)
+  const int l1 = CORR ? slot : s1, l2 = CORR ? s1 : s2;
+  const T* const pE1 = uni((const T*)D.E[l1]);
+  const T* const pE2 = uni((const T*)D.E[l2]);
+  const T* const pF1 = uni((const T*)D.F[l1]);
+  const T* const pF2 = uni((const T*)D.F[l2]);
+  const T* const pG1 = uni((const T*)D.G[l1]);
+  const T* const pG2 = uni((const T*)D.G[l2]);
+  const T* const pE3 = CORR ? uni((const T*)D.E[s2]) : nullptr;
+  const T* const pF3 = CORR ? uni((const T*)D.F[s2]) : nullptr;
+  const T* const pG3 = CORR ? uni((const T*)D.G[s2]) : nullptr;
+  V2 rw[KW], rp[KW], rq[KW], rc[KC], h1p[KB], h2p[KB], h1q[KB], h2q[KB];
+  // keep the load groups in this order (the waits are in issue order)
+  __builtin_amdgcn_sched_barrier(0);
   {
     // the state the spatial operator is taken of: level n, or the predicted level
     const T* w = uni((const T*)(CORR ? D.w[2] : D.w[par]));
     const T* Pn = uni((const T*)D.P[CORR ? s2 : slot]);
     const T* Qn = uni((const T*)D.Q[CORR ? s2 : slot]);
-    const unsigned oW = (unsigned)(j0 * pitch + xoff + i0 - 2 + cW);       // radius-2 tile
+    const unsigned oW = (unsigned)(j0 * pitch + xoff + i0 - 2 + cP);       // radius-2 tile
 #pragma unroll
     for (int k = 0; k < KW; ++k) {
       const unsigned o = oW + (unsigned)(rowW(k) * pitch);
-      rw[k] = ldu(w, o);
-      rp[k] = ldu(Pn, o);
-      rq[k] = ldu(Qn, o);
+      rw[k] = ldv<2>(w, o);
+      rp[k] = ldv<2>(Pn, o);
+      rq[k] = ldv<2>(Qn, o);
     }
     const T* Dc = uni((const T*)D.Dc);
-    const unsigned oC = (unsigned)(j0 * cpitch + i0 + cC);                 // corners
+    const unsigned oC = (unsigned)(j0 * cpitch + i0 + cC);                 // corners from i0 - 2
 #pragma unroll
-    for (int k = 0; k < KC; ++k) rc[k] = ldu(Dc, oC + (unsigned)(rowC(k) * cpitch));
-    const unsigned oB = (unsigned)((j0 + 1) * pitch + xoff + i0 - 1 + cB);   // radius-1 tile
+    for (int k = 0; k < KC; ++k) rc[k] = ldv<2>(Dc, oC + (unsigned)(rowC(k) * cpitch));
+    // radius-1 rows j0-1 .. j0+TY, in the radius-2 tile's columns
+    const unsigned oB = (unsigned)((j0 + 1) * pitch + xoff + i0 - 2 + cP);
     if (CORR) {
       // level n, for the change of the F*, G* terms
       const T* P1 = uni((const T*)D.P[slot]);
@@ -900,11 +947,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         const unsigned o = oB + (unsigned)(rowB(k) * pitch);
-        h1p[k] = ldu(P1, o);
-        h1q[k] = ldu(Q1, o);
-        h2p[k] = h2q[k] = T(0);
+        h1p[k] = ldv<2>(P1, o);
+        h1q[k] = ldv<2>(Q1, o);
+        h2p[k] = h2q[k] = V2{{T(0), T(0)}};
       }
-    } else if (hist) {
+    } else {
+      // loaded also before the history exists (the values are then not
+      // used): a branch here would make the waits before the first LDS
+      // stores cover these loads as well
       const T* P1 = uni((const T*)D.P[s1]);
       const T* P2 = uni((const T*)D.P[s2]);
       const T* Q1 = uni((const T*)D.Q[s1]);
@@ -912,90 +962,111 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         const unsigned o = oB + (unsigned)(rowB(k) * pitch);
-        h1p[k] = ldu(P1, o);
-        h2p[k] = ldu(P2, o);
-        h1q[k] = ldu(Q1, o);
-        h2q[k] = ldu(Q2, o);
+        h1p[k] = ldv<2>(P1, o);
+        h2p[k] = ldv<2>(P2, o);
+        h1q[k] = ldv<2>(Q1, o);
+        h2q[k] = ldv<2>(Q2, o);
       }
-    } else {
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  // E, F, G history of this thread's cells, issued last: they are consumed
+  // only in phase 2, so the waits before the first LDS stores do not cover
+  // them and their latency overlaps the phases in between
+  const V e1 = ldv<CPT>(pE1, oI), e2 = ldv<CPT>(pE2, oI);
+  const V f1 = ldv<CPT>(pF1, oI), f2 = ldv<CPT>(pF2, oI);
+  const V g1 = ldv<CPT>(pG1, oI), g2 = ldv<CPT>(pG2, oI);
+  V e3, f3, g3;
+  if (CORR) {
+    e3 = ldv<CPT>(pE3, oI);
+    f3 = ldv<CPT>(pF3, oI);
+    g3 = ldv<CPT>(pG3, oI);
+  }
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int k = 0; k < KB; ++k) h1p[k] = h2p[k] = h1q[k] = h2q[k] = T(0);
+  for (int k = 0; k < KW; ++k) {
+    const int e = rowW(k) * LW + cP;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      sm.w[e + u] = rw[k].v[u];
+      sm.p[e + u] = rp[k].v[u];
+      sm.q[e + u] = rq[k].v[u];
     }
   }
 #pragma unroll
-  for (int k = 0; k < KW; ++k) {
-    const int e = rowW(k) * LW + cW;
-    sm.w[e] = rw[k];
-    sm.p[e] = rp[k];
-    sm.q[e] = rq[k];
+  for (int k = 0; k < KC; ++k) {
+    sm.dc[rowC(k) * CP + cC] = rc[k].v[0];
+    sm.dc[rowC(k) * CP + cC + 1] = rc[k].v[1];
   }
-#pragma unroll
-  for (int k = 0; k < KC; ++k) sm.dc[rowC(k) * CXN + cC] = rc[k];
   __syncthreads();
   // weighted P/Q history (level n from the staged tile) and cell depths
 #pragma unroll
   for (int k = 0; k < KB; ++k) {
     const int r = rowB(k);
-    const int t2 = (r + 1) * LW + cB + 1;             // same cell in the radius-2 tile
-    sm.x.h.pt[r * BX + cB] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k] + beta2 * h2p[k] : T(0);
-    sm.x.h.qt[r * BX + cB] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k] + beta2 * h2q[k] : T(0);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t2 = (r + 1) * LW + cP + u;           // same cell in the radius-2 tile
+      sm.x.h.pt[r * PW + cP + u] = hist ? beta0 * sm.p[t2] + beta1 * h1p[k].v[u] + beta2 * h2p[k].v[u] : T(0);
+      sm.x.h.qt[r * PW + cP + u] = hist ? beta0 * sm.q[t2] + beta1 * h1q[k].v[u] + beta2 * h2q[k].v[u] : T(0);
+    }
   }
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
-    const int c0 = rowW(k) * CXN + cW;
-    sm.db[rowW(k) * LW + cW] = dbar4(sm.dc[c0], sm.dc[c0 + 1], sm.dc[c0 + CXN], sm.dc[c0 + CXN + 1]);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int c0 = rowW(k) * CP + cP + u;
+      sm.db[rowW(k) * LW + cP + u] = dbar4(sm.dc[c0], sm.dc[c0 + 1], sm.dc[c0 + CP], sm.dc[c0 + CP + 1]);
+    }
   }
 
   __syncthreads();
   // F*, G* terms of this thread's cells (Eq. 14-15 are linear, so
-  // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k})), folded into the AB3
-  // history terms of U*, V* (Eq. 43); after them the history tiles' LDS
-  // holds the x-parts of the face pass
+  // sum_k beta_k F*^{n-k} = F*(sum_k beta_k Q^{n-k})), added to the AB3
+  // history terms of U*, V* (Eq. 43) in phase 2; after them the history
+  // tiles' LDS holds the y-parts of the face pass
+  T fsF[CPT], fsG[CPT];
   {
     const T i2dx = D.i2dx, i2dy = D.i2dy, i4dxdy = D.i4dxdy, Bc = D.Bc;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int r = rY0 + q, c = cY;
+    for (int k = 0; k < CPT; ++k) {
+      const int r = vr, c = vc + k;
       const int C0 = (r + 2) * LW + c + 2;
       const T d0 = dpos(sm.db[C0]);
       const T ddx = (dpos(sm.db[C0 + 1]) - dpos(sm.db[C0 - 1])) * i2dx;
       const T ddy = (dpos(sm.db[C0 + LW]) - dpos(sm.db[C0 - LW])) * i2dy;
-      const int B0 = (r + 1) * BX + c + 1;
-      const T qy = (sm.x.h.qt[B0 + BX] - sm.x.h.qt[B0 - BX]) * i2dy;
+      const int B0 = (r + 1) * PW + c + 2;
+      const T qy = (sm.x.h.qt[B0 + PW] - sm.x.h.qt[B0 - PW]) * i2dy;
       const T qx = (sm.x.h.qt[B0 + 1] - sm.x.h.qt[B0 - 1]) * i2dx;
-      const T qxy = ((sm.x.h.qt[B0 + BX + 1] - sm.x.h.qt[B0 - BX + 1]) -
-                     (sm.x.h.qt[B0 + BX - 1] - sm.x.h.qt[B0 - BX - 1])) * i4dxdy;
-      const T py = (sm.x.h.pt[B0 + BX] - sm.x.h.pt[B0 - BX]) * i2dy;
+      const T qxy = ((sm.x.h.qt[B0 + PW + 1] - sm.x.h.qt[B0 - PW + 1]) -
+                     (sm.x.h.qt[B0 + PW - 1] - sm.x.h.qt[B0 - PW - 1])) * i4dxdy;
+      const T py = (sm.x.h.pt[B0 + PW] - sm.x.h.pt[B0 - PW]) * i2dy;
       const T px = (sm.x.h.pt[B0 + 1] - sm.x.h.pt[B0 - 1]) * i2dx;
-      const T pxy = ((sm.x.h.pt[B0 + BX + 1] - sm.x.h.pt[B0 - BX + 1]) -
-                     (sm.x.h.pt[B0 + BX - 1] - sm.x.h.pt[B0 - BX - 1])) * i4dxdy;
-      hF[q] += d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
-      hG[q] += d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
-      pin(hE[q]);
-      pin(hF[q]);
-      pin(hG[q]);
+      const T pxy = ((sm.x.h.pt[B0 + PW + 1] - sm.x.h.pt[B0 - PW + 1]) -
+                     (sm.x.h.pt[B0 + PW - 1] - sm.x.h.pt[B0 - PW - 1])) * i4dxdy;
+      fsF[k] = d0 * ddx * qy * T(1.0 / 6.0) + d0 * ddy * qx * T(1.0 / 6.0) + Bc * d0 * d0 * qxy;
+      fsG[k] = d0 * ddx * py * T(1.0 / 6.0) + d0 * ddy * px * T(1.0 / 6.0) + Bc * d0 * d0 * pxy;
+      pin(fsF[k]);
+      pin(fsG[k]);
     }
   }
   __syncthreads();
   const T g = D.g, eps = D.eps, ht = T(0.5) * D.theta;
   const T idx = D.idx, idy = D.idy;
-  // ---- phase 1x: x-faces by row segments ----------------------------------
-  // Thread (row rx, cells cx0 .. cx0+CPT-1) reconstructs cells cx0-1 ..
-  // cx0+CPT once, takes the CPT+1 faces between them (the last one is also
-  // its right neighbour's first) and writes the x-parts of its cells' E, F, G
-  // (flux differences plus the x bed-slope source) to LDS.
-  constexpr int SPR = TX / CPT;
-  static_assert(SPR * TY == NT, "one x-segment per thread");
+  // ---- phase 1x: x-faces by row segments, kept in registers -----------------
+  // The thread's own cells: it reconstructs cells vc-1 .. vc+CPT once, takes
+  // the CPT+1 faces between them (the last one is also its right
+  // neighbour's first) and keeps the x-parts of its cells' E, F, G (flux
+  // differences plus the x bed-slope source).
+  T acc_e[CPT], acc_f[CPT], acc_g[CPT];
   {
-    const int rx = tid / SPR, cx0 = (tid - rx * SPR) * CPT;
-    const T* wr = sm.w + (rx + 2) * LW + cx0;         // tile column cx0 = cell cx0 - 2
-    const T* pr = sm.p + (rx + 2) * LW + cx0;
-    const T* qr = sm.q + (rx + 2) * LW + cx0;
-    const T* c0 = sm.dc + (rx + 2) * CXN + cx0 + 1;   // corners of face cx0 - 1
-    T Dfx[CPT + 3];                                   // still-water depth of face cx0 - 1 + k
+    const T* wr = sm.w + (vr + 2) * LW + vc;          // tile column vc = cell vc - 2
+    const T* pr = sm.p + (vr + 2) * LW + vc;
+    const T* qr = sm.q + (vr + 2) * LW + vc;
+    const T* c0 = sm.dc + (vr + 2) * CP + vc + 1;     // corners of face vc - 1
+    T Dfx[CPT + 3];                                   // still-water depth of face vc - 1 + k
 #pragma unroll
-    for (int k = 0; k < CPT + 3; ++k) Dfx[k] = T(0.5) * (c0[k] + c0[k + CXN]);
-    // cell cx0 - 1 + k at its low (l) and high (h) faces
+    for (int k = 0; k < CPT + 3; ++k) Dfx[k] = T(0.5) * (c0[k] + c0[k + CP]);
+    // cell vc - 1 + k at its low (l) and high (h) faces
     T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
     // limited (theta > 0) or central slopes: one uniform branch per tile
     auto recon = [&](auto lim) {
@@ -1016,23 +1087,22 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     T f0w = T(0), fnw = T(0), ftw = T(0), dvw = T(0);  // west face of the cell being closed
 #pragma unroll
     for (int m = 0; m <= CPT; ++m) {
-      // face cx0 + m between cells cx0 + m - 1 (k = m) and cx0 + m (k = m + 1)
+      // face vc + m between cells vc + m - 1 (k = m) and vc + m (k = m + 1)
       const T Df = Dfx[m + 1];
       const Side<T> L = make_side(wh[m], ph[m], qh[m], Df, eps, g);
       const Side<T> R = make_side(wl[m + 1], pl[m + 1], ql[m + 1], Df, eps, g);
       T f0, fn, ft;
       cu_flux(L, R, g, Df, f0, fn, ft);
       if (m > 0) {
-        // cell cx0 + m - 1: well-balanced bed source -g h b_x with h the mean
+        // cell vc + m - 1: well-balanced bed source -g h b_x with h the mean
         // of its own face depths; with the still-water parts of the pressure
         // fluxes taken out only the face-depth departures remain
         const T Dw = Dfx[m], De = Dfx[m + 1];
         T bed = g * (De - Dw) * (T(0.5) * (L.dev + dvw));
         add_shore(bed, Dw, De, g);
-        const int o = rx * AXP + cx0 + m - 1;
-        sm.x.ax[0][o] = -(f0 - f0w) * idx;
-        sm.x.ax[1][o] = (bed - (fn - fnw)) * idx;
-        sm.x.ax[2][o] = -(ft - ftw) * idx;
+        acc_e[m - 1] = -(f0 - f0w) * idx;
+        acc_f[m - 1] = (bed - (fn - fnw)) * idx;
+        acc_g[m - 1] = -(ft - ftw) * idx;
       }
       f0w = f0;
       fnw = fn;
@@ -1040,17 +1110,17 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       dvw = R.dev;
     }
   }
-  // ---- phase 1y: y-faces by column segments, kept in registers ---------------
+  // ---- phase 1y: y-faces by column segments, parts to LDS -------------------
   // normal = Q, tangential = P; thread cells (rY0 + q, cY)
-  T acc_e[CPT], acc_f[CPT], acc_g[CPT];
   {
+    const int cY = tid % TX, rY0 = (tid / TX) * CPT;
     const T* wc = sm.w + rY0 * LW + cY + 2;           // tile row rY0 = row rY0 - 2
     const T* pc = sm.p + rY0 * LW + cY + 2;
     const T* qc = sm.q + rY0 * LW + cY + 2;
-    const T* c0 = sm.dc + (rY0 + 1) * CXN + cY + 2;   // corners of face rY0 - 1
+    const T* c0 = sm.dc + (rY0 + 1) * CP + cY + 2;    // corners of face rY0 - 1
     T Dfy[CPT + 3];
 #pragma unroll
-    for (int k = 0; k < CPT + 3; ++k) Dfy[k] = T(0.5) * (c0[k * CXN] + c0[k * CXN + 1]);
+    for (int k = 0; k < CPT + 3; ++k) Dfy[k] = T(0.5) * (c0[k * CP] + c0[k * CP + 1]);
     T wl[CPT + 2], wh[CPT + 2], pl[CPT + 2], ph[CPT + 2], ql[CPT + 2], qh[CPT + 2];
     auto recon = [&](auto lim) {
       constexpr bool LIM = decltype(lim)::value;
@@ -1079,9 +1149,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
         const T Ds = Dfy[m], Dn = Dfy[m + 1];
         T bed = g * (Dn - Ds) * (T(0.5) * (Sd.dev + dvs));
         add_shore(bed, Ds, Dn, g);
-        acc_e[m - 1] = -(f0 - f0s) * idy;
-        acc_f[m - 1] = -(ft - fts) * idy;              // x-momentum through y-faces
-        acc_g[m - 1] = (bed - (fn - fns)) * idy;       // y-momentum
+        const int o = (rY0 + m - 1) * AXP + cY;
+        sm.x.ay[0][o] = -(f0 - f0s) * idy;
+        sm.x.ay[1][o] = -(ft - fts) * idy;            // x-momentum through y-faces
+        sm.x.ay[2][o] = (bed - (fn - fns)) * idy;     // y-momentum
       }
       f0s = f0;
       fns = fn;
@@ -1093,29 +1164,51 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 
   // ---- phase 2: per-cell right-hand sides and AB3 update -------------------
   const T B = D.B, gn2 = D.gn2, cf = D.cf;
-  const T a0 = (T)(CORR ? st->gamma[0] : st->alpha[0]);
+  const T a0 = (T)sa0;
   T* const wn = uni(CORR ? D.w[par ^ 1] : (D.corrector ? D.w[2] : D.w[par ^ 1]));
   const T* const wbase = uni((const T*)D.w[par]);   // w^n (the corrector's base)
-  T* const E0 = uni(D.E[slot]);
-  T* const F0 = uni(D.F[slot]);
-  T* const G0 = uni(D.G[slot]);
-  // The thread's cells are consecutive rows of one column, and the body is
+  // The thread's cells are consecutive columns of one row, and the body is
   // branch-free, so the stencil reads and the eta / depth values they share
   // are formed once for all of them (cells outside the domain compute
   // harmless values and store nothing).
   const T i2dx = D.i2dx, i2dy = D.i2dy, idx2 = D.idx2, idy2 = D.idy2, i4dxdy = D.i4dxdy;
   const T i2dx3 = D.i2dx3, i2dy3 = D.i2dy3, i2dxdy2 = D.i2dxdy2, i2dx2dy = D.i2dx2dy;
   const T Bg = B * g;
-  static_assert(S::AXP == TXP, "U*, V* alias the x-parts cell by cell");
+  static_assert(S::AXP == TXP, "U*, V* alias the y-parts cell by cell");
+  const bool row_in = j0 + vr < ny;
+  const bool all_in = row_in && i0 + vc + CPT <= nx;
+  // AB3 history terms alpha_1 X^{n-1} + alpha_2 X^{n-2} (Eq. 42), the
+  // corrector's gamma_1 X^n + gamma_2 X^{n-1} + gamma_3 X^{n-2}
+  T hE[CPT], hF[CPT], hG[CPT];
+  {
+    const T a1 = (T)sa1, a2 = (T)sa2;
+    const T a3 = CORR ? (T)sa3 : T(0);
 #pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int r = rY0 + q, c = cY;
-    const bool in = (i0 + c < nx) & (j0 + r < ny);
+    for (int k = 0; k < CPT; ++k) {
+      hE[k] = a1 * e1.v[k] + a2 * e2.v[k];
+      hF[k] = a1 * f1.v[k] + a2 * f2.v[k];
+      hG[k] = a1 * g1.v[k] + a2 * g2.v[k];
+      if (CORR) {
+        hE[k] += a3 * e3.v[k];
+        hF[k] += a3 * f3.v[k];
+        hG[k] += a3 * g3.v[k];
+      }
+      hF[k] += fsF[k];
+      hG[k] += fsG[k];
+    }
+  }
+  V ve, vf, vg, vw;
+  V wb;
+  if (CORR) wb = ldv<CPT>(wbase, oG);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int r = vr, c = vc + k;
+    const bool in = row_in & (i0 + c < nx);
     const int C0 = (r + 2) * LW + c + 2;   // radius-2 tile index of the cell
     const int o = r * AXP + c;
-    T e_ = sm.x.ax[0][o] + acc_e[q];
-    T f_ = sm.x.ax[1][o] + acc_f[q];
-    T g_ = sm.x.ax[2][o] + acc_g[q];
+    T e_ = acc_e[k] + sm.x.ay[0][o];
+    T f_ = acc_f[k] + sm.x.ay[1][o];
+    T g_ = acc_g[k] + sm.x.ay[2][o];
     const T Db = sm.db[C0];
     const T d0 = dpos(Db);
     const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
@@ -1146,30 +1239,49 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     const T Pc = sm.p[C0], Qc = sm.q[C0];
     if (gn2 > T(0) || cf > T(0)) {
       const T h = fmax(sm.w[C0] + Db, T(0));
-      const T vf = vfac(h, eps);
-      const T u = Pc * vf, v = Qc * vf;
-      const T k = h > T(0) ? (gn2 * frcbrt(h) + cf) * fsqrt(u * u + v * v) : T(0);
-      f_ -= k * u;
-      g_ -= k * v;
+      const T vfc = vfac(h, eps);
+      const T u = Pc * vfc, v = Qc * vfc;
+      const T kf = h > T(0) ? (gn2 * frcbrt(h) + cf) * fsqrt(u * u + v * v) : T(0);
+      f_ -= kf * u;
+      g_ -= kf * v;
     }
     // Eq. (42)-(43)
-    if (in) {
-      const unsigned ii = oI + (unsigned)(q * ipitch);
-      const unsigned og = oG + (unsigned)(q * pitch);
-      if (!CORR) {
-        stu(E0, ii, e_);
-        stu(F0, ii, f_);
-        stu(G0, ii, g_);
-      }
-      stu(wn, og, (CORR ? ldu(wbase, og) : sm.w[C0]) + (a0 * e_ + hE[q]));
-    }
+    ve.v[k] = e_;
+    vf.v[k] = f_;
+    vg.v[k] = g_;
+    vw.v[k] = (CORR ? wb.v[k] : sm.w[C0]) + (a0 * e_ + hE[k]);
     // increments U*^{n+1} - U*^n, V*^{n+1} - V*^n (Eq. 43); the line solves
     // below act on them: P^{n+1} = P^n + T^-1 (U*^{n+1} - U*^n) since
     // U*^n = T P^n with the same matrix.  They overwrite this cell's own
-    // x-parts (same word of the union), which no other thread reads, so no
+    // y-parts (same word of the union), which no other thread reads, so no
     // barrier is needed between the two.
-    sm.x.s.u[o] = in ? a0 * f_ + hF[q] : T(0);
-    sm.x.s.v[o] = in ? a0 * g_ + hG[q] : T(0);
+    sm.x.s.u[o] = in ? a0 * f_ + hF[k] : T(0);
+    sm.x.s.v[o] = in ? a0 * g_ + hG[k] : T(0);
+  }
+  {
+    T* const E0 = uni(D.E[slot]);
+    T* const F0 = uni(D.F[slot]);
+    T* const G0 = uni(D.G[slot]);
+    if (all_in) {
+      if (!CORR) {
+        stv(E0, oI, ve);
+        stv(F0, oI, vf);
+        stv(G0, oI, vg);
+      }
+      stv(wn, oG, vw);
+    } else if (row_in) {
+      // the domain's last cells end inside this vector
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) {
+        if (i0 + vc + k >= nx) break;
+        if (!CORR) {
+          stu(E0, oI + k, ve.v[k]);
+          stu(F0, oI + k, vf.v[k]);
+          stu(G0, oI + k, vg.v[k]);
+        }
+        stu(wn, oG + k, vw.v[k]);
+      }
+    }
   }
   __syncthreads();
 
@@ -1216,18 +1328,20 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   __syncthreads();
   // local solutions (cells outside the domain land in the fields' padding),
   // on the base P^n, Q^n
-  T* const xhP = uni(D.xhP);
-  T* const xhQ = uni(D.xhQ);
-  const T* const Pb = uni((const T*)D.P[slot]);
-  const T* const Qb = uni((const T*)D.Q[slot]);
+  {
+    V xp, xq, pb, qb;
+    if (CORR) {
+      pb = ldv<CPT>(uni((const T*)D.P[slot]), oG);
+      qb = ldv<CPT>(uni((const T*)D.Q[slot]), oG);
+    }
 #pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int r = rY0 + q;
-    const int C0 = (r + 2) * LW + cY + 2;
-    const unsigned ii = oI + (unsigned)(q * ipitch);
-    const unsigned og = oG + (unsigned)(q * pitch);
-    stu(xhP, ii, (CORR ? ldu(Pb, og) : sm.p[C0]) + sm.x.s.u[r * TXP + cY]);
-    stu(xhQ, ii, (CORR ? ldu(Qb, og) : sm.q[C0]) + sm.x.s.v[r * TXP + cY]);
+    for (int k = 0; k < CPT; ++k) {
+      const int C0 = (vr + 2) * LW + vc + k + 2;
+      xp.v[k] = (CORR ? pb.v[k] : sm.p[C0]) + sm.x.s.u[vr * TXP + vc + k];
+      xq.v[k] = (CORR ? qb.v[k] : sm.q[C0]) + sm.x.s.v[vr * TXP + vc + k];
+    }
+    stv(uni(D.xhP), oI, xp);
+    stv(uni(D.xhQ), oI, xq);
   }
 }
 
@@ -1521,9 +1635,11 @@ struct alignas(16) FinSmem {
   static constexpr int CXN = TX + 3, CYN = TY + 3;    // corners of cells i0-1 .. i0+TX, j0-1 .. j0+TY
   static constexpr int BX = TX + 2, BY = TY + 2;      // cells with one neighbour on each side
   static constexpr int TXP = TX + 1;
+  // corners are staged in pairs from corner i0 - 2 (one before the CXN used)
+  static constexpr int CP = CXN + 1;
   T db[BY * BX];                                      // cell still-water depth
   union {
-    T dc[CYN * CXN];                                  // corners (until db is formed)
+    T dc[CYN * CP];                                   // corners (until db is formed)
     struct {
       T cx[TY * TXP];                                 // x-line correction of P
       T cy[TY * TXP];                                 // y-line correction of Q
@@ -1541,8 +1657,10 @@ template <typename T, int TY, int MX, int MODE>
 __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                              int nd, int swizzle) {
   using S = FinSmem<T, TY, MX>;
-  constexpr int CXN = S::CXN, BX = S::BX, TXP = S::TXP;
+  constexpr int CP = S::CP, BX = S::BX, TXP = S::TXP;
   constexpr int CPT = (TX * TY) / NT;
+  using V = Vec<T, CPT>;
+  using V2 = Vec<T, 2>;
   __shared__ S sm;
   int dom, tile;
   // swizzle = 1: XCD-aware tile order, as in the stencil kernel (the corner
@@ -1562,56 +1680,64 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   T* const Q = uni(D.Q[ns]);
   const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
   const T g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
-  // cells of a thread: column cY, rows rY0 .. rY0+CPT-1 (as in the stencil kernel)
-  const int cY = tid % TX, rY0 = (tid / TX) * CPT;
-  const unsigned oI = (unsigned)((j0 + rY0) * ipitch + i0 + cY);
-  const unsigned oG = (unsigned)((j0 + rY0 + 2) * pitch + xoff + i0 + cY);
-  // all loads first: the neighbour-chunk end values of this thread's line
-  // solve (if it has one), the corners of the tile's cells and their
-  // neighbours (rows read in groups, no clamping: the fields are padded to
-  // whole tiles), the local solutions and the new surface
+  // cells of a thread: row vr, columns vc .. vc+CPT-1 (as in the stencil kernel)
+  constexpr int SPR = TX / CPT;
+  const int vr = tid / SPR, vc = (tid - vr * SPR) * CPT;
+  const unsigned oI = (unsigned)((j0 + vr) * ipitch + i0 + vc);
+  const unsigned oG = (unsigned)((j0 + vr + 2) * pitch + xoff + i0 + vc);
+  // All loads first, in the order they are needed (the waits are in issue
+  // order): the corners of the tile's cells and their neighbours (pairs of
+  // corners, rows read in groups, no clamping: the fields are padded to
+  // whole tiles), the neighbour-chunk end values of the line solves, the
+  // local solutions and the new surface.
+  const double dt = uni(st->dt);
   constexpr int NCX = TX / MX;
-  T xl = T(0), xr = T(0);
-  if (tid < TY * NCX) {
-    const int r = tid / NCX, qc = tid - r * NCX;
-    const int j = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
-    const size_t o = (size_t)(is / MX) * ny + j;
-    xl = D.ifx[o];
-    xr = D.ifx[(size_t)D.cx * ny + o];
-  } else if (tid >= 64 && tid < 64 + TX) {
-    const int i = min(i0 + tid - 64, nx - 1);
-    const size_t o = (size_t)(j0 / TY) * nx + i;
-    xl = D.ify[o];
-    xr = D.ify[(size_t)D.cy * nx + o];
-  }
-  constexpr int RGC = NT / CXN, KC = (S::CYN + RGC - 1) / RGC;
-  const int rC = min(tid / CXN, RGC - 1), cC = tid - (tid / CXN) * CXN;
+  constexpr int NPC = CP / 2, RGC = NT / NPC, KC = (S::CYN + RGC - 1) / RGC;
+  const int rC = min(tid / NPC, RGC - 1), cC = 2 * (tid - (tid / NPC) * NPC);
   auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
-  T rc[KC];
+  V2 rc[KC];
+  __builtin_amdgcn_sched_barrier(0);
   {
     const T* Dc = uni((const T*)D.Dc);
-    const unsigned oC = (unsigned)((j0 + 1) * cpitch + i0 + 1 + cC);   // corner (i0-1+cC, j0-1)
+    const unsigned oC = (unsigned)((j0 + 1) * cpitch + i0 + cC);   // corner (i0-2+cC, j0-1)
 #pragma unroll
-    for (int k = 0; k < KC; ++k) rc[k] = ldu(Dc, oC + (unsigned)(rowC(k) * cpitch));
+    for (int k = 0; k < KC; ++k) rc[k] = ldv<2>(Dc, oC + (unsigned)(rowC(k) * cpitch));
   }
-  T lp[CPT], lq[CPT], lw[CPT];
+  __builtin_amdgcn_sched_barrier(0);
+  // x solvers (tid < TY * NCX) and y solvers (64 <= tid < 64 + TX) use
+  // one of the two pairs; every thread loads both, at clamped indices
+  T xl, xr;
   {
-    const T* xhP = uni((const T*)D.xhP);
-    const T* xhQ = uni((const T*)D.xhQ);
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      lp[q] = ldu(xhP, oI + (unsigned)(q * ipitch));
-      lq[q] = ldu(xhQ, oI + (unsigned)(q * ipitch));
-      lw[q] = ldu((const T*)w, oG + (unsigned)(q * pitch));
-    }
+    const int r = min(tid / NCX, TY - 1), qc = tid - (tid / NCX) * NCX;
+    const int jx = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
+    const unsigned ox = (unsigned)((is / MX) * ny + jx);
+    const int iy = min(i0 + ((tid - 64) & (TX - 1)), nx - 1);
+    const unsigned oy = (unsigned)((j0 / TY) * nx + iy);
+    const T* ifx = uni((const T*)D.ifx);
+    const T* ify = uni((const T*)D.ify);
+    const unsigned cxn = (unsigned)(D.cx * ny), cyn = (unsigned)(D.cy * nx);
+    const T xlx = ldu(ifx, ox), xrx = ldu(ifx, cxn + ox);
+    const T xly = ldu(ify, oy), xry = ldu(ify, cyn + oy);
+    const bool xs = tid < TY * NCX;
+    xl = xs ? xlx : xly;
+    xr = xs ? xrx : xry;
   }
+  __builtin_amdgcn_sched_barrier(0);
+  const V lp = ldv<CPT>(uni((const T*)D.xhP), oI);
+  const V lq = ldv<CPT>(uni((const T*)D.xhQ), oI);
+  const V lw = ldv<CPT>((const T*)w, oG);
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int k = 0; k < KC; ++k) sm.u.dc[rowC(k) * CXN + cC] = rc[k];
+  for (int k = 0; k < KC; ++k) {
+    sm.u.dc[rowC(k) * CP + cC] = rc[k].v[0];
+    sm.u.dc[rowC(k) * CP + cC + 1] = rc[k].v[1];
+  }
   __syncthreads();
   for (int e = tid; e < S::BY * BX; e += NT) {
     const int r = e / BX, c = e - r * BX;
-    sm.db[e] = dbar4(sm.u.dc[r * CXN + c], sm.u.dc[r * CXN + c + 1], sm.u.dc[(r + 1) * CXN + c],
-                     sm.u.dc[(r + 1) * CXN + c + 1]);
+    // cell (i0 - 1 + c, j0 - 1 + r): corners c + 1, c + 2 of the staged rows
+    sm.db[e] = dbar4(sm.u.dc[r * CP + c + 1], sm.u.dc[r * CP + c + 2], sm.u.dc[(r + 1) * CP + c + 1],
+                     sm.u.dc[(r + 1) * CP + c + 2]);
   }
   __syncthreads();
   // Exact line solution = local solution + the response of the chunk system
@@ -1649,17 +1775,21 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   }
   __syncthreads();
   // new state, sponge, CFL speeds (Eq. 22) and ghost cells
-  const double dt = st->dt;
+  const int j = j0 + vr;
+  const bool row_in = j < ny;
+  const bool all_in = row_in && i0 + vc + CPT <= nx;
   T smax = T(0);
+  V vp, vq;
 #pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int r = rY0 + q, i = i0 + cY, j = j0 + r;
-    T p = lp[q] + sm.u.s.cx[r * TXP + cY];
-    T qv = lq[q] + sm.u.s.cy[r * TXP + cY];
-    T wv = lw[q];
-    const T Db = sm.db[(r + 1) * BX + cY + 1];
-    if (i >= nx || j >= ny) continue;
-    const unsigned og = oG + (unsigned)(q * pitch);
+  for (int k = 0; k < CPT; ++k) {
+    const int c = vc + k, i = i0 + c;
+    T p = lp.v[k] + sm.u.s.cx[vr * TXP + c];
+    T qv = lq.v[k] + sm.u.s.cy[vr * TXP + c];
+    T wv = lw.v[k];
+    const T Db = sm.db[(vr + 1) * BX + c + 1];
+    vp.v[k] = p;
+    vq.v[k] = qv;
+    if (i >= nx || !row_in) continue;
     if (D.any_sponge && !pred && Db > T(0)) {
       const T dist[4] = {(T(i) + T(0.5)) * D.dx, (T(nx - i) - T(0.5)) * D.dx, (T(j) + T(0.5)) * D.dy,
                          (T(ny - j) - T(0.5)) * D.dy};
@@ -1677,17 +1807,17 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
         wv *= fac;
         p *= fac;
         qv *= fac;
-        stu(w, og, wv);
+        vp.v[k] = p;
+        vq.v[k] = qv;
+        stu(w, oG + k, wv);
       }
     }
-    stu(P, og, p);
-    stu(Q, og, qv);
     const T h = fmax(wv + Db, T(0));
     if (D.runup && !pred && h > D.runup_delta) {
       // run-up record: highest surface over the inundated states (NaN until
       // the first one)
       const gp<T> wm = gbl(D.wmax);
-      const unsigned oi = oI + (unsigned)(q * ipitch);
+      const unsigned oi = oI + (unsigned)k;
       if (!(wm[oi] >= wv)) wm[oi] = wv;
     }
     const T vf = vfac(h, eps);
@@ -1698,6 +1828,17 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     const T sd = (sx != sx || sy != sy) ? T(INFINITY) : fmax(sx, sy);
     smax = fmax(smax, sd);
     if (i < 2 || i >= nx - 2 || j < 2 || j >= ny - 2) ghost_cell(D, w, P, Q, i, j, wv, p, qv, st->gw, st->gP);
+  }
+  if (all_in) {
+    stv(P, oG, vp);
+    stv(Q, oG, vq);
+  } else if (row_in) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (i0 + vc + k >= nx) break;
+      stu(P, oG + k, vp.v[k]);
+      stu(Q, oG + k, vq.v[k]);
+    }
   }
   // block max -> one word per tile (max commutes with the widening to FP64,
   // so the FP32 maximum converts to the same value); no atomics, so a large
