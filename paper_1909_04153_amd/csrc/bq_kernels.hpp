@@ -475,6 +475,100 @@ __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const
   else chunk_solve_db_<T, M, false>(Dl, ds, m, tc, fold_lo, fold_hi, rhs, rs);
 }
 
+// Chunk solve by a pair of lanes (partner = lane ^ 1; the low half is the
+// even lane): the chunk's m rows are split at m0 = (m + 1) / 2, each lane
+// solves its half with zero coupling and for the coupling column (the low
+// half's last row couples to x_{m0} through c_{m0-1}, the high half's first
+// row to x_{m0-1} through a_{m0}), the pair exchanges the two interface
+// values, solves the 2 x 2 interface system and each lane corrects its half
+// (the SPIKE construction of the line coupling, applied inside the chunk, so
+// each serial sweep is half as long).  Dl, ds, tc, fold_lo, fold_hi as in
+// chunk_solve_db; rhs(k) is the right-hand side of chunk row k.  On return
+// x[0 .. mh-1] holds the solution of chunk rows k0 .. k0+mh-1 and xlast
+// that of row k0+mh-1.  Both lanes of a pair must make the call.
+template <typename T, int H, bool FULL, typename RHS>
+__device__ __forceinline__ void pair_solve_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                            bool high, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
+  const int m0 = FULL ? H : (m + 1) >> 1;
+  k0 = high ? m0 : 0;
+  mh = FULL ? H : (high ? m - m0 : m0);
+  T cu[H], sp[H];                             // c_j / u_j; coupling response
+  T y_prev = T(0), s_prev = T(0), iu_prev = T(1), c_prev = T(0);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    if (FULL || j < mh) {
+      const int k = k0 + j;
+      T a, b, c;
+      tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+      if (k == 0 && fold_lo) b -= a;
+      if (k == m - 1 && fold_hi) b -= c;
+      const T r = rhs(k);
+      T u, y, sv;
+      if (j == 0) {
+        u = b;
+        y = r;
+        sv = high ? a : T(0);
+      } else {
+        const T l = a * iu_prev;
+        u = b - l * c_prev;
+        y = r - l * y_prev;
+        sv = -l * s_prev;
+      }
+      if (!high && j == mh - 1) sv += c;
+      const T iu = frcp(u);
+      cu[j] = c * iu;
+      x[j] = y * iu;
+      sp[j] = sv * iu;
+      y_prev = y;
+      s_prev = sv;
+      iu_prev = iu;
+      c_prev = c;
+    }
+  }
+  T xn = T(0), sn = T(0), ex = T(0), es = T(0);
+#pragma unroll
+  for (int j = H - 1; j >= 0; --j) {
+    if (FULL || j < mh) {
+      const bool last = j == mh - 1;
+      const T xv = last ? x[j] : x[j] - cu[j] * xn;
+      const T sv = last ? sp[j] : sp[j] - cu[j] * sn;
+      x[j] = xv;
+      sp[j] = sv;
+      xn = xv;
+      sn = sv;
+      if (!high && last) {
+        ex = xv;
+        es = sv;
+      }
+    }
+  }
+  if (high && (FULL || mh > 0)) {
+    ex = x[0];
+    es = sp[0];
+  }
+  const T px = __shfl_xor(ex, 1, 64), ps = __shfl_xor(es, 1, 64);
+  const T lx = high ? px : ex, lv = high ? ps : es;   // low half, row m0-1: x-hat, response
+  const T hx = high ? ex : px, hw = high ? es : ps;   // high half, row m0: x-hat, response
+  const T alpha = fdiv(lx - hx * lv, T(1) - hw * lv);  // x_{m0-1}
+  const T beta = hx - alpha * hw;                      // x_{m0}
+  const T f = high ? alpha : beta;
+  xlast = T(0);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    if (FULL || j < mh) {
+      x[j] -= f * sp[j];
+      if (j == mh - 1) xlast = x[j];
+    }
+  }
+}
+// full chunks (the common case) take the branch-free unrolled path
+template <typename T, int H, typename RHS>
+__device__ __forceinline__ void pair_solve(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                           bool high, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
+  if (m == 2 * H) pair_solve_<T, H, true>(Dl, ds, m, tc, fold_lo, fold_hi, high, rhs, x, k0, mh, xlast);
+  else pair_solve_<T, H, false>(Dl, ds, m, tc, fold_lo, fold_hi, high, rhs, x, k0, mh, xlast);
+}
+
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
 // own L2): block b runs on XCD b % 8.  Renumber so that every XCD walks a
 // contiguous run of tiles; a tile's halo rows and columns are then mostly
@@ -484,59 +578,6 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
   const int xcd = b % NXCD, local = b / NXCD;
   const int per = nb / NXCD, rem = nb % NXCD;
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
-}
-
-// Response of a chunk system to a right-hand side that is zero except r0 in
-// the first row and r1 in the last (the coupling to the neighbour chunks'
-// end values), for a kernel that must stay light on registers.  The forward
-// sweep keeps y_k / u_k and c_k / u_k in LDS (out, cu; stride rs), so the
-// backward sweep is one multiply-add per row: x_k = y_k/u_k - (c_k/u_k) x_{k+1}.
-// Each iteration issues the next row's LDS read before its own dependent
-// arithmetic, so the read latency overlaps the pivot recurrence.
-template <typename T>
-__device__ __forceinline__ void chunk_edge_solve(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
-                                                 T r0, T r1, T* out, T* cu, int rs) {
-  T d0 = dpos(Dl[0]), d1 = dpos(Dl[ds]), d2 = dpos(Dl[2 * ds]);
-  T r = m == 1 ? r0 + r1 : r0;
-  T y_prev = T(0), iu_prev = T(1), c_prev = T(0);
-  for (int k = 0; k < m; ++k) {
-    const T d3 = dpos(Dl[(k + 3 <= m + 1 ? k + 3 : m + 1) * ds]);
-    T a, b, c;
-    tri_coef(d0, d1, d2, tc, a, b, c);
-    if (k == 0 && fold_lo) b -= a;
-    if (k == m - 1 && fold_hi) b -= c;
-    T u, y;
-    if (k == 0) {
-      u = b;
-      y = r;
-    } else {
-      const T l = a * iu_prev;
-      u = b - l * c_prev;
-      y = r - l * y_prev;
-    }
-    const T iu = frcp(u);
-    out[k * rs] = y * iu;
-    cu[k * rs] = c * iu;
-    y_prev = y;
-    iu_prev = iu;
-    c_prev = c;
-    d0 = d1;
-    d1 = d2;
-    d2 = d3;
-    r = k + 2 == m ? r1 : T(0);
-  }
-  T x_next = out[(m - 1) * rs];
-  if (m < 2) return;
-  T yk = out[(m - 2) * rs], ck = cu[(m - 2) * rs];
-  for (int k = m - 2; k >= 0; --k) {
-    const int kn = k > 0 ? k - 1 : 0;
-    const T yn = out[kn * rs], cn = cu[kn * rs];
-    const T x = yk - ck * x_next;
-    out[k * rs] = x;
-    x_next = x;
-    yk = yn;
-    ck = cn;
-  }
 }
 
 // Work item (tile or line) of a launch -> (domain, index within it).  A
@@ -1286,43 +1327,60 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   __syncthreads();
 
   // ---- phase 3: chunk-local solves of Eq. (19) (x) and Eq. (20) (y) -------
+  // two lanes per chunk (pair_solve): the x-chunks in the first 2 TY NCX
+  // threads, the y-chunks (tile columns) in the last 2 TX
   constexpr int NCX = TX / MX;                  // x-chunks per tile row
   static_assert(TX % MX == 0, "chunks must tile the tile width");
-  static_assert(TY * NCX <= 64, "x-chunk solvers must fit one wave");
+  static_assert(2 * TY * NCX <= NT - 2 * TX, "x- and y-chunk solver pairs must fit the block");
   const bool wave_w = west_driven(D.bc[0]);
-  if (tid < TY * NCX) {
-    const int r = tid / NCX, qc = tid - r * NCX;
+  if (tid < 2 * TY * NCX) {
+    const int qq = tid >> 1;
+    const bool high = tid & 1;
+    const int r = qq / NCX, qc = qq - r * NCX;
     const int j = j0 + r, is = i0 + qc * MX;
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
       // depths of cells is-1 .. is+m (tile columns qc*MX+1 ..)
       const T* dlx = sm.db + (r + 2) * LW + qc * MX + 1;
       T* rhs = sm.x.s.u + r * TXP + qc * MX;
-      if (is == 0 && wave_w) {
+      if (is == 0 && wave_w && !high) {
         // Dirichlet ghost: the increment of P_{-1} from t_n to t_{n+1}
         T a, b, c;
         tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c);
         const T pg = CORR ? D.P[slot][(size_t)(j + 2) * pitch + xoff - 1] : sm.p[(r + 2) * LW + 1];
         rhs[0] -= a * ((T)st->gP[0] - pg);
       }
-      chunk_solve_db<T, MX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, rhs, 1);
+      T xs[MX / 2], xlast;
+      int k0, mh;
+      pair_solve<T, MX / 2>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, high,
+                            [&](int k) { return rhs[k]; }, xs, k0, mh, xlast);
+#pragma unroll
+      for (int u = 0; u < MX / 2; ++u)
+        if (u < mh) rhs[k0 + u] = xs[u];
       const int cgl = is / MX;
       const gp<T> chx = gbl(D.chx);
-      chx[(size_t)cgl * ny + j] = rhs[0];
-      chx[((size_t)D.cx + cgl) * ny + j] = rhs[m - 1];
+      if (!high) chx[(size_t)cgl * ny + j] = xs[0];
+      if (k0 + mh == m && mh > 0) chx[((size_t)D.cx + cgl) * ny + j] = xlast;
     }
-  } else if (tid >= 64 && tid < 64 + TX) {
-    const int c = tid - 64;
+  } else if (tid >= NT - 2 * TX) {
+    const int c = (tid - (NT - 2 * TX)) >> 1;
+    const bool high = tid & 1;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
       const T* dly = sm.db + LW + c + 2;        // depths of rows j0-1 .. j0+m
       T* rhs = sm.x.s.v + c;
-      chunk_solve_db<T, TY>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, rhs, TXP);
+      T xs[TY / 2], xlast;
+      int k0, mh;
+      pair_solve<T, TY / 2>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, high,
+                            [&](int k) { return rhs[k * TXP]; }, xs, k0, mh, xlast);
+#pragma unroll
+      for (int u = 0; u < TY / 2; ++u)
+        if (u < mh) rhs[(k0 + u) * TXP] = xs[u];
       const int cgl = j0 / TY;
       const gp<T> chy = gbl(D.chy);
-      chy[(size_t)cgl * nx + i] = rhs[0];
-      chy[((size_t)D.cy + cgl) * nx + i] = rhs[(m - 1) * TXP];
+      if (!high) chy[(size_t)cgl * nx + i] = xs[0];
+      if (k0 + mh == m && mh > 0) chy[((size_t)D.cy + cgl) * nx + i] = xlast;
     }
   }
   __syncthreads();
@@ -1643,8 +1701,6 @@ struct alignas(16) FinSmem {
     struct {
       T cx[TY * TXP];                                 // x-line correction of P
       T cy[TY * TXP];                                 // y-line correction of Q
-      T ux[TY * TXP];                                 // c_k / u_k of the x solves
-      T uy[TY * TXP];                                 // and of the y solves
     } s;
   } u;
 };
@@ -1704,23 +1760,26 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     for (int k = 0; k < KC; ++k) rc[k] = ldv<2>(Dc, oC + (unsigned)(rowC(k) * cpitch));
   }
   __builtin_amdgcn_sched_barrier(0);
-  // x solvers (tid < TY * NCX) and y solvers (64 <= tid < 64 + TX) use
-  // one of the two pairs; every thread loads both, at clamped indices
+  // lane pairs solve the chunk responses (pair_solve): x-chunks in the
+  // first 2 TY NCX threads, y-chunks (tile columns) in the last 2 TX; every
+  // thread loads the end values of both, at clamped indices, and uses one
+  static_assert(2 * TY * NCX <= NT - 2 * TX, "x- and y-chunk solver pairs must fit the block");
   T xl, xr;
   {
-    const int r = min(tid / NCX, TY - 1), qc = tid - (tid / NCX) * NCX;
+    const int qx = min(tid >> 1, TY * NCX - 1);
+    const int r = qx / NCX, qc = qx - r * NCX;
     const int jx = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
     const unsigned ox = (unsigned)((is / MX) * ny + jx);
-    const int iy = min(i0 + ((tid - 64) & (TX - 1)), nx - 1);
+    const int iy = min(i0 + ((tid >> 1) & (TX - 1)), nx - 1);
     const unsigned oy = (unsigned)((j0 / TY) * nx + iy);
     const T* ifx = uni((const T*)D.ifx);
     const T* ify = uni((const T*)D.ify);
     const unsigned cxn = (unsigned)(D.cx * ny), cyn = (unsigned)(D.cy * nx);
     const T xlx = ldu(ifx, ox), xrx = ldu(ifx, cxn + ox);
     const T xly = ldu(ify, oy), xry = ldu(ify, cyn + oy);
-    const bool xs = tid < TY * NCX;
-    xl = xs ? xlx : xly;
-    xr = xs ? xrx : xry;
+    const bool xsol = tid < 2 * TY * NCX;
+    xl = xsol ? xlx : xly;
+    xr = xsol ? xrx : xry;
   }
   __builtin_amdgcn_sched_barrier(0);
   const V lp = ldv<CPT>(uni((const T*)D.xhP), oI);
@@ -1746,8 +1805,10 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   // in the first row and -c x_right in the last.  The response is solved
   // here from the static matrix instead of read as stored spikes.
   const bool wave_w = west_driven(D.bc[0]);
-  if (tid < TY * NCX) {
-    const int r = tid / NCX, qc = tid - r * NCX;
+  if (tid < 2 * TY * NCX) {
+    const int qq = tid >> 1;
+    const bool high = tid & 1;
+    const int r = qq / NCX, qc = qq - r * NCX;
     const int j = j0 + r, is = i0 + qc * MX;
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
@@ -1756,11 +1817,20 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
       tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c0);
       const T r0 = -a * xl;
       tri_coef(dpos(dlx[m - 1]), dpos(dlx[m]), dpos(dlx[m + 1]), D.tcx, a, b, cm);
-      chunk_edge_solve<T>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, r0, -cm * xr,
-                          sm.u.s.cx + r * TXP + qc * MX, sm.u.s.ux + r * TXP + qc * MX, 1);
+      const T r1 = -cm * xr;
+      T xs[MX / 2], xlast;
+      int k0, mh;
+      pair_solve<T, MX / 2>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, high,
+                            [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
+                            xlast);
+      T* out = sm.u.s.cx + r * TXP + qc * MX + k0;
+#pragma unroll
+      for (int u = 0; u < MX / 2; ++u)
+        if (u < mh) out[u] = xs[u];
     }
-  } else if (tid >= 64 && tid < 64 + TX) {
-    const int c = tid - 64;
+  } else if (tid >= NT - 2 * TX) {
+    const int c = (tid - (NT - 2 * TX)) >> 1;
+    const bool high = tid & 1;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
@@ -1769,8 +1839,16 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
       tri_coef(dpos(dly[0]), dpos(dly[BX]), dpos(dly[2 * BX]), D.tcy, a, b, c0);
       const T r0 = -a * xl;
       tri_coef(dpos(dly[(m - 1) * BX]), dpos(dly[m * BX]), dpos(dly[(m + 1) * BX]), D.tcy, a, b, cm);
-      chunk_edge_solve<T>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, r0, -cm * xr, sm.u.s.cy + c, sm.u.s.uy + c,
-                          TXP);
+      const T r1 = -cm * xr;
+      T xs[TY / 2], xlast;
+      int k0, mh;
+      pair_solve<T, TY / 2>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, high,
+                            [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
+                            xlast);
+      T* out = sm.u.s.cy + k0 * TXP + c;
+#pragma unroll
+      for (int u = 0; u < TY / 2; ++u)
+        if (u < mh) out[u * TXP] = xs[u];
     }
   }
   __syncthreads();
