@@ -206,6 +206,29 @@ __device__ __forceinline__ void stv(T* base, unsigned off, const Vec<T, N>& v) {
   *(gp<R>)(b + (unsigned)(off * (unsigned)sizeof(T))) = x;
 }
 
+// The same with the non-temporal hint, for fields that a step reads or
+// writes once and that are not re-read before much other traffic (the
+// history rings, the local solutions, the new state): their lines are
+// evicted first, which keeps the halo rows that neighbouring tiles re-read
+// in L2.  Measured on the 64-domain batch: 0.547 -> 0.517 ms per step.
+template <int N, typename T>
+__device__ __forceinline__ Vec<T, N> ldv_nt(const T* base, unsigned off) {
+  using R = typename VecRaw<T, N>::t;
+  const gp<const char> b = (gp<const char>)(const char*)base;
+  const R x = __builtin_nontemporal_load((gp<const R>)(b + (unsigned)(off * (unsigned)sizeof(T))));
+  Vec<T, N> r;
+  __builtin_memcpy(&r, &x, sizeof r);
+  return r;
+}
+template <int N, typename T>
+__device__ __forceinline__ void stv_nt(T* base, unsigned off, const Vec<T, N>& v) {
+  using R = typename VecRaw<T, N>::t;
+  R x;
+  __builtin_memcpy(&x, &v, sizeof x);
+  const gp<char> b = (gp<char>)(char*)base;
+  __builtin_nontemporal_store(x, (gp<R>)(b + (unsigned)(off * (unsigned)sizeof(T))));
+}
+
 // Square root, reciprocal and cube root.  FP64 uses the correctly rounded
 // operations (parity with the FP64 oracle at 1e-12); FP32 uses the hardware
 // transcendental instructions (about 1 ulp), whose error is far below the
@@ -1014,14 +1037,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   // E, F, G history of this thread's cells, issued last: they are consumed
   // only in phase 2, so the waits before the first LDS stores do not cover
   // them and their latency overlaps the phases in between
-  const V e1 = ldv<CPT>(pE1, oI), e2 = ldv<CPT>(pE2, oI);
-  const V f1 = ldv<CPT>(pF1, oI), f2 = ldv<CPT>(pF2, oI);
-  const V g1 = ldv<CPT>(pG1, oI), g2 = ldv<CPT>(pG2, oI);
+  const V e1 = ldv_nt<CPT>(pE1, oI), e2 = ldv_nt<CPT>(pE2, oI);
+  const V f1 = ldv_nt<CPT>(pF1, oI), f2 = ldv_nt<CPT>(pF2, oI);
+  const V g1 = ldv_nt<CPT>(pG1, oI), g2 = ldv_nt<CPT>(pG2, oI);
   V e3, f3, g3;
   if (CORR) {
-    e3 = ldv<CPT>(pE3, oI);
-    f3 = ldv<CPT>(pF3, oI);
-    g3 = ldv<CPT>(pG3, oI);
+    e3 = ldv_nt<CPT>(pE3, oI);
+    f3 = ldv_nt<CPT>(pF3, oI);
+    g3 = ldv_nt<CPT>(pG3, oI);
   }
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1305,11 +1328,11 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     T* const G0 = uni(D.G[slot]);
     if (all_in) {
       if (!CORR) {
-        stv(E0, oI, ve);
-        stv(F0, oI, vf);
-        stv(G0, oI, vg);
+        stv_nt(E0, oI, ve);
+        stv_nt(F0, oI, vf);
+        stv_nt(G0, oI, vg);
       }
-      stv(wn, oG, vw);
+      stv_nt(wn, oG, vw);
     } else if (row_in) {
       // the domain's last cells end inside this vector
 #pragma unroll
@@ -1398,8 +1421,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       xp.v[k] = (CORR ? pb.v[k] : sm.p[C0]) + sm.x.s.u[vr * TXP + vc + k];
       xq.v[k] = (CORR ? qb.v[k] : sm.q[C0]) + sm.x.s.v[vr * TXP + vc + k];
     }
-    stv(uni(D.xhP), oI, xp);
-    stv(uni(D.xhQ), oI, xq);
+    stv_nt(uni(D.xhP), oI, xp);
+    stv_nt(uni(D.xhQ), oI, xq);
   }
 }
 
@@ -1782,9 +1805,9 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     xr = xsol ? xrx : xry;
   }
   __builtin_amdgcn_sched_barrier(0);
-  const V lp = ldv<CPT>(uni((const T*)D.xhP), oI);
-  const V lq = ldv<CPT>(uni((const T*)D.xhQ), oI);
-  const V lw = ldv<CPT>((const T*)w, oG);
+  const V lp = ldv_nt<CPT>(uni((const T*)D.xhP), oI);
+  const V lq = ldv_nt<CPT>(uni((const T*)D.xhQ), oI);
+  const V lw = ldv_nt<CPT>((const T*)w, oG);
   __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int k = 0; k < KC; ++k) {
@@ -1908,8 +1931,8 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     if (i < 2 || i >= nx - 2 || j < 2 || j >= ny - 2) ghost_cell(D, w, P, Q, i, j, wv, p, qv, st->gw, st->gP);
   }
   if (all_in) {
-    stv(P, oG, vp);
-    stv(Q, oG, vq);
+    stv_nt(P, oG, vp);
+    stv_nt(Q, oG, vq);
   } else if (row_in) {
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
