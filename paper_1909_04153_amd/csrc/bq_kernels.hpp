@@ -886,7 +886,8 @@ struct alignas(16) RhsSmem {
   // the CXN used; its row pitch is 9 mod 64 words for the face passes
   static constexpr int CP = CXN + 4;
   // the weighted P/Q history is kept on radius-1 rows in the columns of the
-  // radius-2 tile (its pairs load like the radius-2 rows)
+  // radius-2 tile (its pairs load like the radius-2 rows), row pitch 5 mod
+  // 64 words like LW (the F* reads of a thread's consecutive cells)
   static constexpr int PW = WX + 1;
   T w[WY * LW];
   T p[WY * LW];
