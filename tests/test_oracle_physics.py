@@ -97,8 +97,11 @@ def test_ms_dispersion_error_converges():
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
 
 
-def test_solitary_wave_on_flat_bed():
-    nx, dx, a, d, x0 = 1400, 0.1, 0.1, 1.0, 20.0
+def _crest_track(nx, dx, a, x0, dists):
+    """oracle run of the solitary wave on a flat bed (d = 1 m) in a channel of
+    nx x 4 cells; crest position and height (parabolic fit) each 50 steps
+    until the crest has travelled the largest of dists, and the crest
+    height when it passes each of them"""
     o = _dom(S.solitary_flat(nx=nx, ny=4, dx=dx, amp=a, x0=x0))
     X = (np.arange(nx) + 0.5) * dx
 
@@ -108,21 +111,46 @@ def test_solitary_wave_on_flat_bed():
         off = 0.5 * (y0 - y2) / (y0 - 2 * y1 + y2)
         return X[i] + off * dx, y1 - 0.25 * (y0 - y2) * off
 
-    ts, xs = [], []
-    while o.info().t < 20.0:
+    ts, xs, at = [], [], {}
+    todo = sorted(dists)
+    while todo:
         assert o.step(50) == 0
-        xc, _ = crest(o.read("eta")[1])
+        xc, hc = crest(o.read("eta")[1])
         ts.append(o.info().t)
         xs.append(xc)
-    ts, xs = np.array(ts), np.array(xs)
-    m = ts > 4.0
+        while todo and xc - x0 >= todo[0]:
+            at[todo.pop(0)] = hc
+    return np.array(ts), np.array(xs), at, o.read("eta")[1], X
+
+
+def test_solitary_wave_on_flat_bed():
+    # 200 m channel, crest carried 100 m (the solitary-wave case of the
+    # scope table); speed and trailing tail as there.  The crest settles
+    # about 3 % lower over the 100 m: the KdV sech^2 profile with P = c eta
+    # is not a solitary wave of the extended equations, and the drop is a
+    # property of the equations, not of the grid (next test), so the crest
+    # is held to the band that drop falls in rather than to 2 %.
+    nx, dx, a, d, x0 = 2000, 0.1, 0.1, 1.0, 20.0
+    ts, xs, at, e, X = _crest_track(nx, dx, a, x0, (100.0,))
     c = math.sqrt(G * (d + a))
+    m = ts > 4.0
     c_fit = np.polyfit(ts[m], xs[m], 1)[0]
-    e = o.read("eta")[1]
-    xc, hc = crest(e)
     assert abs(c_fit / c - 1.0) < 0.01
-    assert abs(hc / a - 1.0) < 0.03
-    assert np.max(np.abs(e[X < xc - 15.0])) < 0.03 * a
+    drop = 1.0 - at[100.0] / a
+    assert 0.02 < drop < 0.04, drop
+    assert np.max(np.abs(e[X < xs[-1] - 15.0])) < 0.03 * a
+
+
+def test_solitary_crest_drop_is_grid_converged():
+    # the crest drop of the test above on two grids: a scheme error (a
+    # dissipative flux, a wrong dispersive coefficient) would change with
+    # dx; the equations' own adjustment of the initial profile does not
+    a, x0 = 0.1, 20.0
+    _, _, c1, _, _ = _crest_track(800, 0.1, a, x0, (40.0,))
+    _, _, c2, _, _ = _crest_track(1600, 0.05, a, x0, (40.0,))
+    d1, d2 = 1.0 - c1[40.0] / a, 1.0 - c2[40.0] / a
+    assert 0.01 < d1 < 0.03, d1
+    assert abs(d1 - d2) < 1e-3, (d1, d2)
 
 
 def _run_prescribed(spec, dt, T):
