@@ -50,6 +50,10 @@ CASES = {
     "beach_ragged": lambda: S.sloping_beach(nx=133, ny=21, dx=0.1, x_toe=1.0, amp=0.05, ramp=1.0, t_end=0.0),
     # the corrector's second pass
     "pc_hump_2d": lambda: S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.25, fstar_order=2, corrector=1),
+    # a last chunk of one cell on both axes in every shape (161 = 10 x 16 + 1
+    # = 5 x 32 + 1, 17 = 16 + 1 = 2 x 8 + 1 = 4 x 4 + 1): the chunk solves'
+    # lane pairs then have an empty high half
+    "one_cell_chunks": lambda: S.sloping_beach(nx=161, ny=17, dx=0.1, x_toe=1.0, amp=0.05, ramp=1.0, t_end=0.0),
 }
 
 
@@ -86,7 +90,7 @@ def test_fp64_parity_in_every_tile_shape(bq, case, shape):
 
 @pytest.mark.parametrize("shape", FP32_SHAPES)
 def test_fp32_every_tile_shape_against_the_oracle(bq, shape):
-    for case in ("rip_2d", "beach_ragged", "pc_hump_2d"):
+    for case in ("rip_2d", "beach_ragged", "pc_hump_2d", "one_cell_chunks"):
         spec = CASES[case]()
         o = OracleDomain(spec["params"], spec["depth_c"])
         assert o.set_state(spec["eta"], spec["P"], spec["Q"]) == 0
