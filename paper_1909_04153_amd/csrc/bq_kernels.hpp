@@ -1530,9 +1530,54 @@ __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg,
   const size_t CL = (size_t)C * L;
   const int c0 = (int)(((long long)seg * C) / NS), c1 = (int)(((long long)(seg + 1) * C) / NS);
   const int n = active ? c1 - c0 : 0;
+  // A segment of at most NB chunks keeps its inputs in registers from one
+  // batch of loads per RB chunks to the end, so the four sweeps below read
+  // no memory after the first, as the per-chunk affine maps
+  // sigma_c = p0 + p1 alpha_{c-1}, alpha_c = pb + pa alpha_{c-1} and the
+  // backward coefficients t4, t5.  Longer segments load again in every
+  // sweep.  (The register file this takes lowers the kernel's occupancy,
+  // which the latency-bound launches of single domains do not feel.)
+  constexpr int NB = sizeof(T) == 4 ? 16 : 8;
+  const bool reg = n <= NB;
+  T p0[NB], p1[NB], pa[NB], pb[NB], t4[NB], t5[NB];
   // forward, pass 1: the segment's composite map alpha_out = A alpha_in + B
   T A = T(1), B = T(0);
-  for (int b0 = 0; b0 < n; b0 += RB) {
+  if (reg) {
+#pragma unroll
+    for (int b0 = 0; b0 < NB; b0 += RB) {
+      if (b0 < n) {
+        T r0[RB], r1[RB], r2[RB], r3[RB], r4[RB], r5[RB], xs[RB], xe[RB];
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          const size_t o = (size_t)(c0 + min(b0 + k, n - 1)) * L + line;
+          r0[k] = rs[o];
+          r1[k] = rs[CL + o];
+          r2[k] = rs[2 * CL + o];
+          r3[k] = rs[3 * CL + o];
+          r4[k] = rs[4 * CL + o];
+          r5[k] = rs[5 * CL + o];
+          xs[k] = ch[o];
+          xe[k] = ch[CL + o];
+        }
+#pragma unroll
+        for (int k = 0; k < RB; ++k) {
+          const int j = b0 + k;
+          const T q0 = r0[k] * xs[k];
+          p0[j] = q0;
+          p1[j] = r1[k];
+          pa[j] = r2[k] + r3[k] * r1[k];
+          pb[j] = xe[k] + r3[k] * q0;
+          t4[j] = r4[k];
+          t5[j] = r5[k];
+          if (j < n) {
+            A = pa[j] * A;
+            B = pa[j] * B + pb[j];
+          }
+        }
+      }
+    }
+  }
+  for (int b0 = 0; b0 < (reg ? 0 : n); b0 += RB) {
     T k1[RB], k2[RB], m1[RB], m2[RB], xs[RB], xe[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
@@ -1558,8 +1603,19 @@ __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg,
   T al = T(0);
   for (int k = 0; k < seg; ++k) al = xa[k][lane] * al + xb[k][lane];
   __syncthreads();
-  // forward, pass 2: sigma_c, alpha_c of the segment's chunks
-  for (int b0 = 0; b0 < n; b0 += RB) {
+  // forward, pass 2: sigma_c, alpha_c of the segment's chunks (in p0, p1
+  // on the register path)
+  if (reg) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      if (j < n) {
+        const T sg = p0[j] + p1[j] * al;
+        al = pb[j] + pa[j] * al;
+        p0[j] = sg;
+        p1[j] = al;
+      }
+  }
+  for (int b0 = 0; b0 < (reg ? 0 : n); b0 += RB) {
     T r0[RB], r1[RB], r2[RB], r3[RB], xs[RB], xe[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
@@ -1583,7 +1639,15 @@ __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg,
   }
   // backward, pass 1: X_s(c0) = R X_s(c1) + S over the segment
   T R = T(1), Sv = T(0);
-  for (int b1 = 0; b1 < n; b1 += RB) {
+  if (reg) {
+#pragma unroll
+    for (int j = NB - 1; j >= 0; --j)
+      if (j < n) {
+        R = t4[j] * R;
+        Sv = t4[j] * Sv + p0[j];
+      }
+  }
+  for (int b1 = 0; b1 < (reg ? 0 : n); b1 += RB) {
     T tau[RB], sg[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
@@ -1607,7 +1671,27 @@ __device__ __forceinline__ void reduce_line_seg(int C, int L, int line, int seg,
   // chunk is written after the barrier (that segment reads the slot first)
   T held = T(0);
   bool hold = false;
-  for (int b1 = 0; b1 < n; b1 += RB) {
+  if (reg) {
+#pragma unroll
+    for (int j = NB - 1; j >= 0; --j)
+      if (j < n) {
+        const int c = c0 + j;
+        const size_t o = (size_t)c * L + line;
+        const T Xs = p0[j] + t4[j] * xs_next;
+        const T Xe = p1[j] + t5[j] * xs_next;
+        itf[CL + o] = xs_next;                    // right neighbour of chunk c
+        if (c + 1 < C) {
+          if (c == c1 - 1) {
+            held = Xe;
+            hold = true;
+          } else {
+            itf[o + L] = Xe;                      // left neighbour of chunk c + 1
+          }
+        }
+        xs_next = Xs;
+      }
+  }
+  for (int b1 = 0; b1 < (reg ? 0 : n); b1 += RB) {
     T sg[RB], a[RB], r4[RB], r5[RB];
 #pragma unroll
     for (int k = 0; k < RB; ++k) {
