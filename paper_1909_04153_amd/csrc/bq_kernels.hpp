@@ -498,25 +498,36 @@ __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const
   else chunk_solve_db_<T, M, false>(Dl, ds, m, tc, fold_lo, fold_hi, rhs, rs);
 }
 
-// Chunk solve by a pair of lanes (partner = lane ^ 1; the low half is the
-// even lane): the chunk's m rows are split at m0 = (m + 1) / 2, each lane
-// solves its half with zero coupling and for the coupling column (the low
-// half's last row couples to x_{m0} through c_{m0-1}, the high half's first
-// row to x_{m0-1} through a_{m0}), the pair exchanges the two interface
-// values, solves the 2 x 2 interface system and each lane corrects its half
-// (the SPIKE construction of the line coupling, applied inside the chunk, so
-// each serial sweep is half as long).  Dl, ds, tc, fold_lo, fold_hi as in
-// chunk_solve_db; rhs(k) is the right-hand side of chunk row k.  On return
-// x[0 .. mh-1] holds the solution of chunk rows k0 .. k0+mh-1 and xlast
-// that of row k0+mh-1.  Both lanes of a pair must make the call.
-template <typename T, int H, bool FULL, typename RHS>
-__device__ __forceinline__ void pair_solve_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
-                                            bool high, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
-  const int m0 = FULL ? H : (m + 1) >> 1;
-  k0 = high ? m0 : 0;
-  mh = FULL ? H : (high ? m - m0 : m0);
-  T cu[H], sp[H];                             // c_j / u_j; coupling response
-  T y_prev = T(0), s_prev = T(0), iu_prev = T(1), c_prev = T(0);
+// Chunk solve by a group of P lanes (P = 2 or 4 consecutive lanes; lane
+// part = lane % P takes the part-th of P consecutive parts of the chunk's m
+// rows, of (m + P - 1 - part) / P rows each, so that only trailing parts
+// are empty).  Each lane eliminates its part with zero coupling to the
+// other parts, for the right-hand side and for its two coupling columns:
+// its last row couples to the next part's first unknown through c (response
+// v), its first row to the previous part's last unknown through a (response
+// w).  The group exchanges the parts' end values by lane shuffles, every
+// lane solves the small system of the interface unknowns (L_i = x at part
+// i's last row, R_i = x at part i+1's first row), and each lane corrects its
+// part: x = x-hat - R_part v - L_{part-1} w.  This is the SPIKE construction
+// of the line coupling applied inside the chunk: each serial sweep is 1/P as
+// long.  Dl, ds, tc, fold_lo, fold_hi as in chunk_solve_db; rhs(k) is the
+// right-hand side of chunk row k.  On return x[0 .. mh-1] holds the solution
+// of chunk rows k0 .. k0+mh-1 and xlast that of row k0+mh-1.  Every lane of
+// a group must make the call.
+template <typename T, int H, int P, bool FULL, typename RHS>
+__device__ __forceinline__ void group_solve_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                             int part, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
+  static_assert(P == 2 || P == 4, "groups of two or four lanes");
+  constexpr int N = 2 * (P - 1);              // interface unknowns L_0, R_0, L_1, R_1, ...
+  auto size = [&](int q) { return FULL ? H : (m + P - 1 - q) / P; };
+  k0 = 0;
+#pragma unroll
+  for (int q = 0; q < P - 1; ++q)
+    if (q < part) k0 += size(q);
+  mh = size(part);
+  const int np = min(P, m);                   // parts that hold rows
+  T cu[H], wv[H], vv[H];                      // c_j / u_j; responses to the left / right couplings
+  T y_prev = T(0), s_prev = T(0), iu_prev = T(1), c_prev = T(0), vy = T(0);
 #pragma unroll
   for (int j = 0; j < H; ++j) {
     if (FULL || j < mh) {
@@ -526,70 +537,132 @@ __device__ __forceinline__ void pair_solve_(const T* Dl, int ds, int m, const T*
       if (k == 0 && fold_lo) b -= a;
       if (k == m - 1 && fold_hi) b -= c;
       const T r = rhs(k);
-      T u, y, sv;
+      T u, y, sw;
       if (j == 0) {
         u = b;
         y = r;
-        sv = high ? a : T(0);
+        sw = part > 0 ? a : T(0);
       } else {
         const T l = a * iu_prev;
         u = b - l * c_prev;
         y = r - l * y_prev;
-        sv = -l * s_prev;
+        sw = -l * s_prev;
       }
-      if (!high && j == mh - 1) sv += c;
       const T iu = frcp(u);
       cu[j] = c * iu;
       x[j] = y * iu;
-      sp[j] = sv * iu;
+      wv[j] = sw * iu;
+      // the right coupling enters in the last row only (no elimination
+      // reaches it before)
+      if (j == mh - 1) vy = (part < np - 1 ? c : T(0)) * iu;
       y_prev = y;
-      s_prev = sv;
+      s_prev = sw;
       iu_prev = iu;
       c_prev = c;
     }
   }
-  T xn = T(0), sn = T(0), ex = T(0), es = T(0);
+  // backward sweeps; end values of the part (first and last row)
+  T xn = T(0), wn = T(0), vn = T(0);
+  T xL = T(0), wL = T(0), vL = T(0);
 #pragma unroll
   for (int j = H - 1; j >= 0; --j) {
     if (FULL || j < mh) {
       const bool last = j == mh - 1;
       const T xv = last ? x[j] : x[j] - cu[j] * xn;
-      const T sv = last ? sp[j] : sp[j] - cu[j] * sn;
+      const T wvv = last ? wv[j] : wv[j] - cu[j] * wn;
+      const T vvv = last ? vy : -cu[j] * vn;
       x[j] = xv;
-      sp[j] = sv;
+      wv[j] = wvv;
+      vv[j] = vvv;
       xn = xv;
-      sn = sv;
-      if (!high && last) {
-        ex = xv;
-        es = sv;
+      wn = wvv;
+      vn = vvv;
+      if (last) {
+        xL = xv;
+        wL = wvv;
+        vL = vvv;
       }
     }
   }
-  if (high && (FULL || mh > 0)) {
-    ex = x[0];
-    es = sp[0];
+  const bool any = FULL || mh > 0;
+  const T xF = any ? x[0] : T(0), wF = any ? wv[0] : T(0), vF = any ? vv[0] : T(0);
+  // every part's end values, from the lanes of the group
+  const int base = (int)(threadIdx.x & 63) & ~(P - 1);
+  T gxL[P], gwL[P], gvL[P], gxF[P], gwF[P], gvF[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    gxL[q] = __shfl(xL, base + q, 64);
+    gwL[q] = __shfl(wL, base + q, 64);
+    gvL[q] = __shfl(vL, base + q, 64);
+    gxF[q] = __shfl(xF, base + q, 64);
+    gwF[q] = __shfl(wF, base + q, 64);
+    gvF[q] = __shfl(vF, base + q, 64);
   }
-  const T px = __shfl_xor(ex, 1, 64), ps = __shfl_xor(es, 1, 64);
-  const T lx = high ? px : ex, lv = high ? ps : es;   // low half, row m0-1: x-hat, response
-  const T hx = high ? ex : px, hw = high ? es : ps;   // high half, row m0: x-hat, response
-  const T alpha = fdiv(lx - hx * lv, T(1) - hw * lv);  // x_{m0-1}
-  const T beta = hx - alpha * hw;                      // x_{m0}
-  const T f = high ? alpha : beta;
+  // interface system M z = r, z = (L_0, R_0, L_1, R_1, ...); an interface
+  // past the last part with rows has L = R = 0
+  T M[N][N], rv[N];
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    rv[e] = T(0);
+#pragma unroll
+    for (int f = 0; f < N; ++f) M[e][f] = e == f ? T(1) : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < P - 1; ++i) {
+    if (i < np - 1) {
+      // L_i + v_i(last) R_i + w_i(last) L_{i-1} = x-hat_i(last)
+      M[2 * i][2 * i + 1] = gvL[i];
+      if (i > 0) M[2 * i][2 * i - 2] = gwL[i];
+      rv[2 * i] = gxL[i];
+      // R_i + w_{i+1}(first) L_i + v_{i+1}(first) R_{i+1} = x-hat_{i+1}(first)
+      M[2 * i + 1][2 * i] = gwF[i + 1];
+      if (i + 1 < P - 1) M[2 * i + 1][2 * i + 3] = gvF[i + 1];
+      rv[2 * i + 1] = gxF[i + 1];
+    }
+  }
+  // Gaussian elimination (the matrix is the identity plus coupling
+  // responses below one in size: no pivoting)
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    const T id = fdiv(T(1), M[e][e]);
+#pragma unroll
+    for (int f = e + 1; f < N; ++f) {
+      const T l = M[f][e] * id;
+#pragma unroll
+      for (int g = e; g < N; ++g) M[f][g] -= l * M[e][g];
+      rv[f] -= l * rv[e];
+    }
+  }
+  T z[N];
+#pragma unroll
+  for (int e = N - 1; e >= 0; --e) {
+    T t = rv[e];
+#pragma unroll
+    for (int f = e + 1; f < N; ++f) t -= M[e][f] * z[f];
+    z[e] = fdiv(t, M[e][e]);
+  }
+  T Rp = T(0), Lm = T(0);                      // R_part, L_{part-1}
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+    if (q == part) {
+      if (q < P - 1) Rp = z[2 * q + 1];
+      if (q > 0) Lm = z[2 * q - 2];
+    }
   xlast = T(0);
 #pragma unroll
   for (int j = 0; j < H; ++j) {
     if (FULL || j < mh) {
-      x[j] -= f * sp[j];
+      x[j] -= Rp * vv[j] + Lm * wv[j];
       if (j == mh - 1) xlast = x[j];
     }
   }
 }
 // full chunks (the common case) take the branch-free unrolled path
-template <typename T, int H, typename RHS>
-__device__ __forceinline__ void pair_solve(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
-                                           bool high, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
-  if (m == 2 * H) pair_solve_<T, H, true>(Dl, ds, m, tc, fold_lo, fold_hi, high, rhs, x, k0, mh, xlast);
-  else pair_solve_<T, H, false>(Dl, ds, m, tc, fold_lo, fold_hi, high, rhs, x, k0, mh, xlast);
+template <typename T, int H, int P, typename RHS>
+__device__ __forceinline__ void group_solve(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                            int part, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
+  if (m == P * H) group_solve_<T, H, P, true>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
+  else group_solve_<T, H, P, false>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
 }
 
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
@@ -1351,15 +1424,16 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   __syncthreads();
 
   // ---- phase 3: chunk-local solves of Eq. (19) (x) and Eq. (20) (y) -------
-  // two lanes per chunk (pair_solve): the x-chunks in the first 2 TY NCX
-  // threads, the y-chunks (tile columns) in the last 2 TX
+  // lane groups per chunk (group_solve; parts of 8 rows along x, two
+  // halves along y): the x-chunks in the first PX TY NCX threads, the
+  // y-chunks (tile columns) in the last 2 TX
   constexpr int NCX = TX / MX;                  // x-chunks per tile row
+  constexpr int PX = MX / 8;                    // lanes per x-chunk
   static_assert(TX % MX == 0, "chunks must tile the tile width");
-  static_assert(2 * TY * NCX <= NT - 2 * TX, "x- and y-chunk solver pairs must fit the block");
+  static_assert(PX * TY * NCX <= NT - 2 * TX, "x- and y-chunk solver groups must fit the block");
   const bool wave_w = west_driven(D.bc[0]);
-  if (tid < 2 * TY * NCX) {
-    const int qq = tid >> 1;
-    const bool high = tid & 1;
+  if (tid < PX * TY * NCX) {
+    const int qq = tid / PX, part = tid - qq * PX;
     const int r = qq / NCX, qc = qq - r * NCX;
     const int j = j0 + r, is = i0 + qc * MX;
     if (j < ny && is < nx) {
@@ -1367,28 +1441,28 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       // depths of cells is-1 .. is+m (tile columns qc*MX+1 ..)
       const T* dlx = sm.db + (r + 2) * LW + qc * MX + 1;
       T* rhs = sm.x.s.u + r * TXP + qc * MX;
-      if (is == 0 && wave_w && !high) {
+      if (is == 0 && wave_w && part == 0) {
         // Dirichlet ghost: the increment of P_{-1} from t_n to t_{n+1}
         T a, b, c;
         tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c);
         const T pg = CORR ? D.P[slot][(size_t)(j + 2) * pitch + xoff - 1] : sm.p[(r + 2) * LW + 1];
         rhs[0] -= a * ((T)st->gP[0] - pg);
       }
-      T xs[MX / 2], xlast;
+      T xs[8], xlast;
       int k0, mh;
-      pair_solve<T, MX / 2>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, high,
+      group_solve<T, 8, PX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, part,
                             [&](int k) { return rhs[k]; }, xs, k0, mh, xlast);
 #pragma unroll
-      for (int u = 0; u < MX / 2; ++u)
+      for (int u = 0; u < 8; ++u)
         if (u < mh) rhs[k0 + u] = xs[u];
       const int cgl = is / MX;
       const gp<T> chx = gbl(D.chx);
-      if (!high) chx[(size_t)cgl * ny + j] = xs[0];
+      if (part == 0) chx[(size_t)cgl * ny + j] = xs[0];
       if (k0 + mh == m && mh > 0) chx[((size_t)D.cx + cgl) * ny + j] = xlast;
     }
   } else if (tid >= NT - 2 * TX) {
     const int c = (tid - (NT - 2 * TX)) >> 1;
-    const bool high = tid & 1;
+    const int part = tid & 1;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
@@ -1396,14 +1470,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       T* rhs = sm.x.s.v + c;
       T xs[TY / 2], xlast;
       int k0, mh;
-      pair_solve<T, TY / 2>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, high,
-                            [&](int k) { return rhs[k * TXP]; }, xs, k0, mh, xlast);
+      group_solve<T, TY / 2, 2>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, part,
+                                [&](int k) { return rhs[k * TXP]; }, xs, k0, mh, xlast);
 #pragma unroll
       for (int u = 0; u < TY / 2; ++u)
         if (u < mh) rhs[(k0 + u) * TXP] = xs[u];
       const int cgl = j0 / TY;
       const gp<T> chy = gbl(D.chy);
-      if (!high) chy[(size_t)cgl * nx + i] = xs[0];
+      if (part == 0) chy[(size_t)cgl * nx + i] = xs[0];
       if (k0 + mh == m && mh > 0) chy[((size_t)D.cy + cgl) * nx + i] = xlast;
     }
   }
@@ -1868,13 +1942,15 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     for (int k = 0; k < KC; ++k) rc[k] = ldv<2>(Dc, oC + (unsigned)(rowC(k) * cpitch));
   }
   __builtin_amdgcn_sched_barrier(0);
-  // lane pairs solve the chunk responses (pair_solve): x-chunks in the
-  // first 2 TY NCX threads, y-chunks (tile columns) in the last 2 TX; every
-  // thread loads the end values of both, at clamped indices, and uses one
-  static_assert(2 * TY * NCX <= NT - 2 * TX, "x- and y-chunk solver pairs must fit the block");
+  // lane groups solve the chunk responses (group_solve; parts of 8 rows
+  // along x, two halves along y): x-chunks in the first PX TY NCX threads,
+  // y-chunks (tile columns) in the last 2 TX; every thread loads the end
+  // values of both, at clamped indices, and uses one
+  constexpr int PX = MX / 8;
+  static_assert(PX * TY * NCX <= NT - 2 * TX, "x- and y-chunk solver groups must fit the block");
   T xl, xr;
   {
-    const int qx = min(tid >> 1, TY * NCX - 1);
+    const int qx = min(tid / PX, TY * NCX - 1);
     const int r = qx / NCX, qc = qx - r * NCX;
     const int jx = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
     const unsigned ox = (unsigned)((is / MX) * ny + jx);
@@ -1885,7 +1961,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     const unsigned cxn = (unsigned)(D.cx * ny), cyn = (unsigned)(D.cy * nx);
     const T xlx = ldu(ifx, ox), xrx = ldu(ifx, cxn + ox);
     const T xly = ldu(ify, oy), xry = ldu(ify, cyn + oy);
-    const bool xsol = tid < 2 * TY * NCX;
+    const bool xsol = tid < PX * TY * NCX;
     xl = xsol ? xlx : xly;
     xr = xsol ? xrx : xry;
   }
@@ -1913,9 +1989,8 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   // in the first row and -c x_right in the last.  The response is solved
   // here from the static matrix instead of read as stored spikes.
   const bool wave_w = west_driven(D.bc[0]);
-  if (tid < 2 * TY * NCX) {
-    const int qq = tid >> 1;
-    const bool high = tid & 1;
+  if (tid < PX * TY * NCX) {
+    const int qq = tid / PX, part = tid - qq * PX;
     const int r = qq / NCX, qc = qq - r * NCX;
     const int j = j0 + r, is = i0 + qc * MX;
     if (j < ny && is < nx) {
@@ -1926,19 +2001,19 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
       const T r0 = -a * xl;
       tri_coef(dpos(dlx[m - 1]), dpos(dlx[m]), dpos(dlx[m + 1]), D.tcx, a, b, cm);
       const T r1 = -cm * xr;
-      T xs[MX / 2], xlast;
+      T xs[8], xlast;
       int k0, mh;
-      pair_solve<T, MX / 2>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, high,
+      group_solve<T, 8, PX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, part,
                             [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
                             xlast);
       T* out = sm.u.s.cx + r * TXP + qc * MX + k0;
 #pragma unroll
-      for (int u = 0; u < MX / 2; ++u)
+      for (int u = 0; u < 8; ++u)
         if (u < mh) out[u] = xs[u];
     }
   } else if (tid >= NT - 2 * TX) {
     const int c = (tid - (NT - 2 * TX)) >> 1;
-    const bool high = tid & 1;
+    const int part = tid & 1;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
@@ -1950,7 +2025,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
       const T r1 = -cm * xr;
       T xs[TY / 2], xlast;
       int k0, mh;
-      pair_solve<T, TY / 2>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, high,
+      group_solve<T, TY / 2, 2>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, part,
                             [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
                             xlast);
       T* out = sm.u.s.cy + k0 * TXP + c;
