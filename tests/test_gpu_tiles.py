@@ -52,7 +52,7 @@ CASES = {
     "pc_hump_2d": lambda: S.closed_basin_hump(nx=70, ny=45, dx=0.1, cfl=0.25, fstar_order=2, corrector=1),
     # a last chunk of one cell on both axes in every shape (161 = 10 x 16 + 1
     # = 5 x 32 + 1, 17 = 16 + 1 = 2 x 8 + 1 = 4 x 4 + 1): the chunk solves'
-    # lane pairs then have an empty high half
+    # lane groups then have empty parts
     "one_cell_chunks": lambda: S.sloping_beach(nx=161, ny=17, dx=0.1, x_toe=1.0, amp=0.05, ramp=1.0, t_end=0.0),
 }
 
