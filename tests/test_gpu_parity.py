@@ -401,17 +401,24 @@ def test_two_lane_batch_profile_and_graphs_match_one_lane(bq):
                 assert np.array_equal(a, c)
 
 
-def test_full_size_batch64_as_benched(bq):
+@pytest.mark.parametrize("shape", [(16, 16), (16, 32)])
+def test_full_size_batch64_as_benched(bq, shape):
     """The benchmark's 64-domain FP32 batch (21.3 M cells) at full size, in
-    the schedule the autotuner picks for it (3 lanes, 16-step graph replays,
-    64-thread line coupling): every member equals its solo run bit for bit,
-    and the smallest solitary-wave and beach members match the FP64 oracle."""
+    the schedules the autotuner picks for it (2 lanes, 16-step graph
+    replays, 4-segment line coupling, tiles of 16 x 16 or 16 x 32 cells):
+    every member equals its solo run (a batch of one in the same tile shape
+    and line coupling) bit for bit, and the smallest solitary-wave and beach
+    members match the FP64 oracle."""
     specs = S.batch_mix(64, seed=190904154)
     steps = 32
-    print("batch64: %d cells" % sum(s["params"]["nx"] * s["params"]["ny"] for s in specs), flush=True)
+    tune = dict(lanes=2, graph_steps=16, reduce_block=256, reduce_segments=4, swizzle=1, tile_y=shape[0],
+                chunk_x=shape[1])
+    print("batch64: %d cells, tile %s" % (sum(s["params"]["nx"] * s["params"]["ny"] for s in specs), shape),
+          flush=True)
     doms = [bq.domain_from_spec(s, precision=bq.FP32) for s in specs]
-    b = bq.Batch(doms, lanes=3)
-    b.set_tune(dict(lanes=3, graph_steps=16, reduce_block=64, reduce_segments=1, swizzle=1))
+    b = bq.Batch(doms, lanes=2)
+    b.set_tune(tune)
+    assert (b.tune["tile_y"], b.tune["chunk_x"]) == shape
     b.step(steps)
     b.sync()
     batched = []
@@ -424,10 +431,14 @@ def test_full_size_batch64_as_benched(bq):
         d.close()
     for k, s in enumerate(specs):
         g = bq.domain_from_spec(s, precision=bq.FP32)
-        g.step(steps)
+        solo = bq.Batch([g], lanes=1)
+        solo.set_tune(dict(tune, lanes=1, graph_steps=0))
+        solo.step(steps)
+        solo.sync()
         assert g.sync().status == 0
         for f, r in zip(FIELDS, batched[k]):
             assert np.array_equal(g.read(f), r), (s["name"], f)
+        solo.close()
         g.close()
     def cells(k):
         return specs[k]["params"]["nx"] * specs[k]["params"]["ny"]
