@@ -83,6 +83,11 @@ def load(path: str | None = None):
     p = path or os.environ.get("BQ_LIBRARY", LIB_PATH)
     if not os.path.exists(p):
         raise RuntimeError(f"libbq.so not built ({p}); run __graft_entry__.build()")
+    # torch ships its own HIP runtime with the same soname as ROCm's; loading
+    # torch first makes libbq bind to that one copy, so the library and the
+    # workspaces torch allocates share one runtime (two copies in one process
+    # see no device in the second)
+    import torch  # noqa: F401
     L = ctypes.CDLL(p)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32
     L.bq_abi_version.restype = ctypes.c_int

@@ -18,7 +18,7 @@ usable criterion in run-up cases: the kinetic term (P^2 + Q^2) / 2h of thin
 films at the wet/dry front grows without any instability.
 
     python -m paper_1909_04153_amd.robustness [--nx 601] [--t-end 20] [--fp64]
-        [--scenario conical|shelf] [--corrector] [--cfl C]
+        [--scenario conical|shelf|rip] [--corrector] [--cfl C]
 """
 from __future__ import annotations
 
@@ -131,8 +131,10 @@ def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0
     """The fixed-versus-adaptive comparison on the conical-island basin (Sec.
     5.1) at nx x nx cells over the same 30 m, or (scenario "shelf") on the
     breaking solitary wave over a shelf with an island (Sec. 5.2) at
-    nx x nx/5 cells over the same 40 m x 8 m; optionally with the
-    Adams-Moulton corrector and another CFL target."""
+    nx x nx/5 cells over the same 40 m x 8 m, or (scenario "rip") on the rip
+    beach under irregular (JONSWAP) waves from rest (Sec. 5.4) at nx x nx
+    cells over 1024 m; optionally with the Adams-Moulton corrector and
+    another CFL target."""
     kw = {}
     if corrector:
         kw.update(corrector=1, fstar_order=2)
@@ -140,6 +142,10 @@ def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0
         kw.update(cfl=float(cfl))
     if scenario == "shelf":
         spec = S.shelf_breaking(nx=nx, ny=nx // 5, dx=40.0 / nx, **kw)
+    elif scenario == "rip":
+        kw.setdefault("cfl", 0.125)
+        kw.setdefault("fstar_order", 1)
+        spec = S.rip_beach_scaled(nx, nx, **kw)
     else:
         dx = 30.0 / (nx - 1) if nx != 601 else 0.05
         spec = S.conical_island(nx=nx, ny=nx, dx=dx, **kw)
@@ -149,8 +155,8 @@ def study(nx=601, t_end=20.0, precision=bq.FP32, snapshots=(4.0, 7.0, 10.0, 14.0
     if log:
         log(f"adaptive: {'stable' if ad['stable'] else 'unstable'} after {ad['steps']} steps to t = {ad['t']:.3f}")
     dts = np.array([dt for _, dt in ad["trace"][1:]])
-    rec = ad["domain"].read("runup")
-    radii = runup_radii(spec, rec)
+    # run-up around an island (the rip beach has none)
+    radii = runup_radii(spec, ad["domain"].read("runup")) if "center" in spec else None
     ad["domain"].close()
     lo, hi = 0.1 * float(dts.min()), 4.0 * float(dts.max())
     t0 = time.perf_counter()
@@ -183,7 +189,7 @@ def main():
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--corrector", action="store_true", help="AB3 predictor + Adams-Moulton corrector")
     ap.add_argument("--cfl", type=float, default=None, help="CFL target of the adaptive run")
-    ap.add_argument("--scenario", choices=("conical", "shelf"), default="conical")
+    ap.add_argument("--scenario", choices=("conical", "shelf", "rip"), default="conical")
     ap.add_argument("--snapshots", default="4,7,10,14", help="times of the local CFL maps, comma separated")
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
