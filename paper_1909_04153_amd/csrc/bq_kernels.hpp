@@ -514,7 +514,7 @@ __device__ __forceinline__ void chunk_solve_db(const T* Dl, int ds, int m, const
 // right-hand side of chunk row k.  On return x[0 .. mh-1] holds the solution
 // of chunk rows k0 .. k0+mh-1 and xlast that of row k0+mh-1.  Every lane of
 // a group must make the call.
-template <typename T, int H, int P, bool FULL, typename RHS>
+template <typename T, int H, int P, bool FULL, bool POS, typename RHS>
 __device__ __forceinline__ void group_solve_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
                                              int part, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
   static_assert(P == 2 || P == 4, "groups of two or four lanes");
@@ -526,6 +526,9 @@ __device__ __forceinline__ void group_solve_(const T* Dl, int ds, int m, const T
     if (q < part) k0 += size(q);
   mh = size(part);
   const int np = min(P, m);                   // parts that hold rows
+  // the chunk's first row is this part's first when part == 0, its last row
+  // this part's last when part == np - 1
+  const bool lo = fold_lo && part == 0, hi = fold_hi && part == np - 1;
   T cu[H], wv[H], vv[H];                      // c_j / u_j; responses to the left / right couplings
   T y_prev = T(0), s_prev = T(0), iu_prev = T(1), c_prev = T(0), vy = T(0);
 #pragma unroll
@@ -533,9 +536,10 @@ __device__ __forceinline__ void group_solve_(const T* Dl, int ds, int m, const T
     if (FULL || j < mh) {
       const int k = k0 + j;
       T a, b, c;
-      tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
-      if (k == 0 && fold_lo) b -= a;
-      if (k == m - 1 && fold_hi) b -= c;
+      if (POS) tri_coef(Dl[k * ds], Dl[(k + 1) * ds], Dl[(k + 2) * ds], tc, a, b, c);
+      else tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+      if (j == 0 && lo) b -= a;
+      if (j == mh - 1 && hi) b -= c;
       const T r = rhs(k);
       T u, y, sw;
       if (j == 0) {
@@ -657,12 +661,13 @@ __device__ __forceinline__ void group_solve_(const T* Dl, int ds, int m, const T
     }
   }
 }
-// full chunks (the common case) take the branch-free unrolled path
-template <typename T, int H, int P, typename RHS>
+// full chunks (the common case) take the branch-free unrolled path.  POS:
+// the depths Dl are already max(D, 0).
+template <typename T, int H, int P, bool POS = false, typename RHS>
 __device__ __forceinline__ void group_solve(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
                                             int part, RHS rhs, T (&x)[H], int& k0, int& mh, T& xlast) {
-  if (m == P * H) group_solve_<T, H, P, true>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
-  else group_solve_<T, H, P, false>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
+  if (m == P * H) group_solve_<T, H, P, true, POS>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
+  else group_solve_<T, H, P, false, POS>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
 }
 
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
@@ -1335,6 +1340,23 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       hG[k] += fsG[k];
     }
   }
+  // eta = w + min(D, 0) over the radius-2 tile, formed once per cell for the
+  // dispersive stencils below (in the staging's cell mapping) into the
+  // corner tile's words, which nothing reads after the face passes; the
+  // depth tile keeps d = max(D, 0) from here on (h = w + D = eta + d)
+  T* const eta = sm.dc;
+  static_assert(S::CYN * S::CP >= S::WY * LW, "the eta tile fits in the corner tile");
+#pragma unroll
+  for (int k = 0; k < KW; ++k) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int e = rowW(k) * LW + cP + u;
+      const T De = sm.db[e];
+      eta[e] = sm.w[e] + dneg(De);
+      sm.db[e] = dpos(De);
+    }
+  }
+  __syncthreads();
   V ve, vf, vg, vw;
   V wb;
   if (CORR) wb = ldv<CPT>(wbase, oG);
@@ -1347,15 +1369,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     T e_ = acc_e[k] + sm.x.ay[0][o];
     T f_ = acc_f[k] + sm.x.ay[1][o];
     T g_ = acc_g[k] + sm.x.ay[2][o];
-    const T Db = sm.db[C0];
-    const T d0 = dpos(Db);
-    const T dxm = dpos(sm.db[C0 - 1]), dxp = dpos(sm.db[C0 + 1]);
-    const T dym = dpos(sm.db[C0 - LW]), dyp = dpos(sm.db[C0 + LW]);
+    const T d0 = sm.db[C0];
+    const T dxm = sm.db[C0 - 1], dxp = sm.db[C0 + 1];
+    const T dym = sm.db[C0 - LW], dyp = sm.db[C0 + LW];
     const T ddx = (dxp - dxm) * i2dx, ddy = (dyp - dym) * i2dy;
     // dispersive terms of Eq. (12)-(13): eta = h - d = w + min(D, 0); they
     // vanish with d0 on land
     {
-#define ETA(o) (sm.w[C0 + (o)] + dneg(sm.db[C0 + (o)]))
+#define ETA(o) eta[C0 + (o)]
       const T e00 = ETA(0);
       const T exm = ETA(-1), exp_ = ETA(1), eym = ETA(-LW), eyp = ETA(LW);
       const T emm = ETA(-LW - 1), epm = ETA(-LW + 1), emp = ETA(LW - 1), epp = ETA(LW + 1);
@@ -1376,7 +1397,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     // plus the quadratic law f u |U|
     const T Pc = sm.p[C0], Qc = sm.q[C0];
     if (gn2 > T(0) || cf > T(0)) {
-      const T h = fmax(sm.w[C0] + Db, T(0));
+      const T h = fmax(eta[C0] + d0, T(0));
       const T vfc = vfac(h, eps);
       const T u = Pc * vfc, v = Qc * vfc;
       const T kf = h > T(0) ? (gn2 * frcbrt(h) + cf) * fsqrt(u * u + v * v) : T(0);
@@ -1444,14 +1465,14 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       if (is == 0 && wave_w && part == 0) {
         // Dirichlet ghost: the increment of P_{-1} from t_n to t_{n+1}
         T a, b, c;
-        tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c);
+        tri_coef(dlx[0], dlx[1], dlx[2], D.tcx, a, b, c);
         const T pg = CORR ? D.P[slot][(size_t)(j + 2) * pitch + xoff - 1] : sm.p[(r + 2) * LW + 1];
         rhs[0] -= a * ((T)st->gP[0] - pg);
       }
       T xs[8], xlast;
       int k0, mh;
-      group_solve<T, 8, PX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, part,
-                            [&](int k) { return rhs[k]; }, xs, k0, mh, xlast);
+      group_solve<T, 8, PX, true>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, part,
+                                  [&](int k) { return rhs[k]; }, xs, k0, mh, xlast);
 #pragma unroll
       for (int u = 0; u < 8; ++u)
         if (u < mh) rhs[k0 + u] = xs[u];
@@ -1470,8 +1491,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       T* rhs = sm.x.s.v + c;
       T xs[TY / 2], xlast;
       int k0, mh;
-      group_solve<T, TY / 2, 2>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, part,
-                                [&](int k) { return rhs[k * TXP]; }, xs, k0, mh, xlast);
+      group_solve<T, TY / 2, 2, true>(dly, LW, m, D.tcy, j0 == 0, j0 + m == ny, part,
+                                      [&](int k) { return rhs[k * TXP]; }, xs, k0, mh, xlast);
 #pragma unroll
       for (int u = 0; u < TY / 2; ++u)
         if (u < mh) rhs[(k0 + u) * TXP] = xs[u];
