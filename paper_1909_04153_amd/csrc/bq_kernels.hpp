@@ -670,6 +670,56 @@ __device__ __forceinline__ void group_solve(const T* Dl, int ds, int m, const T*
   else group_solve_<T, H, P, false, POS>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
 }
 
+// Lane layouts of the per-cell phases and the chunk solves.  LDS serves a
+// wave in two halves of 32 lanes over 32 banks of 4 bytes, so a half-wave's
+// 32 words are conflict-free when they fall in distinct banks mod 32.  The
+// tile buffers have odd row pitches (5 or 1 mod 32 words), which the
+// layouts below rely on; FP64 keeps the plain row-major layouts.
+//
+// Cells of thread t: CPT consecutive columns vc .. vc+CPT-1 of row vr.  In
+// FP32 each half-wave takes CPT rows of 32 columns (32/CPT lanes per row),
+// so its CPT-strided words cover every bank once.
+template <typename T, int CPT>
+__device__ __forceinline__ void cell_of(int t, int& vr, int& vc) {
+  if (sizeof(T) == 4 && CPT > 1) {
+    constexpr int LS = 32 / CPT;                   // lanes per 32-column row segment
+    const int w = t >> 6, half = (t >> 5) & 1, h = t & 31;
+    vr = CPT * w + h / LS;
+    vc = 32 * half + CPT * (h % LS);
+  } else {
+    constexpr int SPR = TX / CPT;
+    vr = t / SPR;
+    vc = (t - vr * SPR) * CPT;
+  }
+}
+// Row r and chunk qc of x-chunk lane group qq (PX lanes, parts of 8
+// columns): in FP32 each half-wave's 32 / PX groups take 8 rows of 4 / PX
+// chunks, so the parts' first columns (8 apart) fall in distinct banks.
+template <typename T, int TY, int NCX, int PX>
+__device__ __forceinline__ void xchunk_of(int qq, int& r, int& qc) {
+  if (sizeof(T) == 4 && TY % 8 == 0 && (32 / PX) % 8 == 0) {
+    constexpr int HC = 32 / PX, QH = HC / 8, RB = TY / 8;
+    const int hw = qq / HC, i = qq - hw * HC;
+    r = 8 * (hw % RB) + (i & 7);
+    qc = QH * (hw / RB) + (i >> 3);
+  } else {
+    r = qq / NCX;
+    qc = qq - r * NCX;
+  }
+}
+// Tile column of y-chunk lane pair g (parts of TY / 2 rows): in FP32 with
+// 16-row tiles each half-wave's 16 pairs take two runs of 8 columns 16
+// apart, so the two parts (8 rows apart: 8 mod 32 words) fall in distinct
+// banks.
+template <typename T, int TY>
+__device__ __forceinline__ int ycol_of(int g) {
+  if (sizeof(T) == 4 && TY == 16) {
+    const int hw = g >> 4, i = g & 15;
+    return 32 * (hw >> 1) + 8 * (hw & 1) + 16 * (i >> 3) + (i & 7);
+  }
+  return g;
+}
+
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
 // own L2): block b runs on XCD b % 8.  Renumber so that every XCD walks a
 // contiguous run of tiles; a tile's halo rows and columns are then mostly
@@ -1026,9 +1076,9 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   // Cells of a thread in the per-cell phases: row vr, columns vc .. vc+CPT-1
   // (consecutive columns: one vector access per field, and the x-face pass
   // below takes the same cells, so its results stay in registers).
-  constexpr int SPR = TX / CPT;
-  static_assert(SPR * TY == NT, "one row segment per thread");
-  const int vr = tid / SPR, vc = (tid - vr * SPR) * CPT;
+  static_assert((TX / CPT) * TY == NT, "one row segment per thread");
+  int vr, vc;
+  cell_of<T, CPT>(tid, vr, vc);
   const unsigned oI = (unsigned)((j0 + vr) * ipitch + i0 + vc);          // interior fields
   const unsigned oG = (unsigned)((j0 + vr + 2) * pitch + xoff + i0 + vc);  // ghosted fields
 
@@ -1348,12 +1398,17 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   static_assert(S::CYN * S::CP >= S::WY * LW, "the eta tile fits in the corner tile");
 #pragma unroll
   for (int k = 0; k < KW; ++k) {
+    // every cell by one thread only: the staging's repeated rows (threads
+    // past the last whole row, rows past the tile) would read a depth that
+    // another wave has already clamped
+    if (tid < NP * RGP && rP + RGP * k < S::WY) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int e = rowW(k) * LW + cP + u;
-      const T De = sm.db[e];
-      eta[e] = sm.w[e] + dneg(De);
-      sm.db[e] = dpos(De);
+      for (int u = 0; u < 2; ++u) {
+        const int e = (rP + RGP * k) * LW + cP + u;
+        const T De = sm.db[e];
+        eta[e] = sm.w[e] + dneg(De);
+        sm.db[e] = dpos(De);
+      }
     }
   }
   __syncthreads();
@@ -1455,7 +1510,8 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
   const bool wave_w = west_driven(D.bc[0]);
   if (tid < PX * TY * NCX) {
     const int qq = tid / PX, part = tid - qq * PX;
-    const int r = qq / NCX, qc = qq - r * NCX;
+    int r, qc;
+    xchunk_of<T, TY, NCX, PX>(qq, r, qc);
     const int j = j0 + r, is = i0 + qc * MX;
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
@@ -1482,7 +1538,7 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
       if (k0 + mh == m && mh > 0) chx[((size_t)D.cx + cgl) * ny + j] = xlast;
     }
   } else if (tid >= NT - 2 * TX) {
-    const int c = (tid - (NT - 2 * TX)) >> 1;
+    const int c = ycol_of<T, TY>((tid - (NT - 2 * TX)) >> 1);
     const int part = tid & 1;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
@@ -1895,10 +1951,11 @@ template <typename T, int TY, int MX>
 struct alignas(16) FinSmem {
   static constexpr int CXN = TX + 3, CYN = TY + 3;    // corners of cells i0-1 .. i0+TX, j0-1 .. j0+TY
   static constexpr int BX = TX + 2, BY = TY + 2;      // cells with one neighbour on each side
+  static constexpr int BXP = BX + 3;                  // their row pitch: 5 mod 32 words
   static constexpr int TXP = TX + 1;
   // corners are staged in pairs from corner i0 - 2 (one before the CXN used)
   static constexpr int CP = CXN + 1;
-  T db[BY * BX];                                      // cell still-water depth
+  T db[BY * BXP];                                     // cell still-water depth
   union {
     T dc[CYN * CP];                                   // corners (until db is formed)
     struct {
@@ -1916,7 +1973,7 @@ template <typename T, int TY, int MX, int MODE>
 __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms, const int* __restrict__ tile_map,
                                              int nd, int swizzle) {
   using S = FinSmem<T, TY, MX>;
-  constexpr int CP = S::CP, BX = S::BX, TXP = S::TXP;
+  constexpr int CP = S::CP, BX = S::BX, BXP = S::BXP, TXP = S::TXP;
   constexpr int CPT = (TX * TY) / NT;
   using V = Vec<T, CPT>;
   using V2 = Vec<T, 2>;
@@ -1940,8 +1997,8 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   const int pitch = uni(D.pitch), xoff = uni(D.xoff), ipitch = uni(D.ipitch), cpitch = uni(D.cpitch);
   const T g = D.g, eps = D.eps, idx = D.idx, idy = D.idy;
   // cells of a thread: row vr, columns vc .. vc+CPT-1 (as in the stencil kernel)
-  constexpr int SPR = TX / CPT;
-  const int vr = tid / SPR, vc = (tid - vr * SPR) * CPT;
+  int vr, vc;
+  cell_of<T, CPT>(tid, vr, vc);
   const unsigned oI = (unsigned)((j0 + vr) * ipitch + i0 + vc);
   const unsigned oG = (unsigned)((j0 + vr + 2) * pitch + xoff + i0 + vc);
   // All loads first, in the order they are needed (the waits are in issue
@@ -1972,10 +2029,11 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   T xl, xr;
   {
     const int qx = min(tid / PX, TY * NCX - 1);
-    const int r = qx / NCX, qc = qx - r * NCX;
+    int r, qc;
+    xchunk_of<T, TY, NCX, PX>(qx, r, qc);
     const int jx = min(j0 + r, ny - 1), is = min(i0 + qc * MX, nx - 1);
     const unsigned ox = (unsigned)((is / MX) * ny + jx);
-    const int iy = min(i0 + ((tid >> 1) & (TX - 1)), nx - 1);
+    const int iy = min(i0 + ycol_of<T, TY>((tid >> 1) & (TX - 1)), nx - 1);
     const unsigned oy = (unsigned)((j0 / TY) * nx + iy);
     const T* ifx = uni((const T*)D.ifx);
     const T* ify = uni((const T*)D.ify);
@@ -2000,7 +2058,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   for (int e = tid; e < S::BY * BX; e += NT) {
     const int r = e / BX, c = e - r * BX;
     // cell (i0 - 1 + c, j0 - 1 + r): corners c + 1, c + 2 of the staged rows
-    sm.db[e] = dbar4(sm.u.dc[r * CP + c + 1], sm.u.dc[r * CP + c + 2], sm.u.dc[(r + 1) * CP + c + 1],
+    sm.db[r * BXP + c] = dbar4(sm.u.dc[r * CP + c + 1], sm.u.dc[r * CP + c + 2], sm.u.dc[(r + 1) * CP + c + 1],
                      sm.u.dc[(r + 1) * CP + c + 2]);
   }
   __syncthreads();
@@ -2012,11 +2070,12 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   const bool wave_w = west_driven(D.bc[0]);
   if (tid < PX * TY * NCX) {
     const int qq = tid / PX, part = tid - qq * PX;
-    const int r = qq / NCX, qc = qq - r * NCX;
+    int r, qc;
+    xchunk_of<T, TY, NCX, PX>(qq, r, qc);
     const int j = j0 + r, is = i0 + qc * MX;
     if (j < ny && is < nx) {
       const int m = min(MX, nx - is);
-      const T* dlx = sm.db + (r + 1) * BX + qc * MX;   // cells is-1 .. is+m
+      const T* dlx = sm.db + (r + 1) * BXP + qc * MX;  // cells is-1 .. is+m
       T a, b, c0, cm;
       tri_coef(dpos(dlx[0]), dpos(dlx[1]), dpos(dlx[2]), D.tcx, a, b, c0);
       const T r0 = -a * xl;
@@ -2033,20 +2092,20 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
         if (u < mh) out[u] = xs[u];
     }
   } else if (tid >= NT - 2 * TX) {
-    const int c = (tid - (NT - 2 * TX)) >> 1;
+    const int c = ycol_of<T, TY>((tid - (NT - 2 * TX)) >> 1);
     const int part = tid & 1;
     const int i = i0 + c;
     if (i < nx && j0 < ny) {
       const int m = min(TY, ny - j0);
       const T* dly = sm.db + c + 1;                    // rows j0-1 .. j0+m
       T a, b, c0, cm;
-      tri_coef(dpos(dly[0]), dpos(dly[BX]), dpos(dly[2 * BX]), D.tcy, a, b, c0);
+      tri_coef(dpos(dly[0]), dpos(dly[BXP]), dpos(dly[2 * BXP]), D.tcy, a, b, c0);
       const T r0 = -a * xl;
-      tri_coef(dpos(dly[(m - 1) * BX]), dpos(dly[m * BX]), dpos(dly[(m + 1) * BX]), D.tcy, a, b, cm);
+      tri_coef(dpos(dly[(m - 1) * BXP]), dpos(dly[m * BXP]), dpos(dly[(m + 1) * BXP]), D.tcy, a, b, cm);
       const T r1 = -cm * xr;
       T xs[TY / 2], xlast;
       int k0, mh;
-      group_solve<T, TY / 2, 2>(dly, BX, m, D.tcy, j0 == 0, j0 + m == ny, part,
+      group_solve<T, TY / 2, 2>(dly, BXP, m, D.tcy, j0 == 0, j0 + m == ny, part,
                             [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
                             xlast);
       T* out = sm.u.s.cy + k0 * TXP + c;
@@ -2068,7 +2127,7 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
     T p = lp.v[k] + sm.u.s.cx[vr * TXP + c];
     T qv = lq.v[k] + sm.u.s.cy[vr * TXP + c];
     T wv = lw.v[k];
-    const T Db = sm.db[(vr + 1) * BX + c + 1];
+    const T Db = sm.db[(vr + 1) * BXP + c + 1];
     vp.v[k] = p;
     vq.v[k] = qv;
     if (i >= nx || !row_in) continue;
