@@ -1006,16 +1006,17 @@ struct alignas(16) RhsSmem {
   static constexpr int BX = TX + 2, BY = TY + 2;      // radius-1 tiles
   static constexpr int CXN = TX + 5, CYN = TY + 5;    // corners
   static constexpr int TXP = TX + 1;                  // padded row of the solve buffers
-  // LDS row pitch of the radius-2 tiles: 5 mod 64 words, so the x-segment
-  // threads (stride 4 within a row, 4 rows per wave) hit 64 distinct banks
+  // LDS row pitch of the radius-2 tiles: 5 mod 32 words, so that the lane
+  // layouts of the per-cell phases (cell_of: CPT-strided columns of CPT rows
+  // per half-wave) and of the chunk solves hit 32 distinct banks
   static constexpr int LW = WX + 1;
   static constexpr int AXP = TX + 1;                  // row pitch of ay (same reason)
   // the corner tile is staged in pairs from corner i0 - 2, one corner past
-  // the CXN used; its row pitch is 9 mod 64 words for the face passes
+  // the CXN used; its row pitch is 9 mod 32 words for the face passes
   static constexpr int CP = CXN + 4;
   // the weighted P/Q history is kept on radius-1 rows in the columns of the
   // radius-2 tile (its pairs load like the radius-2 rows), row pitch 5 mod
-  // 64 words like LW (the F* reads of a thread's consecutive cells)
+  // 32 words like LW (the F* reads of a thread's consecutive cells)
   static constexpr int PW = WX + 1;
   T w[WY * LW];
   T p[WY * LW];
