@@ -41,7 +41,8 @@ WORDS_STEP = 24
 # reading) is kept with the profile summaries, tagged with a hash of the
 # kernel sources it was taken on; it is reported only while they match
 PROFILE_SUMMARIES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ("paper_1909_04153_amd/csrc/bq_kernels.hpp", "paper_1909_04153_amd/csrc/bq_lib.hip")
+KERNEL_SOURCES = ("paper_1909_04153_amd/csrc/bq_kernels.hpp", "paper_1909_04153_amd/csrc/bq_layout.hpp",
+                  "paper_1909_04153_amd/csrc/bq_lib.hip")
 
 
 def kernel_source_hash():

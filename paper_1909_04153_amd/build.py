@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbq.so")
 SOURCES = [os.path.join(CSRC, "bq_lib.hip")]
-HEADERS = [os.path.join(CSRC, "bq_kernels.hpp"), os.path.join(ROOT, "include", "bq.h")]
+HEADERS = [os.path.join(CSRC, "bq_kernels.hpp"), os.path.join(CSRC, "bq_layout.hpp"), os.path.join(ROOT, "include", "bq.h")]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "bq_layout.hpp"
+
 namespace bqk {
 
 enum { WALL = 0, SINE = 1, SPONGE = 2, IRREGULAR = 3, TIMESERIES = 4 };
@@ -35,8 +37,6 @@ enum { WALL = 0, SINE = 1, SPONGE = 2, IRREGULAR = 3, TIMESERIES = 4 };
 __host__ __device__ inline bool west_driven(int bc) { return bc == SINE || bc == IRREGULAR || bc == TIMESERIES; }
 enum { ST_OK = 0, ST_ENONFINITE = -4, ST_EDTMIN = -5, ST_EDONE = -7 };
 
-constexpr int TX = 64;      // tile width (cells)
-constexpr int NT = 256;     // threads per tile block
 constexpr int NDIAG = 256;  // blocks of the diagnostic sums
 
 struct alignas(64) DevState {
@@ -670,56 +670,6 @@ __device__ __forceinline__ void group_solve(const T* Dl, int ds, int m, const T*
   else group_solve_<T, H, P, false, POS>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
 }
 
-// Lane layouts of the per-cell phases and the chunk solves.  LDS serves a
-// wave in two halves of 32 lanes over 32 banks of 4 bytes, so a half-wave's
-// 32 words are conflict-free when they fall in distinct banks mod 32.  The
-// tile buffers have odd row pitches (5 or 1 mod 32 words), which the
-// layouts below rely on; FP64 keeps the plain row-major layouts.
-//
-// Cells of thread t: CPT consecutive columns vc .. vc+CPT-1 of row vr.  In
-// FP32 each half-wave takes CPT rows of 32 columns (32/CPT lanes per row),
-// so its CPT-strided words cover every bank once.
-template <typename T, int CPT>
-__device__ __forceinline__ void cell_of(int t, int& vr, int& vc) {
-  if (sizeof(T) == 4 && CPT > 1) {
-    constexpr int LS = 32 / CPT;                   // lanes per 32-column row segment
-    const int w = t >> 6, half = (t >> 5) & 1, h = t & 31;
-    vr = CPT * w + h / LS;
-    vc = 32 * half + CPT * (h % LS);
-  } else {
-    constexpr int SPR = TX / CPT;
-    vr = t / SPR;
-    vc = (t - vr * SPR) * CPT;
-  }
-}
-// Row r and chunk qc of x-chunk lane group qq (PX lanes, parts of 8
-// columns): in FP32 each half-wave's 32 / PX groups take 8 rows of 4 / PX
-// chunks, so the parts' first columns (8 apart) fall in distinct banks.
-template <typename T, int TY, int NCX, int PX>
-__device__ __forceinline__ void xchunk_of(int qq, int& r, int& qc) {
-  if (sizeof(T) == 4 && TY % 8 == 0 && (32 / PX) % 8 == 0) {
-    constexpr int HC = 32 / PX, QH = HC / 8, RB = TY / 8;
-    const int hw = qq / HC, i = qq - hw * HC;
-    r = 8 * (hw % RB) + (i & 7);
-    qc = QH * (hw / RB) + (i >> 3);
-  } else {
-    r = qq / NCX;
-    qc = qq - r * NCX;
-  }
-}
-// Tile column of y-chunk lane pair g (parts of TY / 2 rows): in FP32 with
-// 16-row tiles each half-wave's 16 pairs take two runs of 8 columns 16
-// apart, so the two parts (8 rows apart: 8 mod 32 words) fall in distinct
-// banks.
-template <typename T, int TY>
-__device__ __forceinline__ int ycol_of(int g) {
-  if (sizeof(T) == 4 && TY == 16) {
-    const int hw = g >> 4, i = g & 15;
-    return 32 * (hw >> 1) + 8 * (hw & 1) + 16 * (i >> 3) + (i & 7);
-  }
-  return g;
-}
-
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
 // own L2): block b runs on XCD b % 8.  Renumber so that every XCD walks a
 // contiguous run of tiles; a tile's halo rows and columns are then mostly
@@ -1018,6 +968,9 @@ struct alignas(16) RhsSmem {
   // radius-2 tile (its pairs load like the radius-2 rows), row pitch 5 mod
   // 32 words like LW (the F* reads of a thread's consecutive cells)
   static constexpr int PW = WX + 1;
+  static_assert(LW % 32 == PITCH_MOD_TILE && PW % 32 == PITCH_MOD_TILE && AXP % 32 == PITCH_MOD_ROWS &&
+                    TXP % 32 == PITCH_MOD_ROWS && CP % 32 == PITCH_MOD_CORNERS,
+                "the lane layouts assume these row pitches");
   T w[WY * LW];
   T p[WY * LW];
   T q[WY * LW];
@@ -1954,6 +1907,7 @@ struct alignas(16) FinSmem {
   static constexpr int BX = TX + 2, BY = TY + 2;      // cells with one neighbour on each side
   static constexpr int BXP = BX + 3;                  // their row pitch: 5 mod 32 words
   static constexpr int TXP = TX + 1;
+  static_assert(BXP % 32 == PITCH_MOD_TILE && TXP % 32 == PITCH_MOD_ROWS, "the lane layouts assume these row pitches");
   // corners are staged in pairs from corner i0 - 2 (one before the CXN used)
   static constexpr int CP = CXN + 1;
   T db[BY * BXP];                                     // cell still-water depth
