@@ -767,7 +767,6 @@ __device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP
     return;
   }
   // incident wave train: sum of the components
-  __shared__ double red[4][64];
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   const int nw = D.n_waves;
   for (int m = tid; tid < 64 && m < nw; m += 64) {
@@ -779,18 +778,18 @@ __device__ void west_ghosts(const DomDev<T>& D, double t, double* gw, double* gP
     a2 += s2;
     a3 += om / k * s2;
   }
+  // the first wave sums its lanes' partial sums by a butterfly (lanes past
+  // the component count hold zeros)
   if (tid < 64) {
-    red[0][tid] = a0; red[1][tid] = a1; red[2][tid] = a2; red[3][tid] = a3;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    // lanes past the component count hold zeros: summing them would change
-    // nothing but the time
-    double s[4] = {0, 0, 0, 0};
-    const int nq = nw < 64 ? nw : 64;
-    for (int q = 0; q < nq; ++q)
-      for (int c = 0; c < 4; ++c) s[c] += red[c][q];
-    gw[0] = s[0]; gP[0] = s[1]; gw[1] = s[2]; gP[1] = s[3];
+    for (int o = 32; o > 0; o >>= 1) {
+      a0 += __shfl_xor(a0, o, 64);
+      a1 += __shfl_xor(a1, o, 64);
+      a2 += __shfl_xor(a2, o, 64);
+      a3 += __shfl_xor(a3, o, 64);
+    }
+    if (tid == 0) {
+      gw[0] = a0; gP[0] = a1; gw[1] = a2; gP[1] = a3;
+    }
   }
   __syncthreads();
 }
