@@ -1037,21 +1037,20 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
 
   // ---- phase 0: issue every load of the tile before the first LDS store ----
   // The halo tiles are read in pairs of cells (8 or 16 bytes per lane): a
-  // radius-2 row is NP pairs from cell i0 - 2, a corner row NPC pairs from
-  // corner i0 - 2; thread (r0, c) loads rows r0 + RG k, so the LDS index is
-  // a per-thread base plus a constant.  The threads beyond RG whole rows and
-  // the rows past the tile in the last round repeat a row of the tile (same
-  // values to the same LDS words), so every round is branch-free.  The
-  // workspace pads every field to whole tiles plus the halo, so no index is
-  // clamped to the domain: values outside it only reach cells outside it.
-  constexpr int NP = WX / 2, RGP = NT / NP;
-  constexpr int KW = (S::WY + RGP - 1) / RGP, KB = (S::BY + RGP - 1) / RGP;
-  constexpr int NPC = (CXN + 1) / 2, RGC = NT / NPC, KC = (S::CYN + RGC - 1) / RGC;
-  const int rP = min(tid / NP, RGP - 1), cP = 2 * (tid - (tid / NP) * NP);
-  const int rC = min(tid / NPC, RGC - 1), cC = 2 * (tid - (tid / NPC) * NPC);
-  auto rowW = [&](int k) { return k < KW - 1 ? rP + RGP * k : min(rP + RGP * k, S::WY - 1); };
-  auto rowB = [&](int k) { return k < KB - 1 ? rP + RGP * k : min(rP + RGP * k, S::BY - 1); };
-  auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
+  // radius-2 row is WX / 2 pairs from cell i0 - 2, a corner row (CXN + 1) / 2
+  // pairs from corner i0 - 2, each staged by PairStaging (thread (r0, c)
+  // loads rows r0 + RG k, so the LDS index is a per-thread base plus a
+  // constant; repeated rows keep every round branch-free).  The workspace
+  // pads every field to whole tiles plus the halo, so no index is clamped to
+  // the domain: values outside it only reach cells outside it.
+  using SW = PairStaging<WX / 2, S::WY>;            // radius-2 rows
+  using SB = PairStaging<WX / 2, S::BY>;            // radius-1 rows, radius-2 columns
+  using SC = PairStaging<(CXN + 1) / 2, S::CYN>;    // corner rows
+  constexpr int KW = SW::K, KB = SB::K, KC = SC::K;
+  const int cP = SW::col(tid), cC = SC::col(tid);
+  auto rowW = [&](int k) { return SW::row(tid, k); };
+  auto rowB = [&](int k) { return SB::row(tid, k); };
+  auto rowC = [&](int k) { return SC::row(tid, k); };
   // the history fields' addresses first (a wait for a descriptor read
   // would also wait for every field load issued before it)
   const int l1 = CORR ? slot : s1, l2 = CORR ? s1 : s2;
@@ -1354,10 +1353,10 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
     // every cell by one thread only: the staging's repeated rows (threads
     // past the last whole row, rows past the tile) would read a depth that
     // another wave has already clamped
-    if (tid < NP * RGP && rP + RGP * k < S::WY) {
+    if (SW::owns(tid, k)) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int e = (rP + RGP * k) * LW + cP + u;
+        const int e = rowW(k) * LW + cP + u;
         const T De = sm.db[e];
         eta[e] = sm.w[e] + dneg(De);
         sm.db[e] = dpos(De);
@@ -1962,9 +1961,10 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   // local solutions and the new surface.
   const double dt = uni(st->dt);
   constexpr int NCX = TX / MX;
-  constexpr int NPC = CP / 2, RGC = NT / NPC, KC = (S::CYN + RGC - 1) / RGC;
-  const int rC = min(tid / NPC, RGC - 1), cC = 2 * (tid - (tid / NPC) * NPC);
-  auto rowC = [&](int k) { return k < KC - 1 ? rC + RGC * k : min(rC + RGC * k, S::CYN - 1); };
+  using SC = PairStaging<CP / 2, S::CYN>;           // corner rows
+  constexpr int KC = SC::K;
+  const int cC = SC::col(tid);
+  auto rowC = [&](int k) { return SC::row(tid, k); };
   V2 rc[KC];
   __builtin_amdgcn_sched_barrier(0);
   {

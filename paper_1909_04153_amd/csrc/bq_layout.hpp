@@ -65,4 +65,23 @@ constexpr int ycol_of(int g) {
   return g;
 }
 
+// Staging of an LDS tile of NR rows by 2 NPR columns in pairs of cells by
+// the NT threads of a block: thread t loads the pair of columns col(t) =
+// 2 (t mod NPR) of rows row(t, k) = r0(t) + RG k, k = 0 .. K - 1, with RG =
+// NT / NPR whole rows per round.  Threads past the last whole row repeat
+// row RG - 1, and rows past the tile repeat its last row, so every round is
+// branch-free (the repeats store the same values again); owns(t, k) marks
+// the one thread of each cell, for the passes that update a cell in place.
+template <int NPR, int NR>
+struct PairStaging {
+  static constexpr int RG = NT / NPR, K = (NR + RG - 1) / RG;
+  static_assert(RG >= 1, "a row of pairs must fit the block");
+  static constexpr int r0(int t) { return t / NPR < RG - 1 ? t / NPR : RG - 1; }
+  static constexpr int col(int t) { return 2 * (t - (t / NPR) * NPR); }
+  static constexpr int row(int t, int k) {
+    return k < K - 1 ? r0(t) + RG * k : (r0(t) + RG * k < NR - 1 ? r0(t) + RG * k : NR - 1);
+  }
+  static constexpr bool owns(int t, int k) { return t < NPR * RG && r0(t) + RG * k < NR; }
+};
+
 }  // namespace bqk

@@ -95,7 +95,45 @@ static void check_shape(const char* name, bool expect_conflict_free_solves_y) {
   std::printf("%s checked\n", name);
 }
 
+// pair staging of an NR x 2 NPR tile: every cell staged, and owned by
+// exactly one thread, whose row is its own (not a repeat)
+template <int NPR, int NR>
+static void check_staging(const char* name) {
+  using S = PairStaging<NPR, NR>;
+  std::vector<int> staged(NR * 2 * NPR, 0), owned(NR * 2 * NPR, 0);
+  for (int t = 0; t < NT; ++t)
+    for (int k = 0; k < S::K; ++k) {
+      const int r = S::row(t, k), c = S::col(t);
+      CHECK(r >= 0 && r < NR && c >= 0 && c + 1 < 2 * NPR, "%s: thread %d round %d at (%d, %d)", name, t, k, r, c);
+      if (!(r >= 0 && r < NR && c >= 0 && c + 1 < 2 * NPR)) continue;
+      for (int u = 0; u < 2; ++u) {
+        ++staged[r * 2 * NPR + c + u];
+        if (S::owns(t, k)) ++owned[r * 2 * NPR + c + u];
+      }
+      if (S::owns(t, k)) CHECK(r == S::r0(t) + S::RG * k, "%s: thread %d owns a repeated row", name, t);
+    }
+  for (int e = 0; e < NR * 2 * NPR; ++e) {
+    CHECK(staged[e] >= 1, "%s: cell %d never staged", name, e);
+    CHECK(owned[e] == 1, "%s: cell %d owned by %d threads", name, e, owned[e]);
+  }
+  std::printf("%s staging checked\n", name);
+}
+
 int main() {
+  // the stencil kernel's radius-2 rows, radius-1 rows and corner rows, the
+  // finalize kernel's corner rows, for tile heights 16, 8 and 4
+  check_staging<(TX + 4) / 2, 16 + 4>("radius-2 rows, TY 16");
+  check_staging<(TX + 4) / 2, 8 + 4>("radius-2 rows, TY 8");
+  check_staging<(TX + 4) / 2, 4 + 4>("radius-2 rows, TY 4");
+  check_staging<(TX + 4) / 2, 16 + 2>("radius-1 rows, TY 16");
+  check_staging<(TX + 4) / 2, 8 + 2>("radius-1 rows, TY 8");
+  check_staging<(TX + 4) / 2, 4 + 2>("radius-1 rows, TY 4");
+  check_staging<(TX + 6) / 2, 16 + 5>("corner rows, TY 16");
+  check_staging<(TX + 6) / 2, 8 + 5>("corner rows, TY 8");
+  check_staging<(TX + 6) / 2, 4 + 5>("corner rows, TY 4");
+  check_staging<(TX + 4) / 2, 16 + 3>("finalize corner rows, TY 16");
+  check_staging<(TX + 4) / 2, 8 + 3>("finalize corner rows, TY 8");
+  check_staging<(TX + 4) / 2, 4 + 3>("finalize corner rows, TY 4");
   check_shape<float, 16, 16>("fp32 16x16", true);
   check_shape<float, 16, 32>("fp32 16x32", true);
   check_shape<float, 8, 16>("fp32 8x16", false);
