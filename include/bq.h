@@ -161,7 +161,10 @@ int bq_live_handles(int32_t* counts);
  * theta 1.3, walls, fstar_order 2, FP64. */
 void bq_params_default(bq_params* p);
 
-/* Device bytes a domain with these parameters needs (pure host function). */
+/* Device bytes a domain with these parameters needs (pure host function).
+ * BQ_EINVAL for a domain of more than 2e9 cells, or one whose largest field,
+ * padded to whole tiles with its halo, reaches 2^31 elements (the kernels
+ * index fields by 32-bit offsets; this bounds very elongated domains). */
 int bq_workspace_bytes(const bq_params* p, size_t* bytes);
 
 /* Create a domain in the caller's device workspace; hip_stream is a

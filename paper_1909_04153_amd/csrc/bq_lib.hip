@@ -557,7 +557,7 @@ struct Layout {
   size_t off_w, off_P, off_Q, off_E, off_F, off_G, off_part, off_wmax;
   size_t off_Dc, off_Dbar, off_xhP, off_xhQ;
   size_t off_chx, off_chy, off_rsx, off_rsy, off_ifx, off_ify, off_wave, off_io;
-  size_t ghosted, interior, total;
+  size_t ghosted, interior, corners, total;
   // sizes for every tile shape: chunks per line (shortest chunks), tiles
   // (shortest tiles)
   int pitch, xoff, ipitch, cpitch, cx, cy, tiles_x, tiles_max;
@@ -582,6 +582,7 @@ static Layout layout_for(const bq_params* p) {
   L.cpitch = (int)rup((size_t)NX + 5, 64);
   L.ghosted = (size_t)(NY + 4) * L.pitch * sizeof(T);
   L.interior = (size_t)NY * L.ipitch * sizeof(T);
+  L.corners = (size_t)(NY + 5) * L.cpitch * sizeof(T);
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
@@ -600,7 +601,7 @@ static Layout layout_for(const bq_params* p) {
   // part of the checkpoint)
   L.off_part = take(sizeof(double) * ((size_t)L.tiles_max + 2 * NDIAG));
   L.off_wmax = take(p->runup_delta > 0.0 ? L.interior : 0);   // run-up record (checkpointed)
-  L.off_Dc = take((size_t)(NY + 5) * L.cpitch * sizeof(T));
+  L.off_Dc = take(L.corners);
   L.off_Dbar = take(L.interior);
   L.off_xhP = take(L.interior);
   L.off_xhQ = take(L.interior);
@@ -616,6 +617,14 @@ static Layout layout_for(const bq_params* p) {
   L.off_io = take((size_t)(nx + 1) * (ny + 1) * sizeof(double));
   L.total = o;
   return L;
+}
+
+// elements of the largest padded field of a domain
+template <typename T>
+static size_t max_field_elements(const bq_params* p) {
+  const Layout L = layout_for<T>(p);
+  const size_t b = std::max(L.ghosted, std::max(L.interior, L.corners));
+  return b / sizeof(T);
 }
 
 static int check_params(const bq_params* p) {
@@ -645,6 +654,14 @@ static int check_params(const bq_params* p) {
     return fail(BQ_EINVAL, "a wavemaker needs n_waves >= 1 with amplitudes and frequencies");
   if (p->fstar_order < 0 || p->fstar_order > 2) return fail(BQ_EINVAL, "fstar_order must be 0, 1 or 2");
   if (p->precision != BQ_FP64 && p->precision != BQ_FP32) return fail(BQ_EINVAL, "bad precision");
+  {
+    // the kernels index a field by 32-bit element offsets (row times pitch
+    // plus column, in int arithmetic): every padded field, with its halo
+    // and its padding to whole tiles, must stay below 2^31 elements
+    const size_t el = p->precision == BQ_FP32 ? max_field_elements<float>(p) : max_field_elements<double>(p);
+    if (el >= ((size_t)1 << 31))
+      return fail(BQ_EINVAL, "domain too large: a padded field of %zu elements exceeds 32-bit offsets", el);
+  }
   // the forcing must be finite (the kernels take it as given)
   if (p->bc[0] == BQ_TIMESERIES)
     for (int k = 0; k < p->ts_n; ++k)

@@ -46,6 +46,20 @@ def test_workspace_size_and_parameter_checks_on_host():
         bq.workspace_bytes(dict(spec["params"], nx=3))
 
 
+def test_domain_size_limits_on_host():
+    # a square domain at the 2e9-cell limit fits the 32-bit element offsets
+    # of the kernels in both precisions; an elongated one of fewer cells, whose
+    # padded fields reach 2^31 elements, and one past the cell limit do not
+    base = dict(nx=44721, ny=44721, dx=1.0, dy=1.0)
+    for prec in (bq.FP32, bq.FP64):
+        n = bq.workspace_bytes(base, prec)
+        assert n > 44721 * 44721 * 4 * 15
+        with pytest.raises(bq.BqError, match="32-bit offsets"):
+            bq.workspace_bytes(dict(base, nx=64, ny=31_000_000), prec)
+        with pytest.raises(bq.BqError, match="too large"):
+            bq.workspace_bytes(dict(base, nx=44800, ny=44800), prec)
+
+
 def test_binding_struct_layout_matches_the_header(tmp_path):
     """offsets and sizes of bq_params / bq_info as the C compiler lays them out"""
     fields = [f for f, _ in bq.Params._fields_]
