@@ -40,3 +40,23 @@ def test_adaptive_trace_and_fixed_step_bisection(rb):
     radii = ad["runup_over_shoreline_radius"]
     west = radii[len(radii) // 2 - 1: len(radii) // 2 + 1]
     assert min(west) < 1.0
+
+
+def test_rip_beach_study_runs_without_an_island(rb):
+    # the study driver on the rip beach under irregular waves (Sec. 5.4,
+    # Fig. 5.18) at 128 x 128 cells of 8 m over 60 s: the adaptive run holds
+    # the CFL target, the bisection brackets the largest stable fixed step,
+    # and no run-up radii are reported (the beach has no island)
+    from paper_1909_04153_amd import bq
+
+    res = rb.study(nx=128, t_end=60.0, precision=bq.FP32, snapshots=(20.0, 40.0), scenario="rip")
+    ad, fx = res["adaptive"], res["fixed"]
+    print({k: v for k, v in ad.items() if k != "trace"})
+    print(fx)
+    assert ad["stable"], ad["reason"]
+    assert ad["cfl_max"] <= 0.125 * 1.1
+    best = fx["largest_stable_dt"]
+    assert best is not None
+    unstable = [r["dt"] for r in fx["runs"] if not r["stable"]]
+    assert unstable and min(unstable) <= best * 1.03 * (1 + 1e-12)
+    assert ad["runup_over_shoreline_radius"] is None
