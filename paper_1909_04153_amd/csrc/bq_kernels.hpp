@@ -670,6 +670,158 @@ __device__ __forceinline__ void group_solve(const T* Dl, int ds, int m, const T*
   else group_solve_<T, H, P, false, POS>(Dl, ds, m, tc, fold_lo, fold_hi, part, rhs, x, k0, mh, xlast);
 }
 
+// The chunk system's response to its two neighbour-chunk values alone: the
+// right-hand side is r0 in the chunk's first row and r1 in its last, zero
+// elsewhere, solved by the same lane groups and parts as group_solve.  Every
+// vector a part needs is then a combination of two: f and g, the part's
+// responses to a unit value in its first and in its last row.  The part's
+// own right-hand side is rf e_first + rl e_last (rf = r0 in the first part,
+// rl = r1 in the last), its coupling columns are a e_first and c e_last, so
+// x-hat = rf f + rl g, w = a f, v = c g, and the corrected solution is
+// (rf - a L_{part-1}) f + (rl - c R_part) g: one forward and two backward
+// sweeps per row instead of three of each.
+template <typename T, int H, int P, bool FULL>
+__device__ __forceinline__ void group_response_(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                                int part, T r0, T r1, T (&x)[H], int& k0, int& mh) {
+  static_assert(P == 2 || P == 4, "groups of two or four lanes");
+  constexpr int N = 2 * (P - 1);
+  auto size = [&](int q) { return FULL ? H : (m + P - 1 - q) / P; };
+  k0 = 0;
+#pragma unroll
+  for (int q = 0; q < P - 1; ++q)
+    if (q < part) k0 += size(q);
+  mh = size(part);
+  const int np = min(P, m);
+  const bool lo = fold_lo && part == 0, hi = fold_hi && part == np - 1;
+  // forward: LU of the part and the forward sweep of e_first (y_j / u_j in f)
+  T cu[H], f[H], g[H];
+  T iu_prev = T(1), c_prev = T(0), y_prev = T(1);
+  T aF = T(0), cL = T(0), iuL = T(0);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    if (FULL || j < mh) {
+      const int k = k0 + j;
+      T a, b, c;
+      tri_coef(dpos(Dl[k * ds]), dpos(Dl[(k + 1) * ds]), dpos(Dl[(k + 2) * ds]), tc, a, b, c);
+      if (j == 0 && lo) b -= a;
+      if (j == mh - 1 && hi) b -= c;
+      T u, y;
+      if (j == 0) {
+        u = b;
+        y = T(1);
+        aF = part > 0 ? a : T(0);
+      } else {
+        const T l = a * iu_prev;
+        u = b - l * c_prev;
+        y = -l * y_prev;
+      }
+      const T iu = frcp(u);
+      cu[j] = c * iu;
+      f[j] = y * iu;
+      if (j == mh - 1) {
+        cL = part < np - 1 ? c : T(0);
+        iuL = iu;
+      }
+      y_prev = y;
+      iu_prev = iu;
+      c_prev = c;
+    }
+  }
+  // backward sweeps of f and of g (g is iu at the last row, zero before it
+  // in the forward sweep)
+  T fn = T(0), gn = T(0);
+#pragma unroll
+  for (int j = H - 1; j >= 0; --j) {
+    if (FULL || j < mh) {
+      const bool last = j == mh - 1;
+      const T fv = last ? f[j] : f[j] - cu[j] * fn;
+      const T gv = last ? iuL : -cu[j] * gn;
+      f[j] = fv;
+      g[j] = gv;
+      fn = fv;
+      gn = gv;
+    }
+  }
+  const bool any = FULL || mh > 0;
+  const T fF = any ? f[0] : T(0), gF = any ? g[0] : T(0);
+  T fL = T(0), gL = T(0);
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+    if ((FULL || j < mh) && j == mh - 1) {
+      fL = f[j];
+      gL = g[j];
+    }
+  const T rf = part == 0 ? r0 : T(0), rl = part == np - 1 ? r1 : T(0);
+  // the end values group_solve gathers: x-hat, w, v at the first and last row
+  const T xL = rf * fL + rl * gL, wL = aF * fL, vL = cL * gL;
+  const T xF = rf * fF + rl * gF, wF = aF * fF, vF = cL * gF;
+  const int base = (int)(threadIdx.x & 63) & ~(P - 1);
+  T gxL[P], gwL[P], gvL[P], gxF[P], gwF[P], gvF[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    gxL[q] = __shfl(xL, base + q, 64);
+    gwL[q] = __shfl(wL, base + q, 64);
+    gvL[q] = __shfl(vL, base + q, 64);
+    gxF[q] = __shfl(xF, base + q, 64);
+    gwF[q] = __shfl(wF, base + q, 64);
+    gvF[q] = __shfl(vF, base + q, 64);
+  }
+  T M[N][N], rv[N];
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    rv[e] = T(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) M[e][q] = e == q ? T(1) : T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < P - 1; ++i) {
+    if (i < np - 1) {
+      M[2 * i][2 * i + 1] = gvL[i];
+      if (i > 0) M[2 * i][2 * i - 2] = gwL[i];
+      rv[2 * i] = gxL[i];
+      M[2 * i + 1][2 * i] = gwF[i + 1];
+      if (i + 1 < P - 1) M[2 * i + 1][2 * i + 3] = gvF[i + 1];
+      rv[2 * i + 1] = gxF[i + 1];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < N; ++e) {
+    const T id = fdiv(T(1), M[e][e]);
+#pragma unroll
+    for (int q = e + 1; q < N; ++q) {
+      const T l = M[q][e] * id;
+#pragma unroll
+      for (int h = e; h < N; ++h) M[q][h] -= l * M[e][h];
+      rv[q] -= l * rv[e];
+    }
+  }
+  T z[N];
+#pragma unroll
+  for (int e = N - 1; e >= 0; --e) {
+    T t = rv[e];
+#pragma unroll
+    for (int q = e + 1; q < N; ++q) t -= M[e][q] * z[q];
+    z[e] = fdiv(t, M[e][e]);
+  }
+  T Rp = T(0), Lm = T(0);
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+    if (q == part) {
+      if (q < P - 1) Rp = z[2 * q + 1];
+      if (q > 0) Lm = z[2 * q - 2];
+    }
+  const T cf = rf - aF * Lm, cg = rl - cL * Rp;
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+    if (FULL || j < mh) x[j] = cf * f[j] + cg * g[j];
+}
+template <typename T, int H, int P>
+__device__ __forceinline__ void group_response(const T* Dl, int ds, int m, const T* tc, bool fold_lo, bool fold_hi,
+                                               int part, T r0, T r1, T (&x)[H], int& k0, int& mh) {
+  if (m == P * H) group_response_<T, H, P, true>(Dl, ds, m, tc, fold_lo, fold_hi, part, r0, r1, x, k0, mh);
+  else group_response_<T, H, P, false>(Dl, ds, m, tc, fold_lo, fold_hi, part, r0, r1, x, k0, mh);
+}
+
 // Work-groups of a launch are dealt round-robin to the 8 XCDs (each with its
 // own L2): block b runs on XCD b % 8.  Renumber so that every XCD walks a
 // contiguous run of tiles; a tile's halo rows and columns are then mostly
@@ -2020,7 +2172,9 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
   // to its coupling with the neighbour chunks' end values (from the
   // line-coupling kernel): a right-hand side that is zero except -a x_left
   // in the first row and -c x_right in the last.  The response is solved
-  // here from the static matrix instead of read as stored spikes.
+  // here from the static matrix instead of read as stored spikes, by the
+  // lane groups of the chunk solves in their two-vector form
+  // (group_response).
   const bool wave_w = west_driven(D.bc[0]);
   if (tid < PX * TY * NCX) {
     const int qq = tid / PX, part = tid - qq * PX;
@@ -2035,11 +2189,9 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
       const T r0 = -a * xl;
       tri_coef(dpos(dlx[m - 1]), dpos(dlx[m]), dpos(dlx[m + 1]), D.tcx, a, b, cm);
       const T r1 = -cm * xr;
-      T xs[8], xlast;
+      T xs[8];
       int k0, mh;
-      group_solve<T, 8, PX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, part,
-                            [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
-                            xlast);
+      group_response<T, 8, PX>(dlx, 1, m, D.tcx, is == 0 && !wave_w, is + m == nx, part, r0, r1, xs, k0, mh);
       T* out = sm.u.s.cx + r * TXP + qc * MX + k0;
 #pragma unroll
       for (int u = 0; u < 8; ++u)
@@ -2057,11 +2209,9 @@ __global__ void __launch_bounds__(NT) k_final(const DomDev<T>* __restrict__ doms
       const T r0 = -a * xl;
       tri_coef(dpos(dly[(m - 1) * BXP]), dpos(dly[m * BXP]), dpos(dly[(m + 1) * BXP]), D.tcy, a, b, cm);
       const T r1 = -cm * xr;
-      T xs[TY / 2], xlast;
+      T xs[TY / 2];
       int k0, mh;
-      group_solve<T, TY / 2, 2>(dly, BXP, m, D.tcy, j0 == 0, j0 + m == ny, part,
-                            [&](int k) { return (k == 0 ? r0 : T(0)) + (k == m - 1 ? r1 : T(0)); }, xs, k0, mh,
-                            xlast);
+      group_response<T, TY / 2, 2>(dly, BXP, m, D.tcy, j0 == 0, j0 + m == ny, part, r0, r1, xs, k0, mh);
       T* out = sm.u.s.cy + k0 * TXP + c;
 #pragma unroll
       for (int u = 0; u < TY / 2; ++u)
