@@ -961,9 +961,9 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
   DevState S = load_state(st);
   const double t_end = D.t_end, cfl = D.cfl, ema = D.ema_alpha, dt_init = D.dt_init, dt_max = D.dt_max,
                dt_min = D.dt_min;
-  const int fixed_dt = D.fixed_dt, fstar_order = D.fstar_order;
+  const int fixed_dt = D.fixed_dt, fstar_order = D.fstar_order, corrector = D.corrector;
   __asm__ volatile("" ::"s"(t_end), "s"(cfl), "s"(ema), "s"(dt_init), "s"(dt_max), "s"(dt_min), "s"(fixed_dt),
-                   "s"(fstar_order));
+                   "s"(fstar_order), "s"(corrector));
   // CFL maximum of the current state: the finalize kernel's per-tile maxima
   // (a NaN there is already +inf) and the initial state's value
   double tmax = 0.0;
@@ -1023,40 +1023,44 @@ __global__ void __launch_bounds__(DT_THREADS) k_dt(const DomDev<T>* __restrict__
             }
           }
           if (ok) {
+            // one thread, FP64: the weights are formed from three
+            // reciprocals (a division is a long dependent chain here)
             const double h0 = dt, h1 = S.dt1, h2 = S.dt2;
+            const double i1 = 1.0 / h1, i2 = n >= 2 ? 1.0 / h2 : 0.0, h6 = h0 * (1.0 / 6.0);
             double a0 = h0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
             if (n == 1) {
-              b0 = h0 / h1;
+              b0 = h0 * i1;
               b1 = -b0;
             } else if (n >= 2) {
               // Eq. (42): integral over [t_n, t_n + h0] of the quadratic
               // through the three last nodes
-              const double r1 = h0 / h1, s12 = h1 + h2;
-              a0 = h0 / 6.0 * (r1 * (2.0 * h0 + 6.0 * h1 + 3.0 * h2) / s12 + 6.0);
-              a1 = -h0 / 6.0 * (r1 * (2.0 * h0 + 3.0 * h1 + 3.0 * h2) / h2);
-              a2 = h0 / 6.0 * ((h0 / h2) * (2.0 * h0 + 3.0 * h1) / s12);
+              const double r1 = h0 * i1, s12 = h1 + h2, is = 1.0 / s12;
+              a0 = h6 * (r1 * (2.0 * h0 + 6.0 * h1 + 3.0 * h2) * is + 6.0);
+              a1 = -h6 * (r1 * (2.0 * h0 + 3.0 * h1 + 3.0 * h2) * i2);
+              a2 = h6 * ((h0 * i2) * (2.0 * h0 + 3.0 * h1) * is);
               if (fstar_order == 1) {
                 b0 = r1;
                 b1 = -r1;
               } else {
                 // Eq. (43) with (44)-(46) sum to the increment of the quadratic
                 // through (t_{n-k}, F*^{n-k}) from t_n to t_n + h0
-                b0 = (h0 + h1) * (h0 + s12) / (h1 * s12) - 1.0;
-                b1 = -h0 * (h0 + s12) / (h1 * h2);
-                b2 = h0 * (h0 + h1) / (h2 * s12);
+                b0 = (h0 + h1) * (h0 + s12) * (i1 * is) - 1.0;
+                b1 = -h0 * (h0 + s12) * (i1 * i2);
+                b2 = h0 * (h0 + h1) * (i2 * is);
               }
             }
-            // Adams-Moulton corrector: integral over [t_n, t_n + h0] of the
-            // Lagrange basis through t_{n+1}, t_n, t_{n-1}, t_{n-2} (closed
-            // forms with a = h1, b = h1 + h2), the cubic from n = 2 on, the
-            // quadratic at n = 1, the trapezoidal rule at n = 0
+            // Adams-Moulton corrector (domains that run it): integral over
+            // [t_n, t_n + h0] of the Lagrange basis through t_{n+1}, t_n,
+            // t_{n-1}, t_{n-2} (closed forms with a = h1, b = h1 + h2), the
+            // cubic from n = 2 on, the quadratic at n = 1, the trapezoidal
+            // rule at n = 0
             double g0 = 0.5 * h0, g1 = 0.5 * h0, g2 = 0.0, g3 = 0.0;
-            if (n == 1) {
+            if (corrector && n == 1) {
               const double a = h1;
               g0 = h0 * (2.0 * h0 + 3.0 * a) / (6.0 * (h0 + a));
               g1 = h0 * (h0 + 3.0 * a) / (6.0 * a);
               g2 = -h0 * h0 * h0 / (6.0 * a * (a + h0));
-            } else if (n >= 2) {
+            } else if (corrector && n >= 2) {
               const double a = h1, b = h1 + h2, hh = h0 * h0 * h0;
               g0 = h0 * (3.0 * h0 * h0 + 4.0 * (a + b) * h0 + 6.0 * a * b) / (12.0 * (h0 + a) * (h0 + b));
               g1 = h0 * (h0 * h0 + 2.0 * (a + b) * h0 + 6.0 * a * b) / (12.0 * a * b);
