@@ -1253,13 +1253,17 @@ __global__ void __launch_bounds__(NT) k_rhs(const DomDev<T>* __restrict__ doms, 
         h2p[k] = h2q[k] = V2{{T(0), T(0)}};
       }
     } else {
-      // loaded also before the history exists (the values are then not
-      // used): a branch here would make the waits before the first LDS
-      // stores cover these loads as well
-      const T* P1 = uni((const T*)D.P[s1]);
-      const T* P2 = uni((const T*)D.P[s2]);
-      const T* Q1 = uni((const T*)D.Q[s1]);
-      const T* Q2 = uni((const T*)D.Q[s2]);
+      // loaded also where a level's weight is zero (before the history
+      // exists, and level n-2 with linear F* extrapolation): a branch here
+      // would make the waits before the first LDS stores cover these loads
+      // as well.  A level that is not needed repeats the addresses of a level
+      // that is loaded anyway (n-1, else the staged level n), so its loads
+      // hit the cache instead of reaching HBM.
+      const int u1 = sb1 != 0.0 ? s1 : slot, u2 = sb2 != 0.0 ? s2 : u1;
+      const T* P1 = uni((const T*)D.P[u1]);
+      const T* P2 = uni((const T*)D.P[u2]);
+      const T* Q1 = uni((const T*)D.Q[u1]);
+      const T* Q2 = uni((const T*)D.Q[u2]);
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         const unsigned o = oB + (unsigned)(rowB(k) * pitch);
